@@ -1,0 +1,151 @@
+"""Pins of the oracle's threshold, clip iterations and peak map
+(Sec. 2.1.1-2.1.2, App. B.1, App. C)."""
+
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import ndimage
+from scipy.stats import norm
+
+from oracle.config import KERNEL_BOX, KERNEL_GAUSS
+from oracle.detect import band_peaks, local_max, sigma_clip
+from oracle.filters import centre_spread, taps_1d
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def read_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                k, i, j, v = line.split()
+                rows.append((k, int(i), int(j), float(v)))
+    return rows
+
+
+def test_golden_box_single_hot_pixel():
+    X = np.zeros((7, 7), dtype=np.float32)
+    X[3, 3] = 9.0
+    M = np.ones((7, 7), dtype=bool)
+    g = taps_1d(KERNEL_BOX, 0.0, 1)
+    C, S, _ = centre_spread(X, M, g)
+    Y2 = sigma_clip(X, M, g, 2.0, 1)[0]
+    Y3 = sigma_clip(X, M, g, 3.0, 1)[0]
+    for key, i, j, v in read_golden("box3_single_hot_pixel.txt"):
+        got = {"C": C, "S": S, "Y2": Y2, "Y3": Y3}[key][i, j]
+        assert abs(float(got) - v) < 1e-12, (key, i, j)
+    Q = local_max(X, M, 3)
+    assert Q.sum() == 1 and Q[3, 3]
+
+
+def maxfilt_brute(X, M, k):
+    H, W = X.shape
+    Q = np.zeros((H, W), dtype=bool)
+    for i in range(H):
+        for j in range(W):
+            if not M[i, j]:
+                continue
+            vals = [X[p, q] for p in range(max(0, i - k), min(H, i + k + 1))
+                    for q in range(max(0, j - k), min(W, j + k + 1)) if M[p, q]]
+            Q[i, j] = X[i, j] == max(vals)
+    return Q
+
+
+@pytest.mark.parametrize("seed,shape", [(0, (9, 9)), (1, (13, 29)), (2, (31, 17))])
+def test_local_max_vs_brute_and_scipy(seed, shape):
+    rng = np.random.default_rng(seed)
+    X = np.round(rng.standard_normal(shape), 1).astype(np.float32)  # rounding creates ties
+    M = rng.uniform(size=shape) > 0.2
+    Q = local_max(X, M, 3)
+    assert np.array_equal(Q, maxfilt_brute(X, M, 3))
+    ref = ndimage.maximum_filter(np.where(M, X.astype(np.float64), -np.inf), size=7,
+                                 mode="constant", cval=-np.inf)
+    assert np.array_equal(Q, M & (X == ref))
+
+
+def test_plateau_ties_all_peaks():
+    rng = np.random.default_rng(4)
+    X = -rng.uniform(1.0, 2.0, (15, 15)).astype(np.float32)
+    X[7, 7] = X[7, 8] = 5.0
+    Q = local_max(X, np.ones_like(X, dtype=bool), 3)
+    assert Q[7, 7] and Q[7, 8]
+    near = np.zeros_like(Q)
+    near[4:11, 4:12] = True
+    assert Q[near].sum() == 2
+
+
+def test_type1_rate_on_pure_noise():
+    """App. B.1: a threshold at kappa noise units has type-1 rate 1 - Phi(kappa).
+
+    The estimates here include the tested pixel itself, with weight
+    w = g_0^2 in C and in S.  For zero-mean unit noise that lifts the
+    effective threshold to x* = kappa / sqrt((1 - w)(1 - kappa^2 w))
+    (solve x(1-w) = kappa sqrt((1-w) + w (1-w)^2 x^2)), so the rate sits a
+    little below 1 - Phi(kappa); finite-window estimation noise adds a few
+    per cent back."""
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((1024, 1024)).astype(np.float32)
+    M = np.ones_like(X, dtype=bool)
+    g = taps_1d(KERNEL_GAUSS, 8.0, 24)
+    kappa = 3.0
+    Y = sigma_clip(X, M, g, kappa, 1)[0]
+    frac = Y.mean()
+    raw = 1.0 - norm.cdf(kappa)
+    assert 0.85 * raw < frac < 1.05 * raw
+    w = g[24] ** 2
+    xstar = kappa / math.sqrt((1 - w) * (1 - kappa * kappa * w))
+    corrected = 1.0 - norm.cdf(xstar)
+    assert 0.95 * corrected < frac < 1.08 * corrected
+
+
+def test_monotone_in_kappa_and_zero_band():
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((96, 96)).astype(np.float32)
+    X[40, 50] += 9.0
+    M = np.ones_like(X, dtype=bool)
+    g = taps_1d(KERNEL_GAUSS, 3.0, 9)
+    prev = None
+    for kappa in (4.0, 3.0, 2.5, 2.0):
+        Y = sigma_clip(X, M, g, kappa, 1)[0]
+        if prev is not None:
+            assert np.all(Y >= prev)
+        prev = Y
+    recs, *_ = band_peaks(0, np.zeros_like(X), M, g, 2.0, 3, 3)
+    assert recs == []
+
+
+def test_clip_iterations_accumulate_and_stop():
+    rng = np.random.default_rng(9)
+    X = rng.standard_normal((80, 80)).astype(np.float32)
+    for (i, j) in [(20, 20), (22, 26), (60, 61), (40, 40)]:
+        X[i, j] += 12.0
+    M = np.ones_like(X, dtype=bool)
+    g = taps_1d(KERNEL_GAUSS, 4.0, 12)
+    Y1, *_ = sigma_clip(X, M, g, 3.0, 1)
+    Y3, C3, S3, den3, it = sigma_clip(X, M, g, 3.0, 10)
+    assert np.all(Y3 >= Y1)
+    assert it < 10   # converges before the cap
+    # at convergence another iteration reproduces the same mask
+    W = M & ~Y3
+    C, S, den = centre_spread(X, W, g)
+    Ynext = Y3 | (M & (den > 0) & (X > C + 3.0 * np.sqrt(S)))
+    assert np.array_equal(Ynext, Y3)
+
+
+def test_peak_records_sig():
+    X = np.zeros((40, 40), dtype=np.float32)
+    rng = np.random.default_rng(1)
+    X += rng.standard_normal(X.shape).astype(np.float32)
+    X[20, 21] = 15.0
+    M = np.ones_like(X, dtype=bool)
+    g = taps_1d(KERNEL_GAUSS, 3.0, 9)
+    recs, Y, C, S = band_peaks(2, X, M, g, 4.0, 1, 3)
+    hit = [r for r in recs if r[1:3] == (20, 21)]
+    assert len(hit) == 1
+    b, i, j, x, c, s, sig = hit[0]
+    assert b == 2 and x == 15.0
+    assert abs(sig - (x - c) / math.sqrt(s)) < 1e-12 and sig > 4.0
