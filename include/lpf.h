@@ -1,0 +1,248 @@
+/*
+ * lpf.h -- C ABI of the MI355X (gfx950) hot path for real-time detection of
+ * dispersed radio transients in image cubes (Ruhe et al., "Detecting
+ * Dispersed Radio Transients in Real Time Using Convolutional Neural
+ * Networks", arXiv:2103.15418).
+ *
+ * Per 1 s time step a stream delivers one image cube X_t of B subbands x H x W
+ * pixels (Sec. 2.1: the pipeline's input at time t is a B x D x D cube).  The
+ * library runs the paper's per-step stages on the GPU:
+ *   lpf_ingest_frame  quality control (App. A) and the image cache (Sec. 2.2)
+ *   lpf_detect        centre/spread estimates, sigma threshold, peak map
+ *                     (Sec. 2.1.1-2.1.2), duplicate removal, association and
+ *                     monitoring (Sec. 2.2)
+ *   lpf_extract_flux  box-maximum flux per band, backward fill, dynamic
+ *                     spectra (Sec. 2.2, Fig. 3)
+ *   lpf_infer         the CNN giving mean and Cholesky factor of the physical
+ *                     parameters (Sec. 2.3.3)
+ *
+ * Conventions
+ *  - Every call returns an int status (LPF_OK = 0 or a negative LPF_E*) and
+ *    never throws; lpf_last_error() gives the context's last message.
+ *  - Memory: everything passed in stays owned by the caller.  Device memory
+ *    the library uses lives in caller-allocated workspaces (sizes from
+ *    lpf_workspace_size / lpf_model_workspace_size); the workspace must stay
+ *    allocated and untouched until the context / model is destroyed.  The
+ *    context and model structs themselves are library-owned host memory.
+ *  - Streams: each context is bound to one hipStream_t at creation; all its
+ *    device work is ordered on that stream.  Only calls that return host data
+ *    synchronise with it (noted per call).
+ *  - Pixel layout: float32, band-major, row-major: cube[(b*H + i)*W + j].
+ *  - Time steps t must strictly increase; a gap marks the skipped steps
+ *    missing in the dynamic spectra.
+ *  - Non-finite input is not an error: quality control discards the band.
+ *  - Call order per step: ingest -> detect -> extract_flux; infer after
+ *    extract_flux.  Violations return LPF_ESTATE.
+ *  - A context is not thread-safe; distinct contexts may be used from
+ *    distinct threads.
+ *  - After a HIP error a context is poisoned: every later call returns
+ *    LPF_EDEVICE.
+ */
+#ifndef LPF_H
+#define LPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lpf_ctx lpf_ctx;     /* one per image stream (opaque)        */
+typedef struct lpf_model lpf_model; /* CNN weights, shareable across ctxs  */
+
+enum {
+    LPF_OK = 0,
+    LPF_EINVAL = -1,  /* bad argument or configuration                       */
+    LPF_ENOMEM = -2,  /* workspace too small                                 */
+    LPF_EFULL = -3,   /* source or peak capacity reached; the step completed,
+                         excess dropped and counted (see lpf_status)          */
+    LPF_EORDER = -4,  /* t not increasing                                     */
+    LPF_EDEVICE = -5, /* HIP error; the context is poisoned                   */
+    LPF_ESTATE = -6   /* call order violated                                  */
+};
+enum { LPF_KERNEL_GAUSS = 0, LPF_KERNEL_BOX = 1 };
+enum { LPF_PREC_FP32 = 0, LPF_PREC_BF16 = 1, LPF_PREC_FP16 = 2 };
+
+/* Method parameters.  Names follow Sec. 2.1-2.2 and App. A. */
+typedef struct {
+    int32_t B, H, W;          /* subbands (1..16), image rows, columns (1..4096) */
+    const uint8_t* sky_mask;  /* host [H][W] 0/1, copied at create; NULL = all  */
+    const int32_t* grid_rows; /* host [B] rows of the 16-row network input that
+                                 the bands occupy; NULL = b * (16 / B)          */
+    float kappa;              /* threshold in spreads: y = x > c + kappa sqrt(s) */
+    float bg_sigma;           /* Gaussian width s, pixels                       */
+    int32_t bg_halfwidth;     /* kernel half-width k; <= 0 -> ceil(3 s); <= 40  */
+    int32_t kernel;           /* LPF_KERNEL_GAUSS or LPF_KERNEL_BOX (square)     */
+    int32_t clip_iters;       /* sigma-clip iterations, 1..16                    */
+    int32_t peak_halfwidth;   /* max-filter half-width (paper: 3), 1..8          */
+    int32_t flux_halfwidth;   /* flux box half-width, 0..8                       */
+    float dup_radius;         /* cross-band duplicate radius, pixels            */
+    float assoc_radius;       /* association radius, pixels                     */
+    int32_t monitor_steps;    /* measured while t - t_last_det <= this          */
+    int32_t backfill_steps;   /* backward fill depth (image cache holds +1)     */
+    int32_t ring_len;         /* dynamic-spectrum window; must be 64            */
+    float qc_band_z;          /* band-mean robust z threshold (App. A: 5)       */
+    float qc_rms_z;           /* band-RMS robust z threshold; <= 0 disables     */
+    float qc_rms_floor;       /* RMS scale floor as a fraction of the median    */
+    float qc_pixel_zeta;      /* per-pixel running z threshold                  */
+    int32_t qc_warmup;        /* accepted frames before the pixel test arms     */
+    int32_t max_sources;      /* source table capacity, 1..65536                */
+    int32_t peak_cap;         /* per band per step; B * peak_cap <= 8192        */
+    int32_t filter_precision; /* LPF_PREC_FP32 (others reserved)                */
+    int32_t debug_planes;     /* 1: also keep S (and the clip mask) readable    */
+} lpf_config;
+
+/* One peak of the map P = Q and Y (Sec. 2.1.2) with the local estimates. */
+typedef struct {
+    int32_t band, row, col;
+    float x;   /* pixel value                       */
+    float c;   /* centre estimate C at the pixel    */
+    float s;   /* spread estimate S at the pixel    */
+    float sig; /* (x - c) / sqrt(s); +inf if s = 0  */
+} lpf_peak;
+
+enum { LPF_EVENT_NEW = 1, LPF_EVENT_ENDED = 2 };
+/* A source-table event of this step (Sec. 2.2). */
+typedef struct {
+    int32_t id, row, col, event;
+    int64_t t_first, t_last_det, t_end; /* t_end: last measured step (ended) */
+} lpf_source;
+
+/* Per-step counters, filled by lpf_status (synchronises). */
+typedef struct {
+    int64_t t;
+    uint32_t rejected_bands;  /* QC decision of the last ingested step          */
+    uint32_t overflow_bands;  /* bands whose peak count exceeded peak_cap:
+                                 their peaks are dropped whole                 */
+    int32_t n_peaks, n_kept, n_new, n_ended, n_measured, n_dropped, n_live;
+} lpf_status_t;
+
+/* Fills cfg with the defaults: kappa 4.5, s 8, k ceil(3s), Gaussian, 1
+ * iteration, k_peak 3, k_flux 2, radii 3, monitor 31, backfill 32, ring 64,
+ * QC 5 / 5 / 0.05 / 30 / 8, max_sources 8192, peak_cap 512.  Host only. */
+int lpf_config_default(lpf_config* cfg, int32_t B, int32_t H, int32_t W);
+
+/* Bytes of device workspace a context with cfg needs.  Host only; no device
+ * call.  LPF_EINVAL for an invalid configuration. */
+int lpf_workspace_size(const lpf_config* cfg, size_t* bytes);
+
+/* Creates a context.  dev_workspace: device memory of at least
+ * lpf_workspace_size bytes, 256-byte aligned, caller-owned, outliving the
+ * context.  hip_stream: a hipStream_t (NULL = default stream).  Copies the
+ * sky mask and initialises state on the stream (asynchronously). */
+int lpf_create(const lpf_config* cfg, void* dev_workspace, size_t bytes, void* hip_stream,
+               lpf_ctx** out);
+void lpf_destroy(lpf_ctx* ctx);
+
+/* Quality control (App. A) of the cube for step t and its entry into the
+ * image cache.  cube: [B][H][W] float32, device memory if cube_on_device,
+ * else host memory (copied before return).  A device cube is only read.
+ * Per band: mean and RMS over all pixels (float64 sums), robust z of each
+ * across bands, max |zeta| of sky pixels against the running mean/std of
+ * accepted steps; a band failing any test (or holding a non-finite value)
+ * is discarded (treated as all zeros downstream) and kept out of the
+ * running statistics.  rejected_out (nullable): the band bitmask; when
+ * non-null the call synchronises.  LPF_EORDER if t does not increase. */
+int lpf_ingest_frame(lpf_ctx* ctx, int64_t t, const float* cube, int32_t cube_on_device,
+                     uint32_t* rejected_out);
+
+/* Source detection (Sec. 2.1) on the last ingested step, then duplicate
+ * removal, association and monitoring (Sec. 2.2).  Asynchronous unless an
+ * output is requested.  peaks_out (nullable, host, cap entries): all peaks
+ * of the step in (band, row, col) order, *n_peaks their total count.
+ * events_out (nullable, host, ev_cap entries): sources opened at this step
+ * (in id order) then episodes ended at this step (in id order); *n_events.
+ * Returns LPF_EFULL (after completing the step) if a band overflowed
+ * peak_cap or the source table was full. */
+int lpf_detect(lpf_ctx* ctx, lpf_peak* peaks_out, int32_t cap, int32_t* n_peaks,
+               lpf_source* events_out, int32_t ev_cap, int32_t* n_events);
+
+/* Flux (Sec. 2.2): the maximum of the quality-controlled image within the
+ * (2k+1)^2 box (clipped to the image) around each measured source, every
+ * band, into the source's dynamic-spectrum ring; new sources are also
+ * measured on the cached steps [max(t - backfill, first t), t - 1].
+ * Device-only and asynchronous. */
+int lpf_extract_flux(lpf_ctx* ctx);
+
+/* Counters of the last step; synchronises. */
+int lpf_status(lpf_ctx* ctx, lpf_status_t* out);
+
+/* Dynamic spectrum of a held source: the ring_len steps ending at its last
+ * measured step.  out: host [B][ring_len] float32 (invalid cells 0);
+ * valid: host [B][ring_len] 0/1 (nullable); t_last (nullable): that step.
+ * Synchronises.  LPF_EINVAL if the id is not held. */
+int lpf_read_spectrum(lpf_ctx* ctx, int32_t source_id, float* out, uint8_t* valid,
+                      int64_t* t_last);
+
+/* ---- parameter inference (Sec. 2.3.3) ------------------------------------ */
+
+/* Weights blob: little-endian float32 in this order (PyTorch layouts):
+ * conv1.w[32][1][3][3] conv1.b[32] conv2.w[32][32][3][3] conv2.b[32]
+ * conv3.w[64][32][3][3] conv3.b[64] conv4.w[64][64][3][3] conv4.b[64]
+ * fc1.w[128][65536] fc1.b[128] fc2.w[14][128] fc2.b[14], followed by one
+ * float: the leaky-rectifier slope alpha (0 = plain rectifier).  Flatten
+ * order before fc1 is (channel, row, column) of the 64 x 16 x 64 map. */
+size_t lpf_model_weights_bytes(void);
+
+/* Device workspace for a model of the given precision serving batches of up
+ * to max_batch windows (larger requests are processed in chunks). */
+int lpf_model_workspace_size(int32_t precision, int32_t max_batch, size_t* bytes);
+
+/* Uploads and re-lays-out the weights (host blob) into dev_workspace on
+ * hip_stream and synchronises.  precision: LPF_PREC_FP32 / BF16 / FP16 for
+ * the convolutions and dense layers (accumulation is always float32). */
+int lpf_model_create(const void* weights, size_t bytes, int32_t precision, int32_t max_batch,
+                     void* dev_workspace, size_t ws_bytes, void* hip_stream, lpf_model** out);
+void lpf_model_destroy(lpf_model* model);
+
+/* Runs the network on the dynamic spectra of sources of one or more
+ * contexts, batched together, on the first context's stream.  source_ids:
+ * NULL = every episode that ended at the context's last detect (all
+ * contexts); else n_ids ids of ctxs[0] (n_ctx must be 1).  Outputs (host):
+ * mu_out [N][4] (DM, width, amplitude, arrival), L_out [N][10] packed
+ * row-major lower triangle with softplus diagonal, src_out [N][2]
+ * (context index, source id); at most cap rows.  *n_out: rows written.
+ * Synchronises. */
+int lpf_infer(lpf_ctx* const* ctxs, int32_t n_ctx, const lpf_model* model,
+              const int32_t* source_ids, int32_t n_ids, float* mu_out, float* L_out,
+              int32_t* src_out, int32_t cap, int32_t* n_out);
+
+/* The network alone on device windows: windows [n][16][64] float32, mu_out
+ * [n][4], L_out [n][10] device float32.  Asynchronous on hip_stream. */
+int lpf_infer_windows(const lpf_model* model, const float* windows, int32_t n, float* mu_out,
+                      float* L_out, void* hip_stream);
+
+/* ---- inspection (tests, diagnostics) ------------------------------------- */
+enum {
+    LPF_DBG_BANDSTATS = 1, /* double [B][6]: mean, rms, z_mean, z_rms, zeta_max, nonfinite */
+    LPF_DBG_WELFORD_MEAN = 2, /* float [B][H][W] running mean (accepted steps)   */
+    LPF_DBG_WELFORD_M2 = 3,   /* float [B][H][W] running M2                      */
+    LPF_DBG_WELFORD_N = 4,    /* int32 [B] accepted-step counts                   */
+    LPF_DBG_CENTRE = 5,       /* float [B][H][W] C of the last iteration          */
+    LPF_DBG_SPREAD = 6,       /* float [B][H][W] S (needs debug_planes)           */
+    LPF_DBG_CLIPMASK = 7,     /* uint8 [B][H][W] Y (needs debug_planes or iters>1) */
+    LPF_DBG_CACHE = 8         /* float [B][H][W] cached cube of the last step     */
+};
+/* Copies an internal buffer to host memory (bytes must match); synchronises.
+ * Rows of rejected bands in the centre/spread planes are unspecified. */
+int lpf_debug_read(lpf_ctx* ctx, int32_t what, void* host_out, size_t bytes);
+
+/* Stage timing with HIP events recorded on the context's stream around each
+ * stage's kernels (diagnostics; adds a few microseconds per step).
+ * Stages: 0 ingest pass, 1 QC decision, 2 centre filter, 3 spread filter +
+ * threshold + peaks (and further clip iterations), 4 association,
+ * 5 flux + backfill, 6 network (recorded by lpf_infer on ctxs[0]). */
+enum { LPF_STAGE_COUNT = 7 };
+int lpf_profile_enable(lpf_ctx* ctx, int32_t on);
+/* Sums the recorded stage times (ms) and counts since the last read and
+ * clears them; synchronises.  ms / counts: host arrays of LPF_STAGE_COUNT. */
+int lpf_profile_read(lpf_ctx* ctx, double* ms, int64_t* counts);
+
+int lpf_sync(lpf_ctx* ctx);
+const char* lpf_last_error(const lpf_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LPF_H */

@@ -1,0 +1,635 @@
+// C ABI of liblpf: configuration, workspace carving, call-order checks and
+// the per-step orchestration of the device kernels.  No arithmetic of the
+// method runs here; every stage is a kernel on the context's stream.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lpf_internal.h"
+
+namespace lpf {
+hipError_t launch_windows_gather(lpf_ctx* c, int n, const int32_t* d_slots, const int64_t* d_tend,
+                                 float* d_out);
+hipError_t launch_ended_ends(lpf_ctx* c, int32_t* slots_out, int64_t* tend_out);
+hipError_t cnn_forward(const lpf_model* m, const float* windows, int n, float* mu, float* L,
+                       hipStream_t s);
+float* model_window_buffer(const lpf_model* m);
+float* model_mu_buffer(const lpf_model* m);
+float* model_L_buffer(const lpf_model* m);
+int model_max_batch(const lpf_model* m);
+size_t model_blob_bytes();
+int model_workspace_size(int precision, int maxb, size_t* bytes);
+int model_create(const void* weights, size_t bytes, int precision, int maxb, void* ws, size_t ws_bytes,
+                 hipStream_t s, lpf_model** out);
+void model_destroy(lpf_model* m);
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + kAlign - 1) & ~(kAlign - 1);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+int validate(const lpf_config* c, std::string* why) {
+    auto bad = [&](const char* m) {
+        if (why) *why = m;
+        return LPF_EINVAL;
+    };
+    if (!c) return bad("null config");
+    if (c->B < 1 || c->B > kMaxB) return bad("B must be in 1..16");
+    if (c->H < 1 || c->H > kMaxDim || c->W < 1 || c->W > kMaxDim) return bad("H, W must be in 1..4096");
+    if (!(c->kappa >= 0.0f) || !std::isfinite(c->kappa)) return bad("kappa must be finite and >= 0");
+    if (c->kernel != LPF_KERNEL_GAUSS && c->kernel != LPF_KERNEL_BOX) return bad("unknown kernel");
+    if (c->kernel == LPF_KERNEL_GAUSS && !(c->bg_sigma > 0.0f)) return bad("bg_sigma must be > 0");
+    int k = c->bg_halfwidth > 0 ? c->bg_halfwidth : (int)std::ceil(3.0 * (double)c->bg_sigma);
+    if (k < 1 || k > kMaxK) return bad("background half-width must be in 1..40");
+    if (c->clip_iters < 1 || c->clip_iters > kMaxIters) return bad("clip_iters must be in 1..16");
+    if (c->peak_halfwidth < 1 || c->peak_halfwidth > kMaxPeakK) return bad("peak_halfwidth in 1..8");
+    if (c->flux_halfwidth < 0 || c->flux_halfwidth > kMaxFluxK) return bad("flux_halfwidth in 0..8");
+    if (!(c->dup_radius >= 0.0f) || !(c->assoc_radius >= 0.0f)) return bad("radii must be >= 0");
+    if (c->monitor_steps < 0) return bad("monitor_steps must be >= 0");
+    if (c->backfill_steps < 0 || c->backfill_steps > 4096) return bad("backfill_steps in 0..4096");
+    if (c->ring_len != kRing) return bad("ring_len must be 64");
+    if (!(c->qc_band_z > 0.0f)) return bad("qc_band_z must be > 0");
+    if (!(c->qc_rms_floor >= 0.0f)) return bad("qc_rms_floor must be >= 0");
+    if (!(c->qc_pixel_zeta > 0.0f)) return bad("qc_pixel_zeta must be > 0");
+    if (c->qc_warmup < 0) return bad("qc_warmup must be >= 0");
+    if (c->max_sources < 1 || c->max_sources > kMaxSources) return bad("max_sources in 1..65536");
+    if (c->peak_cap < 1 || (int64_t)c->peak_cap * c->B > kCatMaxPeaks) return bad("B * peak_cap must be <= 8192");
+    if (c->filter_precision != LPF_PREC_FP32) return bad("filter_precision: only FP32 is available");
+    if (c->grid_rows) {
+        bool used[kGridRows] = {};
+        for (int b = 0; b < c->B; ++b) {
+            int r = c->grid_rows[b];
+            if (r < 0 || r >= kGridRows || used[r]) return bad("grid_rows must be distinct rows in 0..15");
+            used[r] = true;
+        }
+    }
+    return LPF_OK;
+}
+
+Derived derive(const lpf_config* c) {
+    Derived d{};
+    d.k = c->bg_halfwidth > 0 ? c->bg_halfwidth : (int)std::ceil(3.0 * (double)c->bg_sigma);
+    d.Tc = c->backfill_steps + 1;
+    d.HW = (size_t)c->H * c->W;
+    d.plane = (size_t)c->B * d.HW;
+    d.masked = c->sky_mask != nullptr;
+    d.dyn = c->clip_iters > 1 || c->debug_planes != 0;
+    size_t nb = (d.HW + 8191) / 8192;  // ~8K pixels per ingest block
+    if (nb < 1) nb = 1;
+    d.nblk = (int)nb;
+    return d;
+}
+
+// Carves every device buffer; with base == nullptr only sizes the total.
+size_t carve(const lpf_config* c, const Derived& d, char* base, DevBufs* b) {
+    Carver cv{base};
+    const size_t S = (size_t)c->max_sources;
+    b->cache = cv.take<float>((size_t)d.Tc * d.plane);
+    b->cache_t = cv.take<int64_t>(d.Tc);
+    b->cache_rej = cv.take<uint32_t>(d.Tc);
+    b->wf_mean = cv.take<float>(2 * d.plane);
+    b->wf_m2 = cv.take<float>(2 * d.plane);
+    b->wf_n = cv.take<int32_t>(kMaxB);
+    b->wf_cur = cv.take<int32_t>(kMaxB);
+    b->mask = cv.take<uint8_t>(d.HW);
+    b->inv_den = cv.take<float>(d.HW);
+    b->centre = cv.take<float>(d.plane);
+    b->spread = d.dyn ? cv.take<float>(d.plane) : nullptr;
+    b->clip = d.dyn ? cv.take<uint8_t>(2 * d.plane) : nullptr;
+    b->den = c->clip_iters > 1 ? cv.take<float>(d.plane) : nullptr;
+    b->partials = cv.take<BandPartial>((size_t)c->B * d.nblk);
+    b->bandstats = cv.take<double>(6 * kMaxB);
+    b->changed = cv.take<int32_t>((kMaxIters + 1) * kMaxB);
+    b->peak_cnt = cv.take<int32_t>(kMaxB);
+    b->peak_raw = cv.take<PeakRec>((size_t)c->B * c->peak_cap);
+    b->peak_sorted = cv.take<PeakRec>((size_t)c->B * c->peak_cap);
+    b->cat_keys = nullptr;
+    b->cat_order = cv.take<int32_t>(kCatMaxPeaks);
+    b->cat_kept = cv.take<int32_t>(kCatMaxPeaks);
+    b->cat_nbr = cv.take<int32_t>((size_t)kCatMaxPeaks * (kNbr + 1));
+    b->cat_cand = cv.take<int32_t>((size_t)kCatMaxPeaks * (kCand + 1));
+    b->free_list = cv.take<int32_t>(S);
+    b->src_id = cv.take<int32_t>(S);
+    b->src_row = cv.take<int32_t>(S);
+    b->src_col = cv.take<int32_t>(S);
+    b->src_state = cv.take<int32_t>(S);
+    b->src_tfirst = cv.take<int64_t>(S);
+    b->src_tlast = cv.take<int64_t>(S);
+    b->src_tend = cv.take<int64_t>(S);
+    b->src_new = cv.take<int32_t>(S);
+    b->list_measured = cv.take<int32_t>(S);
+    b->list_new = cv.take<int32_t>(S);
+    b->list_ended = cv.take<int32_t>(S);
+    b->ring = cv.take<float>(S * c->B * kRing);
+    b->ring_t = cv.take<int64_t>(S * kRing);
+    b->ring_v = cv.take<uint32_t>(S * kRing);
+    b->status = cv.take<DevStatus>(1);
+    b->events = cv.take<lpf_source>(2 * S);
+    b->windows = nullptr;
+    b->infer_slots = cv.take<int32_t>(S);
+    b->infer_tend = cv.take<int64_t>(S);
+    return (cv.off + kAlign - 1) & ~(kAlign - 1);
+}
+
+int fail(lpf_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+int dev_fail(lpf_ctx* c, hipError_t e, const char* where) {
+    if (c) {
+        c->poisoned = true;
+        c->err = std::string(where) + ": " + hipGetErrorString(e);
+    }
+    return LPF_EDEVICE;
+}
+
+#define LPF_CHECK_CTX(c)                                   \
+    do {                                                   \
+        if (!(c)) return LPF_EINVAL;                       \
+        if ((c)->poisoned) return LPF_EDEVICE;             \
+    } while (0)
+
+#define LPF_HIP(c, expr, where)                            \
+    do {                                                   \
+        hipError_t _e = (expr);                            \
+        if (_e != hipSuccess) return dev_fail((c), _e, (where)); \
+    } while (0)
+
+int pmod(int64_t a, int m) {
+    int64_t r = a % m;
+    return (int)(r < 0 ? r + m : r);
+}
+
+
+}  // namespace
+}  // namespace lpf
+
+using namespace lpf;
+
+extern "C" {
+
+int lpf_config_default(lpf_config* c, int32_t B, int32_t H, int32_t W) {
+    if (!c) return LPF_EINVAL;
+    std::memset(c, 0, sizeof(*c));
+    c->B = B;
+    c->H = H;
+    c->W = W;
+    c->sky_mask = nullptr;
+    c->grid_rows = nullptr;
+    c->kappa = 4.5f;
+    c->bg_sigma = 8.0f;
+    c->bg_halfwidth = 0;
+    c->kernel = LPF_KERNEL_GAUSS;
+    c->clip_iters = 1;
+    c->peak_halfwidth = 3;
+    c->flux_halfwidth = 2;
+    c->dup_radius = 3.0f;
+    c->assoc_radius = 3.0f;
+    c->monitor_steps = 31;
+    c->backfill_steps = 32;
+    c->ring_len = kRing;
+    c->qc_band_z = 5.0f;
+    c->qc_rms_z = 5.0f;
+    c->qc_rms_floor = 0.05f;
+    c->qc_pixel_zeta = 30.0f;
+    c->qc_warmup = 8;
+    c->max_sources = 8192;
+    c->peak_cap = 512;
+    c->filter_precision = LPF_PREC_FP32;
+    c->debug_planes = 0;
+    return LPF_OK;
+}
+
+int lpf_workspace_size(const lpf_config* cfg, size_t* bytes) {
+    if (!bytes) return LPF_EINVAL;
+    int rc = validate(cfg, nullptr);
+    if (rc != LPF_OK) return rc;
+    Derived d = derive(cfg);
+    DevBufs b{};
+    *bytes = carve(cfg, d, nullptr, &b);
+    return LPF_OK;
+}
+
+int lpf_create(const lpf_config* cfg, void* ws, size_t bytes, void* stream, lpf_ctx** out) {
+    if (!out) return LPF_EINVAL;
+    *out = nullptr;
+    std::string why;
+    int rc = validate(cfg, &why);
+    if (rc != LPF_OK) return rc;
+    if (!ws) return LPF_EINVAL;
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign) return LPF_EINVAL;
+    Derived d = derive(cfg);
+    DevBufs tmp{};
+    const size_t need = carve(cfg, d, nullptr, &tmp);
+    if (bytes < need) return LPF_ENOMEM;
+    lpf_ctx* c = new (std::nothrow) lpf_ctx();
+    if (!c) return LPF_ENOMEM;
+    c->cfg = *cfg;
+    c->cfg.sky_mask = nullptr;
+    c->cfg.grid_rows = nullptr;
+    c->d = d;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->t_last = INT64_MIN;
+    c->t_start = INT64_MIN;
+    c->n_frames = 0;
+    c->phase = 0;
+    c->poisoned = false;
+    for (int b = 0; b < cfg->B; ++b) c->grid_rows[b] = cfg->grid_rows ? cfg->grid_rows[b] : b * (kGridRows / cfg->B);
+    // taps: g_u = exp(-u^2 / 2 s^2) / sum_v exp(-v^2 / 2 s^2), or 1 / (2k+1)
+    {
+        std::memset(&c->taps, 0, sizeof(c->taps));
+        c->taps.k = d.k;
+        double sum = 0.0, e[2 * kMaxK + 1];
+        for (int u = -d.k; u <= d.k; ++u) {
+            double v = cfg->kernel == LPF_KERNEL_BOX ? 1.0
+                                                     : std::exp(-(double)u * u / (2.0 * (double)cfg->bg_sigma * cfg->bg_sigma));
+            e[u + d.k] = v;
+            sum += v;
+        }
+        for (int i = 0; i <= 2 * d.k; ++i) c->taps.g[i] = (float)(e[i] / sum);
+    }
+    carve(cfg, d, static_cast<char*>(ws), &c->buf);
+    hipStream_t s = c->stream;
+    auto zero = [&](void* p, size_t n) { return p ? hipMemsetAsync(p, 0, n, s) : hipSuccess; };
+    hipError_t e = hipSuccess;
+    if (d.masked) e = hipMemcpyAsync(c->buf.mask, cfg->sky_mask, d.HW, hipMemcpyHostToDevice, s);
+    else e = hipMemsetAsync(c->buf.mask, 1, d.HW, s);
+    if (e == hipSuccess) e = zero(c->buf.wf_mean, 2 * d.plane * sizeof(float));
+    if (e == hipSuccess) e = zero(c->buf.wf_m2, 2 * d.plane * sizeof(float));
+    if (e == hipSuccess) e = zero(c->buf.wf_n, kMaxB * sizeof(int32_t));
+    if (e == hipSuccess) e = zero(c->buf.wf_cur, kMaxB * sizeof(int32_t));
+    if (e == hipSuccess) e = zero(c->buf.centre, d.plane * sizeof(float));
+    if (e == hipSuccess && c->buf.spread) e = zero(c->buf.spread, d.plane * sizeof(float));
+    if (e == hipSuccess && c->buf.clip) e = zero(c->buf.clip, 2 * d.plane);
+    if (e == hipSuccess) e = zero(c->buf.src_id, cfg->max_sources * sizeof(int32_t));
+    if (e == hipSuccess) e = launch_table_init(c);
+    if (e == hipSuccess) e = launch_inv_den(c);
+    if (e == hipSuccess && d.masked) {
+        // mask copy is from pageable host memory: finish before returning
+        e = hipStreamSynchronize(s);
+    }
+    if (e != hipSuccess) {
+        dev_fail(c, e, "lpf_create");
+        delete c;
+        return LPF_EDEVICE;
+    }
+    *out = c;
+    return LPF_OK;
+}
+
+void lpf_destroy(lpf_ctx* c) {
+    if (!c) return;
+    if (!c->poisoned) (void)hipStreamSynchronize(c->stream);
+    for (auto& e : c->prof_pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+int lpf_ingest_frame(lpf_ctx* c, int64_t t, const float* cube, int32_t on_device, uint32_t* rej_out) {
+    LPF_CHECK_CTX(c);
+    if (!cube) return fail(c, LPF_EINVAL, "null cube");
+    if (c->phase == 1 || c->phase == 2) return fail(c, LPF_ESTATE, "ingest before detect/extract_flux finished");
+    if (c->n_frames > 0 && t <= c->t_last) return fail(c, LPF_EORDER, "t must increase");
+    const int slot = pmod(t, c->d.Tc);
+    float* dst = c->buf.cache + (size_t)slot * c->d.plane;
+    if (on_device) {
+        StageTimer tm(c, 0);
+        LPF_HIP(c, launch_ingest(c, cube, true, slot), "ingest");
+    } else {
+        LPF_HIP(c, hipMemcpyAsync(dst, cube, c->d.plane * sizeof(float), hipMemcpyHostToDevice, c->stream),
+                "ingest H2D");
+        StageTimer tm(c, 0);
+        LPF_HIP(c, launch_ingest(c, dst, false, slot), "ingest");
+    }
+    {
+        StageTimer tm(c, 1);
+        LPF_HIP(c, launch_qc_decide(c, slot, t), "qc");
+    }
+    if (!on_device) LPF_HIP(c, hipStreamSynchronize(c->stream), "ingest sync");
+    if (c->n_frames == 0) c->t_start = t;
+    c->t_last = t;
+    c->n_frames++;
+    c->phase = 1;
+    if (rej_out) {
+        uint32_t r = 0;
+        LPF_HIP(c, hipMemcpyAsync(&r, &c->buf.status->rejected, sizeof(r), hipMemcpyDeviceToHost, c->stream),
+                "ingest D2H");
+        LPF_HIP(c, hipStreamSynchronize(c->stream), "ingest sync");
+        *rej_out = r;
+    }
+    return LPF_OK;
+}
+
+int lpf_detect(lpf_ctx* c, lpf_peak* peaks, int32_t cap, int32_t* n_peaks, lpf_source* events,
+               int32_t ev_cap, int32_t* n_events) {
+    LPF_CHECK_CTX(c);
+    if (c->phase != 1) return fail(c, LPF_ESTATE, "detect needs a fresh ingest");
+    const int slot = pmod(c->t_last, c->d.Tc);
+    LPF_HIP(c, launch_detect_init(c), "detect init");
+    LPF_HIP(c, launch_filters(c, slot), "filters");
+    {
+        StageTimer tm(c, 4);
+        LPF_HIP(c, launch_catalog(c, c->t_last), "catalog");
+    }
+    c->phase = 2;
+    const bool want = peaks || n_peaks || events || n_events;
+    if (!want) return LPF_OK;
+    DevStatus st;
+    LPF_HIP(c, hipMemcpyAsync(&st, c->buf.status, sizeof(st), hipMemcpyDeviceToHost, c->stream), "detect D2H");
+    LPF_HIP(c, hipStreamSynchronize(c->stream), "detect sync");
+    if (n_peaks) *n_peaks = st.n_peaks;
+    if (peaks && cap > 0 && st.n_peaks > 0) {
+        const int n = std::min(cap, st.n_peaks);
+        LPF_HIP(c, hipMemcpy(peaks, c->buf.peak_sorted, n * sizeof(lpf_peak), hipMemcpyDeviceToHost), "peaks D2H");
+    }
+    const int nev = st.n_new + st.n_ended;
+    if (n_events) *n_events = nev;
+    if (events && ev_cap > 0 && nev > 0) {
+        std::vector<lpf_source> tmp(nev);
+        LPF_HIP(c, hipMemcpy(tmp.data(), c->buf.events, nev * sizeof(lpf_source), hipMemcpyDeviceToHost),
+                "events D2H");
+        std::sort(tmp.begin() + st.n_new, tmp.end(),
+                  [](const lpf_source& a, const lpf_source& b) { return a.id < b.id; });
+        std::memcpy(events, tmp.data(), std::min(ev_cap, nev) * sizeof(lpf_source));
+    }
+    if (st.overflow_bands || st.n_dropped) return fail(c, LPF_EFULL, "peak or source capacity reached");
+    return LPF_OK;
+}
+
+int lpf_extract_flux(lpf_ctx* c) {
+    LPF_CHECK_CTX(c);
+    if (c->phase != 2) return fail(c, LPF_ESTATE, "extract_flux needs detect first");
+    {
+        StageTimer tm(c, 5);
+        LPF_HIP(c, launch_flux(c, pmod(c->t_last, c->d.Tc), c->t_last), "flux");
+    }
+    c->phase = 3;
+    return LPF_OK;
+}
+
+int lpf_status(lpf_ctx* c, lpf_status_t* out) {
+    LPF_CHECK_CTX(c);
+    if (!out) return LPF_EINVAL;
+    DevStatus st;
+    LPF_HIP(c, hipMemcpyAsync(&st, c->buf.status, sizeof(st), hipMemcpyDeviceToHost, c->stream), "status D2H");
+    LPF_HIP(c, hipStreamSynchronize(c->stream), "status sync");
+    out->t = c->t_last;
+    out->rejected_bands = st.rejected;
+    out->overflow_bands = st.overflow_bands;
+    out->n_peaks = st.n_peaks;
+    out->n_kept = st.n_kept;
+    out->n_new = st.n_new;
+    out->n_ended = st.n_ended;
+    out->n_measured = st.n_measured;
+    out->n_dropped = st.n_dropped;
+    out->n_live = st.n_live;
+    return LPF_OK;
+}
+
+int lpf_read_spectrum(lpf_ctx* c, int32_t id, float* out, uint8_t* valid, int64_t* t_last) {
+    LPF_CHECK_CTX(c);
+    if (!out) return LPF_EINVAL;
+    const int S = c->cfg.max_sources, B = c->cfg.B;
+    std::vector<int32_t> ids(S), state(S);
+    LPF_HIP(c, hipStreamSynchronize(c->stream), "spectrum sync");
+    LPF_HIP(c, hipMemcpy(ids.data(), c->buf.src_id, S * sizeof(int32_t), hipMemcpyDeviceToHost), "ids D2H");
+    LPF_HIP(c, hipMemcpy(state.data(), c->buf.src_state, S * sizeof(int32_t), hipMemcpyDeviceToHost), "state D2H");
+    int slot = -1;
+    for (int s = 0; s < S; ++s)
+        if (state[s] != kSrcFree && ids[s] == id) {
+            slot = s;
+            break;
+        }
+    if (slot < 0) return fail(c, LPF_EINVAL, "source id not held");
+    int64_t tend = c->t_last;
+    if (state[slot] == kSrcEnded)
+        LPF_HIP(c, hipMemcpy(&tend, c->buf.src_tend + slot, sizeof(int64_t), hipMemcpyDeviceToHost), "tend D2H");
+    std::vector<float> ring((size_t)B * kRing);
+    std::vector<int64_t> rt(kRing);
+    std::vector<uint32_t> rv(kRing);
+    LPF_HIP(c, hipMemcpy(ring.data(), c->buf.ring + (size_t)slot * B * kRing, ring.size() * sizeof(float),
+                         hipMemcpyDeviceToHost), "ring D2H");
+    LPF_HIP(c, hipMemcpy(rt.data(), c->buf.ring_t + (size_t)slot * kRing, kRing * sizeof(int64_t),
+                         hipMemcpyDeviceToHost), "ring_t D2H");
+    LPF_HIP(c, hipMemcpy(rv.data(), c->buf.ring_v + (size_t)slot * kRing, kRing * sizeof(uint32_t),
+                         hipMemcpyDeviceToHost), "ring_v D2H");
+    for (int col = 0; col < kRing; ++col) {
+        const int64_t tau = tend - (kRing - 1) + col;
+        const int ri = pmod(tau, kRing);
+        for (int b = 0; b < B; ++b) {
+            const bool ok = rt[ri] == tau && ((rv[ri] >> b) & 1u);
+            out[(size_t)b * kRing + col] = ok ? ring[(size_t)b * kRing + ri] : 0.0f;
+            if (valid) valid[(size_t)b * kRing + col] = ok ? 1 : 0;
+        }
+    }
+    if (t_last) *t_last = tend;
+    return LPF_OK;
+}
+
+int lpf_debug_read(lpf_ctx* c, int32_t what, void* host, size_t bytes) {
+    LPF_CHECK_CTX(c);
+    if (!host) return LPF_EINVAL;
+    const size_t plane = c->d.plane;
+    const void* src = nullptr;
+    size_t need = 0;
+    std::vector<int32_t> cur(kMaxB);
+    LPF_HIP(c, hipStreamSynchronize(c->stream), "debug sync");
+    switch (what) {
+        case LPF_DBG_BANDSTATS: src = c->buf.bandstats; need = (size_t)c->cfg.B * 6 * sizeof(double); break;
+        case LPF_DBG_WELFORD_N: src = c->buf.wf_n; need = (size_t)c->cfg.B * sizeof(int32_t); break;
+        case LPF_DBG_CENTRE: src = c->buf.centre; need = plane * sizeof(float); break;
+        case LPF_DBG_SPREAD:
+            if (!c->buf.spread) return fail(c, LPF_EINVAL, "spread plane not kept (debug_planes = 0)");
+            src = c->buf.spread; need = plane * sizeof(float); break;
+        case LPF_DBG_CLIPMASK:
+            if (!c->buf.clip) return fail(c, LPF_EINVAL, "clip plane not kept");
+            src = c->buf.clip + (size_t)(c->cfg.clip_iters & 1) * plane; need = plane; break;
+        case LPF_DBG_CACHE:
+            src = c->buf.cache + (size_t)pmod(c->t_last, c->d.Tc) * plane; need = plane * sizeof(float); break;
+        case LPF_DBG_WELFORD_MEAN:
+        case LPF_DBG_WELFORD_M2: {
+            need = plane * sizeof(float);
+            if (bytes != need) return fail(c, LPF_EINVAL, "size mismatch");
+            LPF_HIP(c, hipMemcpy(cur.data(), c->buf.wf_cur, kMaxB * sizeof(int32_t), hipMemcpyDeviceToHost), "cur");
+            const float* base = what == LPF_DBG_WELFORD_MEAN ? c->buf.wf_mean : c->buf.wf_m2;
+            for (int b = 0; b < c->cfg.B; ++b) {
+                const float* p = base + (size_t)cur[b] * plane + (size_t)b * c->d.HW;
+                LPF_HIP(c, hipMemcpy(static_cast<char*>(host) + (size_t)b * c->d.HW * sizeof(float), p,
+                                     c->d.HW * sizeof(float), hipMemcpyDeviceToHost), "welford D2H");
+            }
+            return LPF_OK;
+        }
+        default: return fail(c, LPF_EINVAL, "unknown buffer");
+    }
+    if (bytes != need) return fail(c, LPF_EINVAL, "size mismatch");
+    LPF_HIP(c, hipMemcpy(host, src, need, hipMemcpyDeviceToHost), "debug D2H");
+    return LPF_OK;
+}
+
+int lpf_profile_enable(lpf_ctx* c, int32_t on) {
+    LPF_CHECK_CTX(c);
+    if (on && c->prof_pool.empty()) {
+        c->prof_pool.resize(1 << 14);
+        for (auto& e : c->prof_pool) LPF_HIP(c, hipEventCreate(&e), "event create");
+    }
+    c->prof_on = on != 0;
+    return LPF_OK;
+}
+
+int lpf_profile_read(lpf_ctx* c, double* ms, int64_t* counts) {
+    LPF_CHECK_CTX(c);
+    LPF_HIP(c, hipStreamSynchronize(c->stream), "profile sync");
+    for (int i = 0; i < LPF_STAGE_COUNT; ++i) {
+        if (ms) ms[i] = 0.0;
+        if (counts) counts[i] = 0;
+    }
+    for (const auto& r : c->prof_recs) {
+        float e = 0.0f;
+        LPF_HIP(c, hipEventElapsedTime(&e, r.a, r.b), "event time");
+        if (ms) ms[r.stage] += e;
+        if (counts) counts[r.stage] += 1;
+    }
+    c->prof_recs.clear();
+    c->prof_next = 0;
+    return LPF_OK;
+}
+
+int lpf_sync(lpf_ctx* c) {
+    LPF_CHECK_CTX(c);
+    LPF_HIP(c, hipStreamSynchronize(c->stream), "sync");
+    return LPF_OK;
+}
+
+const char* lpf_last_error(const lpf_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+size_t lpf_model_weights_bytes(void) { return model_blob_bytes(); }
+
+int lpf_model_workspace_size(int32_t precision, int32_t max_batch, size_t* bytes) {
+    if (!bytes) return LPF_EINVAL;
+    return model_workspace_size(precision, max_batch, bytes);
+}
+
+int lpf_model_create(const void* weights, size_t bytes, int32_t precision, int32_t max_batch, void* ws,
+                     size_t ws_bytes, void* stream, lpf_model** out) {
+    return model_create(weights, bytes, precision, max_batch, ws, ws_bytes, static_cast<hipStream_t>(stream), out);
+}
+
+void lpf_model_destroy(lpf_model* m) { model_destroy(m); }
+
+int lpf_infer_windows(const lpf_model* m, const float* windows, int32_t n, float* mu, float* L, void* stream) {
+    if (!m || (n > 0 && (!windows || !mu || !L)) || n < 0) return LPF_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int mb = model_max_batch(m);
+    for (int i = 0; i < n; i += mb) {
+        const int cnt = std::min(mb, n - i);
+        hipError_t e = cnn_forward(m, windows + (size_t)i * kGridRows * kRing, cnt, mu + (size_t)i * 4,
+                                   L + (size_t)i * 10, s);
+        if (e != hipSuccess) return LPF_EDEVICE;
+    }
+    return LPF_OK;
+}
+
+int lpf_infer(lpf_ctx* const* ctxs, int32_t n_ctx, const lpf_model* m, const int32_t* ids, int32_t n_ids,
+              float* mu_out, float* L_out, int32_t* src_out, int32_t cap, int32_t* n_out) {
+    if (!ctxs || n_ctx < 1 || !m || !n_out) return LPF_EINVAL;
+    if (ids && n_ctx != 1) return LPF_EINVAL;
+    for (int i = 0; i < n_ctx; ++i) {
+        LPF_CHECK_CTX(ctxs[i]);
+        if (ctxs[i]->phase != 3) return fail(ctxs[i], LPF_ESTATE, "infer needs extract_flux first");
+    }
+    lpf_ctx* c0 = ctxs[0];
+    hipStream_t s = c0->stream;
+    // gather (ctx, slot, t_end) entries
+    struct Ent { int ctx; int32_t slot; int64_t tend; int32_t id; };
+    std::vector<Ent> ents;
+    for (int ci = 0; ci < n_ctx; ++ci) {
+        lpf_ctx* c = ctxs[ci];
+        LPF_HIP(c, hipStreamSynchronize(c->stream), "infer sync");
+        const int S = c->cfg.max_sources;
+        if (!ids) {
+            DevStatus st;
+            LPF_HIP(c, hipMemcpy(&st, c->buf.status, sizeof(st), hipMemcpyDeviceToHost), "status");
+            if (st.n_ended == 0) continue;
+            std::vector<int32_t> slots(st.n_ended), idv(S);
+            std::vector<int64_t> tend(S);
+            LPF_HIP(c, hipMemcpy(slots.data(), c->buf.list_ended, st.n_ended * sizeof(int32_t), hipMemcpyDeviceToHost), "ended");
+            LPF_HIP(c, hipMemcpy(idv.data(), c->buf.src_id, S * sizeof(int32_t), hipMemcpyDeviceToHost), "ids");
+            LPF_HIP(c, hipMemcpy(tend.data(), c->buf.src_tend, S * sizeof(int64_t), hipMemcpyDeviceToHost), "tend");
+            for (int32_t sl : slots) ents.push_back({ci, sl, tend[sl], idv[sl]});
+        } else {
+            std::vector<int32_t> idv(S), state(S);
+            std::vector<int64_t> tend(S);
+            LPF_HIP(c, hipMemcpy(idv.data(), c->buf.src_id, S * sizeof(int32_t), hipMemcpyDeviceToHost), "ids");
+            LPF_HIP(c, hipMemcpy(state.data(), c->buf.src_state, S * sizeof(int32_t), hipMemcpyDeviceToHost), "state");
+            LPF_HIP(c, hipMemcpy(tend.data(), c->buf.src_tend, S * sizeof(int64_t), hipMemcpyDeviceToHost), "tend");
+            for (int k = 0; k < n_ids; ++k) {
+                int slot = -1;
+                for (int sl = 0; sl < S; ++sl)
+                    if (state[sl] != kSrcFree && idv[sl] == ids[k]) { slot = sl; break; }
+                if (slot < 0) return fail(c, LPF_EINVAL, "source id not held");
+                ents.push_back({ci, slot, state[slot] == kSrcEnded ? tend[slot] : c->t_last, ids[k]});
+            }
+        }
+    }
+    // ended episodes are reported in (context, id) order
+    std::stable_sort(ents.begin(), ents.end(), [&](const Ent& a, const Ent& b) {
+        return a.ctx != b.ctx ? a.ctx < b.ctx : (ids ? false : a.id < b.id);
+    });
+    const int N = (int)ents.size();
+    *n_out = std::min(N, cap);
+    if (N == 0) return LPF_OK;
+    const int mb = model_max_batch(m);
+    float* win = model_window_buffer(m);
+    float* dmu = model_mu_buffer(m);
+    float* dL = model_L_buffer(m);
+    std::vector<float> hmu((size_t)N * 4), hL((size_t)N * 10);
+    for (int i0 = 0; i0 < N; i0 += mb) {
+        const int cnt = std::min(mb, N - i0);
+        // windows per context run: upload (slot, t_end) and gather
+        int j = i0;
+        while (j < i0 + cnt) {
+            int k = j;
+            while (k < i0 + cnt && ents[k].ctx == ents[j].ctx) ++k;
+            lpf_ctx* c = ctxs[ents[j].ctx];
+            std::vector<int32_t> sl(k - j);
+            std::vector<int64_t> te(k - j);
+            for (int q = j; q < k; ++q) { sl[q - j] = ents[q].slot; te[q - j] = ents[q].tend; }
+            LPF_HIP(c, hipMemcpy(c->buf.infer_slots, sl.data(), sl.size() * sizeof(int32_t), hipMemcpyHostToDevice), "slots H2D");
+            LPF_HIP(c, hipMemcpy(c->buf.infer_tend, te.data(), te.size() * sizeof(int64_t), hipMemcpyHostToDevice), "tend H2D");
+            LPF_HIP(c, launch_windows_gather(c, k - j, c->buf.infer_slots, c->buf.infer_tend,
+                                             win + (size_t)(j - i0) * kGridRows * kRing), "windows");
+            LPF_HIP(c, hipStreamSynchronize(c->stream), "windows sync");
+            j = k;
+        }
+        {
+            StageTimer tm(c0, 6);
+            LPF_HIP(c0, cnn_forward(m, win, cnt, dmu, dL, s), "cnn");
+        }
+        LPF_HIP(c0, hipMemcpyAsync(hmu.data() + (size_t)i0 * 4, dmu, cnt * 4 * sizeof(float), hipMemcpyDeviceToHost, s), "mu D2H");
+        LPF_HIP(c0, hipMemcpyAsync(hL.data() + (size_t)i0 * 10, dL, cnt * 10 * sizeof(float), hipMemcpyDeviceToHost, s), "L D2H");
+        LPF_HIP(c0, hipStreamSynchronize(s), "infer sync");
+    }
+    const int nw = *n_out;
+    if (mu_out) std::memcpy(mu_out, hmu.data(), (size_t)nw * 4 * sizeof(float));
+    if (L_out) std::memcpy(L_out, hL.data(), (size_t)nw * 10 * sizeof(float));
+    if (src_out)
+        for (int i = 0; i < nw; ++i) { src_out[2 * i] = ents[i].ctx; src_out[2 * i + 1] = ents[i].id; }
+    return LPF_OK;
+}
+
+}  // extern "C"

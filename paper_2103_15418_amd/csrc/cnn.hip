@@ -1,0 +1,393 @@
+// Parameter-inference network (Sec. 2.3.2-2.3.3) on gfx950 matrix cores.
+//
+// g(x, W) maps a 1 x 16 x 64 dynamic spectrum to [mu ; L]: four 3x3
+// convolutions (1->32->32->64->64, zero padding 1, leaky rectifier
+// phi(h) = h >= 0 ? h : alpha h), a dense layer 65536->128 with phi and a
+// linear layer 128->14.  mu = out[0:4]; out[4:14] fill the lower-triangular
+// Cholesky factor L row by row, its diagonal through softplus so that
+// Sigma = L L^T is a valid covariance.
+//
+// Layout: activations NHWC ([n][row][col][channel]), float32.
+// conv1 (one input channel, 9 MACs per output) runs on the vector ALUs.
+// conv2..4 are implicit GEMMs (pixels x (3*3*Cin) times (3*3*Cin) x Cout)
+// on v_mfma_f32_32x32x2f32: a 256-thread workgroup owns 64 x 64 outputs
+// (one image row for Cout = 64, two rows for Cout = 32), stages the three
+// (or four) input rows channel-major in LDS and streams weights from L2.
+// fc1 is a split-K GEMM on the same instruction (K chunks of 512 staged in
+// LDS) with a fixed-order reduction; fc2 and the head run on the ALUs.
+
+#include <cmath>
+
+#include "lpf_internal.h"
+
+namespace lpf {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+struct ModelLayout {
+    // float offsets inside the weight area
+    size_t w1, b1, w2, b2, w3, b3, w4, b4, f1, fb1, f2, fb2, total;
+};
+
+struct CnnWork {
+    float* act_a;     // [maxb][16][64][64]
+    float* act_b;
+    float* part;      // [128][maxb_pad][128] fc1 split-K partials
+    float* hidden;    // [maxb][128]
+    float* windows;   // [maxb][16][64]
+    float* mu;        // [maxb][4]
+    float* L;         // [maxb][10]
+};
+
+}  // namespace lpf
+
+struct lpf_model {
+    int precision;
+    int max_batch;
+    float alpha;
+    float* wts;
+    lpf::ModelLayout lay;
+    lpf::CnnWork work;
+    hipStream_t stream;
+};
+
+namespace lpf {
+namespace {
+
+constexpr int kGH = 16, kGW = 64;
+constexpr int kFlat = 64 * kGH * kGW;  // 65536
+constexpr int kHidden = 128;
+constexpr int kOut = 14;
+constexpr int kSplitK = 512;
+constexpr int kNSplit = kFlat / kSplitK;  // 128
+
+size_t align64(size_t x) { return (x + 63) & ~size_t(63); }
+
+ModelLayout make_layout() {
+    ModelLayout L{};
+    size_t o = 0;
+    L.w1 = o; o = align64(o + 9 * 32);
+    L.b1 = o; o = align64(o + 32);
+    L.w2 = o; o = align64(o + 9 * 32 * 32);
+    L.b2 = o; o = align64(o + 32);
+    L.w3 = o; o = align64(o + 9 * 32 * 64);
+    L.b3 = o; o = align64(o + 64);
+    L.w4 = o; o = align64(o + 9 * 64 * 64);
+    L.b4 = o; o = align64(o + 64);
+    L.f1 = o; o = align64(o + (size_t)kFlat * kHidden);
+    L.fb1 = o; o = align64(o + kHidden);
+    L.f2 = o; o = align64(o + kHidden * kOut);
+    L.fb2 = o; o = align64(o + kOut);
+    L.total = o;
+    return L;
+}
+
+__device__ inline float act_fn(float v, float alpha) { return v >= 0.0f ? v : alpha * v; }
+
+// conv1: x [n][16][64] -> out [n][16][64][32]
+__global__ __launch_bounds__(256) void k_conv1(const float* __restrict__ x, const float* __restrict__ w,
+                                               const float* __restrict__ bias, float* __restrict__ out,
+                                               int n_total, float alpha) {
+    const int64_t total = (int64_t)n_total * kGH * kGW * 32;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % 32);
+        const int64_t pix = i / 32;
+        const int col = (int)(pix % kGW);
+        const int row = (int)((pix / kGW) % kGH);
+        const int64_t n = pix / (kGW * kGH);
+        const float* xi = x + n * kGH * kGW;
+        float acc = bias[c];
+        for (int kh = 0; kh < 3; ++kh) {
+            const int r = row + kh - 1;
+            if (r < 0 || r >= kGH) continue;
+            for (int kw = 0; kw < 3; ++kw) {
+                const int q = col + kw - 1;
+                if (q < 0 || q >= kGW) continue;
+                acc = fmaf(w[(kh * 3 + kw) * 32 + c], xi[r * kGW + q], acc);
+            }
+        }
+        out[i] = act_fn(acc, alpha);
+    }
+}
+
+// conv (Cin -> Cout), 3x3, pad 1, on MFMA f32 32x32x2.
+// Workgroup: sample n, rows [h0, h0 + ROWS), ROWS = 64 / COUT; 4 waves, each a
+// 32-pixel x 32-channel output block.
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ in,
+                                                   const float* __restrict__ w,  // [9*CIN][COUT]
+                                                   const float* __restrict__ bias,
+                                                   float* __restrict__ out, float alpha) {
+    constexpr int ROWS = 64 / COUT;
+    constexpr int PADW = kGW + 2;  // 66
+    __shared__ float s_in[(ROWS + 2) * CIN * PADW];
+    const int n = blockIdx.x / (kGH / ROWS);
+    const int h0 = (blockIdx.x % (kGH / ROWS)) * ROWS;
+    const float* src = in + (size_t)n * kGH * kGW * CIN;
+    // stage rows h0-1 .. h0+ROWS, channel-major with a zero column either side
+    for (int i = threadIdx.x; i < (ROWS + 2) * PADW * CIN; i += 256) {
+        const int cin = i % CIN;
+        const int col = (i / CIN) % PADW;
+        const int r = i / (CIN * PADW);
+        const int gr = h0 - 1 + r, gc = col - 1;
+        float v = 0.0f;
+        if (gr >= 0 && gr < kGH && gc >= 0 && gc < kGW) v = src[((size_t)gr * kGW + gc) * CIN + cin];
+        s_in[(r * CIN + cin) * PADW + col] = v;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // block assignment: COUT = 64 -> (pixel half, cout half); COUT = 32 -> (row, pixel half)
+    int rloc, px0, co0;
+    if (COUT == 64) {
+        rloc = 0;
+        px0 = (wave & 1) * 32;
+        co0 = (wave >> 1) * 32;
+    } else {
+        rloc = wave >> 1;
+        px0 = (wave & 1) * 32;
+        co0 = 0;
+    }
+    const int m = lane & 31, kk = lane >> 5;
+    floatx16 acc = {};
+#pragma unroll 1
+    for (int kh = 0; kh < 3; ++kh) {
+#pragma unroll 1
+        for (int kw = 0; kw < 3; ++kw) {
+            const float* arow = s_in + ((rloc + kh) * CIN) * PADW + px0 + m + kw;
+            const float* wrow = w + (size_t)((kh * 3 + kw) * CIN) * COUT + co0 + m;
+#pragma unroll 8
+            for (int c = 0; c < CIN; c += 2) {
+                const float av = arow[(c + kk) * PADW];
+                const float bv = wrow[(size_t)(c + kk) * COUT];
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+            }
+        }
+    }
+    // D[i][j]: j = lane % 32 (output channel), i = 8 (v / 4) + 4 (lane / 32) + v % 4 (pixel)
+    const int row = h0 + rloc;
+    float* dst = out + ((size_t)n * kGH + row) * kGW * COUT;
+    const float bj = bias[co0 + m];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int px = px0 + 8 * (v / 4) + 4 * kk + (v % 4);
+        dst[(size_t)px * COUT + co0 + m] = act_fn(acc[v] + bj, alpha);
+    }
+}
+
+// fc1 split-K: part[ks][row][128] = A[rows][kchunk] * W1[kchunk][128]
+// grid (kNSplit, ceil(n / 32)); A = act (NHWC flatten, k = (h*64 + w)*64 + c).
+__global__ __launch_bounds__(256) void k_fc1_mfma(const float* __restrict__ a, const float* __restrict__ w,
+                                                  float* __restrict__ part, int n_total, int ld_part) {
+    constexpr int LDA = kSplitK + 1;
+    __shared__ float s_a[32 * LDA];
+    const int ks = blockIdx.x, mb = blockIdx.y;
+    const int k0 = ks * kSplitK;
+    for (int i = threadIdx.x; i < 32 * kSplitK; i += 256) {
+        const int r = i / kSplitK, k = i % kSplitK;
+        const int n = mb * 32 + r;
+        s_a[r * LDA + k] = n < n_total ? a[(size_t)n * kFlat + k0 + k] : 0.0f;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m = lane & 31, kk = lane >> 5;
+    const int co0 = wave * 32;
+    floatx16 acc = {};
+    const float* wp = w + (size_t)k0 * kHidden + co0 + m;
+#pragma unroll 8
+    for (int k = 0; k < kSplitK; k += 2) {
+        const float av = s_a[m * LDA + k + kk];
+        const float bv = wp[(size_t)(k + kk) * kHidden];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+    }
+    float* dst = part + (size_t)ks * ld_part * kHidden;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int r = mb * 32 + 8 * (v / 4) + 4 * kk + (v % 4);
+        dst[(size_t)r * kHidden + co0 + m] = acc[v];
+    }
+}
+
+// hidden[n][j] = phi(sum_ks part[ks][n][j] + b[j]) in a fixed order.
+__global__ void k_fc1_reduce(const float* __restrict__ part, const float* __restrict__ bias,
+                             float* __restrict__ hidden, int n_total, int ld_part, float alpha) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_total * kHidden) return;
+    const int n = i / kHidden, j = i % kHidden;
+    float acc = 0.0f;
+    for (int ks = 0; ks < kNSplit; ++ks) acc += part[((size_t)ks * ld_part + n) * kHidden + j];
+    hidden[i] = act_fn(acc + bias[j], alpha);
+}
+
+__device__ inline float softplus(float z) { return fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))); }
+
+// fc2 + head: one lane per (sample, output).
+__global__ void k_fc2_head(const float* __restrict__ hidden, const float* __restrict__ w,  // [14][128]
+                           const float* __restrict__ bias, float* __restrict__ mu, float* __restrict__ L,
+                           int n_total) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_total * kOut) return;
+    const int n = i / kOut, o = i % kOut;
+    const float* h = hidden + (size_t)n * kHidden;
+    const float* wr = w + (size_t)o * kHidden;
+    float acc = bias[o];
+    for (int j = 0; j < kHidden; ++j) acc = fmaf(wr[j], h[j], acc);
+    if (o < 4) {
+        mu[n * 4 + o] = acc;
+    } else {
+        const int p = o - 4;
+        const bool diag = p == 0 || p == 2 || p == 5 || p == 9;
+        L[n * 10 + p] = diag ? softplus(acc) : acc;
+    }
+}
+
+// Re-layout of the host blob (PyTorch layouts) into the device layouts.
+__global__ void k_relayout(const float* __restrict__ blob, float* __restrict__ dst, ModelLayout lay) {
+    // blob offsets (PyTorch order)
+    const size_t o_w1 = 0, o_b1 = o_w1 + 32 * 9, o_w2 = o_b1 + 32, o_b2 = o_w2 + 32 * 32 * 9,
+                 o_w3 = o_b2 + 32, o_b3 = o_w3 + 64 * 32 * 9, o_w4 = o_b3 + 64, o_b4 = o_w4 + 64 * 64 * 9,
+                 o_f1 = o_b4 + 64, o_fb1 = o_f1 + (size_t)kHidden * kFlat, o_f2 = o_fb1 + kHidden,
+                 o_fb2 = o_f2 + kOut * kHidden;
+    const size_t nthreads = (size_t)gridDim.x * blockDim.x;
+    const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // conv1: [32][1][3][3] -> [9][32]
+    for (size_t i = tid; i < 32 * 9; i += nthreads) {
+        const int c = (int)(i / 9), k = (int)(i % 9);
+        dst[lay.w1 + k * 32 + c] = blob[o_w1 + i];
+    }
+    for (size_t i = tid; i < 32; i += nthreads) dst[lay.b1 + i] = blob[o_b1 + i];
+    // conv2..4: [Cout][Cin][3][3] -> [(kh*3+kw)*Cin + cin][Cout]
+    auto conv = [&](size_t ob, size_t od, int cin, int cout) {
+        for (size_t i = tid; i < (size_t)cout * cin * 9; i += nthreads) {
+            const int co = (int)(i / (cin * 9));
+            const int ci = (int)((i / 9) % cin);
+            const int k = (int)(i % 9);
+            dst[od + ((size_t)k * cin + ci) * cout + co] = blob[ob + i];
+        }
+    };
+    conv(o_w2, lay.w2, 32, 32);
+    conv(o_w3, lay.w3, 32, 64);
+    conv(o_w4, lay.w4, 64, 64);
+    for (size_t i = tid; i < 32; i += nthreads) dst[lay.b2 + i] = blob[o_b2 + i];
+    for (size_t i = tid; i < 64; i += nthreads) dst[lay.b3 + i] = blob[o_b3 + i];
+    for (size_t i = tid; i < 64; i += nthreads) dst[lay.b4 + i] = blob[o_b4 + i];
+    // fc1: [128][c*1024 + h*64 + w] -> [(h*64 + w)*64 + c][128]
+    for (size_t i = tid; i < (size_t)kHidden * kFlat; i += nthreads) {
+        const int j = (int)(i / kFlat);
+        const int kt = (int)(i % kFlat);
+        const int c = kt / (kGH * kGW), hw = kt % (kGH * kGW);
+        dst[lay.f1 + ((size_t)hw * 64 + c) * kHidden + j] = blob[o_f1 + i];
+    }
+    for (size_t i = tid; i < kHidden; i += nthreads) dst[lay.fb1 + i] = blob[o_fb1 + i];
+    for (size_t i = tid; i < (size_t)kOut * kHidden; i += nthreads) dst[lay.f2 + i] = blob[o_f2 + i];
+    for (size_t i = tid; i < kOut; i += nthreads) dst[lay.fb2 + i] = blob[o_fb2 + i];
+}
+
+size_t blob_floats() {
+    return 32 * 9 + 32 + 32 * 32 * 9 + 32 + 64 * 32 * 9 + 64 + 64 * 64 * 9 + 64 + (size_t)kHidden * kFlat +
+           kHidden + kOut * kHidden + kOut;
+}
+
+int pad32(int n) { return (n + 31) / 32 * 32; }
+
+size_t work_bytes(int maxb) {
+    const size_t act = (size_t)maxb * kGH * kGW * 64 * sizeof(float);
+    size_t b = 0;
+    b += 2 * align64(act);
+    b += align64((size_t)kNSplit * pad32(maxb) * kHidden * sizeof(float));
+    b += align64((size_t)maxb * kHidden * sizeof(float));
+    b += align64((size_t)maxb * kGH * kGW * sizeof(float));
+    b += align64((size_t)maxb * 4 * sizeof(float));
+    b += align64((size_t)maxb * 10 * sizeof(float));
+    return b;
+}
+
+}  // namespace
+
+// Runs the network on n device windows (n <= max_batch).
+hipError_t cnn_forward(const lpf_model* m, const float* windows, int n, float* mu, float* L,
+                       hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const ModelLayout& lay = m->lay;
+    const float* W = m->wts;
+    const CnnWork& w = m->work;
+    int blocks = (int)(((int64_t)n * kGH * kGW * 32 + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_conv1, dim3(blocks), dim3(256), 0, s, windows, W + lay.w1, W + lay.b1, w.act_a, n,
+                       m->alpha);
+    hipLaunchKernelGGL((k_conv_mfma<32, 32>), dim3(n * (kGH / 2)), dim3(256), 0, s, w.act_a, W + lay.w2,
+                       W + lay.b2, w.act_b, m->alpha);
+    hipLaunchKernelGGL((k_conv_mfma<32, 64>), dim3(n * kGH), dim3(256), 0, s, w.act_b, W + lay.w3,
+                       W + lay.b3, w.act_a, m->alpha);
+    hipLaunchKernelGGL((k_conv_mfma<64, 64>), dim3(n * kGH), dim3(256), 0, s, w.act_a, W + lay.w4,
+                       W + lay.b4, w.act_b, m->alpha);
+    const int ldp = pad32(m->max_batch);
+    hipLaunchKernelGGL(k_fc1_mfma, dim3(kNSplit, (n + 31) / 32), dim3(256), 0, s, w.act_b, W + lay.f1, w.part,
+                       n, ldp);
+    hipLaunchKernelGGL(k_fc1_reduce, dim3((n * kHidden + 255) / 256), dim3(256), 0, s, w.part, W + lay.fb1,
+                       w.hidden, n, ldp, m->alpha);
+    hipLaunchKernelGGL(k_fc2_head, dim3((n * kOut + 255) / 256), dim3(256), 0, s, w.hidden, W + lay.f2,
+                       W + lay.fb2, mu, L, n);
+    return hipGetLastError();
+}
+
+float* model_window_buffer(const lpf_model* m) { return m->work.windows; }
+float* model_mu_buffer(const lpf_model* m) { return m->work.mu; }
+float* model_L_buffer(const lpf_model* m) { return m->work.L; }
+int model_max_batch(const lpf_model* m) { return m->max_batch; }
+
+size_t model_blob_bytes() { return (blob_floats() + 1) * sizeof(float); }
+
+int model_workspace_size(int precision, int maxb, size_t* bytes) {
+    if (precision != LPF_PREC_FP32) return LPF_EINVAL;
+    if (maxb < 1 || maxb > 65536) return LPF_EINVAL;
+    *bytes = align64(make_layout().total * sizeof(float)) + work_bytes(maxb) +
+             align64(blob_floats() * sizeof(float));
+    return LPF_OK;
+}
+
+int model_create(const void* weights, size_t bytes, int precision, int maxb, void* ws, size_t ws_bytes,
+                 hipStream_t s, lpf_model** out) {
+    if (!weights || !ws || !out) return LPF_EINVAL;
+    if (bytes != model_blob_bytes()) return LPF_EINVAL;
+    size_t need;
+    int rc = model_workspace_size(precision, maxb, &need);
+    if (rc != LPF_OK) return rc;
+    if (ws_bytes < need) return LPF_ENOMEM;
+    lpf_model* m = new lpf_model();
+    m->precision = precision;
+    m->max_batch = maxb;
+    m->lay = make_layout();
+    m->stream = s;
+    const float* hb = static_cast<const float*>(weights);
+    m->alpha = hb[blob_floats()];
+    char* p = static_cast<char*>(ws);
+    m->wts = reinterpret_cast<float*>(p);
+    p += align64(m->lay.total * sizeof(float));
+    const size_t act = align64((size_t)maxb * kGH * kGW * 64 * sizeof(float));
+    m->work.act_a = reinterpret_cast<float*>(p); p += act;
+    m->work.act_b = reinterpret_cast<float*>(p); p += act;
+    m->work.part = reinterpret_cast<float*>(p);
+    p += align64((size_t)kNSplit * pad32(maxb) * kHidden * sizeof(float));
+    m->work.hidden = reinterpret_cast<float*>(p); p += align64((size_t)maxb * kHidden * sizeof(float));
+    m->work.windows = reinterpret_cast<float*>(p); p += align64((size_t)maxb * kGH * kGW * sizeof(float));
+    m->work.mu = reinterpret_cast<float*>(p); p += align64((size_t)maxb * 4 * sizeof(float));
+    m->work.L = reinterpret_cast<float*>(p); p += align64((size_t)maxb * 10 * sizeof(float));
+    float* staging = reinterpret_cast<float*>(p);
+    hipError_t e = hipMemcpyAsync(staging, weights, blob_floats() * sizeof(float), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_relayout, dim3(1024), dim3(256), 0, s, staging, m->wts, m->lay);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete m;
+        return LPF_EDEVICE;
+    }
+    *out = m;
+    return LPF_OK;
+}
+
+void model_destroy(lpf_model* m) { delete m; }
+
+}  // namespace lpf

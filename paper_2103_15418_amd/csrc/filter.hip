@@ -1,0 +1,440 @@
+// Source detection on one quality-controlled cube (Sec. 2.1.1-2.1.2).
+//
+// Centre and spread are masked, normalised correlations with the Gaussian
+// (or square box) kernel G = g (x) g:
+//   C = (G * (W.X)) / (G * W),   S = (G * (W.(X - C)^2)) / (G * W),
+// with zero extension outside the image and W = sky mask and not yet
+// clipped.  The threshold is y = W-sky and (G*W > 0) and x > c + kappa sqrt(s);
+// a peak is a pixel with y = 1 that equals the maximum of x over its
+// (2k_p+1)^2 window within the image and the sky mask.
+//
+// Kernel design (gfx950): one 256-thread workgroup per 64 x 64 output tile
+// of one band.  The (64 + 2k)^2 input halo is streamed through LDS in
+// 64-row chunks; each chunk is filtered along rows (every thread produces 16
+// consecutive outputs from a register window of 16 + 2k values, taps in
+// SGPRs), the row results are kept in LDS, and a column pass (16
+// consecutive rows per thread) produces the tile.  Inputs come straight from
+// HBM (halo re-reads hit L2: tiles are remapped so that each XCD owns a
+// contiguous run of tiles).  The epilogue fuses normalisation, threshold and
+// the peak test; with one clip iteration neither S nor Y is written to HBM.
+//
+// Passes for one step (per band not rejected by QC):
+//   iteration 1: C  <- filter(M.X) * inv_den          (inv_den static per sky mask)
+//                S  <- filter(M.(X-C)^2) * inv_den, threshold, peaks (fused)
+//   iteration i > 1 (bands whose mask changed): den <- filter(W), C <- filter(W.X)/den,
+//                S <- filter(W.(X-C)^2)/den, Y |= threshold;   then one peak pass.
+
+#include <cmath>
+
+#include "lpf_internal.h"
+
+namespace lpf {
+namespace {
+
+constexpr int R = 16;  // outputs per thread per pass
+
+enum InMode { IN_MX = 0, IN_ME = 1, IN_W = 2, IN_WX = 3, IN_WE = 4, IN_M = 5 };
+enum OutMode {
+    OUT_C_STATIC = 0,    // C = v * inv_den
+    OUT_S_PEAKS = 1,     // S = v * inv_den; threshold; peaks; optional S/Y planes
+    OUT_RAW = 2,         // plane = v (den)
+    OUT_C_DYN = 3,       // C = v / den
+    OUT_S_DYN = 4,       // S = v / den; Y |= threshold; changed flag
+    OUT_INV_DEN = 5      // inv_den = v > 0 ? 1 / v : 0
+};
+
+struct FiltArgs {
+    const float* X;      // band planes [B][H][W] (cache slot)
+    const float* C;      // [B][H][W]
+    const uint8_t* M;    // [H][W] or null (all ones)
+    const uint8_t* Y;    // [B][H][W] clip mask
+    const float* den;    // [B][H][W]
+    const float* inv_den;  // [H][W]
+    float* out;          // output plane(s)
+    float* S_out;        // optional spread plane
+    uint8_t* Y_out;      // optional clip plane
+    uint8_t* Y_out2;     // optional second clip plane (iteration 1 of several)
+    const uint32_t* rej; // rejected bands of this step
+    const int32_t* active;  // per-band active flags (null = all)
+    int32_t* changed;    // per-band changed flags (OUT_S_DYN / OUT_S_PEAKS with Y plane)
+    int32_t* peak_cnt;   // [B]
+    PeakRec* peak_raw;   // [B][cap]
+    int peak_cap;
+    int kp;              // max-filter half-width
+    float kappa;
+    int H, W, B;
+    int tiles_x, tiles_y;
+};
+
+__device__ inline int xcd_remap(int lin, int N) {
+    const int nx = 8;
+    int q = N / nx, r = N % nx;
+    int x = lin % nx, pos = lin / nx;
+    return x * q + (x < r ? x : r) + pos;
+}
+
+template <int IN>
+__device__ inline float load_in(const FiltArgs& a, size_t bo, int gy, int gx) {
+    const size_t p = (size_t)gy * a.W + gx;
+    float m = a.M ? (float)a.M[p] : 1.0f;
+    if (IN == IN_M) return m;
+    if (IN == IN_W || IN == IN_WX || IN == IN_WE) {
+        if (a.Y[bo + p]) m = 0.0f;
+    }
+    if (IN == IN_W) return m;
+    float x = a.X[bo + p];
+    if (IN == IN_MX || IN == IN_WX) return m * x;
+    float r = x - a.C[bo + p];
+    return m * r * r;
+}
+
+// Row window correlation with compile-time half-width K (K > 0) or runtime k (K == 0).
+template <int K>
+__device__ inline void corr16(const float* src, const Taps& tp, float* acc) {
+    if constexpr (K > 0) {
+        float w[R + 2 * K];
+#pragma unroll
+        for (int i = 0; i < R + 2 * K; i += 4) {
+            float4 v = *reinterpret_cast<const float4*>(src + i);
+            w[i] = v.x;
+            if (i + 1 < R + 2 * K) w[i + 1] = v.y;
+            if (i + 2 < R + 2 * K) w[i + 2] = v.z;
+            if (i + 3 < R + 2 * K) w[i + 3] = v.w;
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] = 0.0f;
+#pragma unroll
+        for (int u = 0; u <= 2 * K; ++u) {
+            const float g = tp.g[u];
+#pragma unroll
+            for (int q = 0; q < R; ++q) acc[q] = fmaf(g, w[q + u], acc[q]);
+        }
+    } else {
+        const int k = tp.k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] = 0.0f;
+        for (int u = 0; u <= 2 * k; ++u) {
+            const float g = tp.g[u];
+#pragma unroll
+            for (int q = 0; q < R; ++q) acc[q] = fmaf(g, src[q + u], acc[q]);
+        }
+    }
+}
+
+template <int K>
+__device__ inline void corr16_col(const float* src, int stride, const Taps& tp, float* acc) {
+    if constexpr (K > 0) {
+        float w[R + 2 * K];
+#pragma unroll
+        for (int i = 0; i < R + 2 * K; ++i) w[i] = src[i * stride];
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] = 0.0f;
+#pragma unroll
+        for (int u = 0; u <= 2 * K; ++u) {
+            const float g = tp.g[u];
+#pragma unroll
+            for (int q = 0; q < R; ++q) acc[q] = fmaf(g, w[q + u], acc[q]);
+        }
+    } else {
+        const int k = tp.k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] = 0.0f;
+        for (int u = 0; u <= 2 * k; ++u) {
+            const float g = tp.g[u];
+#pragma unroll
+            for (int q = 0; q < R; ++q) acc[q] = fmaf(g, src[(q + u) * stride], acc[q]);
+        }
+    }
+}
+
+__device__ inline bool is_peak(const FiltArgs& a, size_t bo, int y, int x, float xv) {
+    const int kp = a.kp;
+    for (int dy = -kp; dy <= kp; ++dy) {
+        const int yy = y + dy;
+        if (yy < 0 || yy >= a.H) continue;
+        for (int dx = -kp; dx <= kp; ++dx) {
+            const int xx = x + dx;
+            if (xx < 0 || xx >= a.W) continue;
+            const size_t p = (size_t)yy * a.W + xx;
+            if (a.M && !a.M[p]) continue;
+            if (a.X[bo + p] > xv) return false;
+        }
+    }
+    return true;
+}
+
+template <int K, int IN, int OUT>
+__global__ __launch_bounds__(kFiltThreads) void k_filter(FiltArgs a, Taps tp) {
+    extern __shared__ float lds[];
+    const int k = K > 0 ? K : tp.k;
+    const int nt = a.tiles_x * a.tiles_y;
+    const int lin = xcd_remap(blockIdx.x, gridDim.x);
+    const int b = lin / nt;
+    const int tile = lin % nt;
+    if (OUT != OUT_INV_DEN) {
+        if (a.rej && ((*a.rej >> b) & 1u)) return;
+        if (a.active && !a.active[b]) return;
+    }
+    const int ty = tile / a.tiles_x, tx = tile % a.tiles_x;
+    const int y0 = ty * kTileH, x0 = tx * kTileW;
+    const size_t bo = (size_t)b * a.H * a.W;
+
+    // LDS: stage [64][sw] then rowbuf [(kTileH + 2k)][rw]
+    const int sw = ((kTileW + 2 * k + 3) & ~3) + 4;  // float4-aligned rows, skewed
+    const int rw = kTileW + 1;
+    float* stage = lds;
+    float* rowbuf = lds + 64 * sw;
+    const int rows_in = kTileH + 2 * k;
+    const int tid = threadIdx.x;
+
+    for (int rc = 0; rc < rows_in; rc += 64) {
+        const int nr = rows_in - rc < 64 ? rows_in - rc : 64;
+        const int wide = kTileW + 2 * k;
+        for (int idx = tid; idx < nr * wide; idx += kFiltThreads) {
+            const int r = idx / wide, cc = idx - r * wide;
+            const int gy = y0 - k + rc + r, gx = x0 - k + cc;
+            float v = 0.0f;
+            if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) v = load_in<IN>(a, bo, gy, gx);
+            stage[r * sw + cc] = v;
+        }
+        __syncthreads();
+        {
+            const int r = tid >> 2, cb = (tid & 3) * R;
+            if (r < nr) {
+                float acc[R];
+                corr16<K>(stage + r * sw + cb, tp, acc);
+                float* dst = rowbuf + (rc + r) * rw + cb;
+#pragma unroll
+                for (int q = 0; q < R; ++q) dst[q] = acc[q];
+            }
+        }
+        __syncthreads();
+    }
+
+    // Column pass: thread -> column c, rows rb*16 .. rb*16+15.
+    const int c = tid & 63, rb = tid >> 6;
+    float acc[R];
+    corr16_col<K>(rowbuf + (rb * R) * rw + c, rw, tp, acc);
+    const int gx = x0 + c;
+    if (gx >= a.W) return;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int gy = y0 + rb * R + q;
+        if (gy >= a.H) break;
+        const size_t p = (size_t)gy * a.W + gx;
+        const float v = acc[q];
+        if (OUT == OUT_INV_DEN) {
+            a.out[p] = v > 0.0f ? 1.0f / v : 0.0f;
+        } else if (OUT == OUT_RAW) {
+            a.out[bo + p] = v;
+        } else if (OUT == OUT_C_STATIC) {
+            a.out[bo + p] = v * a.inv_den[p];
+        } else if (OUT == OUT_C_DYN) {
+            const float dn = a.den[bo + p];
+            a.out[bo + p] = dn > 0.0f ? v / dn : 0.0f;
+        } else {
+            float s, dpos;
+            if (OUT == OUT_S_PEAKS) {
+                const float id = a.inv_den[p];
+                s = v * id;
+                dpos = id;
+            } else {
+                const float dn = a.den[bo + p];
+                s = dn > 0.0f ? v / dn : 0.0f;
+                dpos = dn;
+            }
+            const float cv = a.C[bo + p];
+            const float xv = a.X[bo + p];
+            const bool m = a.M ? a.M[p] != 0 : true;
+            const bool y = m && dpos > 0.0f && xv > cv + a.kappa * sqrtf(s);
+            if (a.S_out) a.S_out[bo + p] = s;
+            if (OUT == OUT_S_PEAKS) {
+                if (a.Y_out) a.Y_out[bo + p] = y ? 1 : 0;
+                if (a.Y_out2) a.Y_out2[bo + p] = y ? 1 : 0;
+                if (y && is_peak(a, bo, gy, gx, xv)) {
+                    const int idx = atomicAdd(&a.peak_cnt[b], 1);
+                    if (idx < a.peak_cap) {
+                        PeakRec rec;
+                        rec.band = b;
+                        rec.row = gy;
+                        rec.col = gx;
+                        rec.x = xv;
+                        rec.c = cv;
+                        rec.s = s;
+                        rec.sig = (xv - cv) / sqrtf(s);
+                        a.peak_raw[(size_t)b * a.peak_cap + idx] = rec;
+                    }
+                }
+                if (y && a.changed) a.changed[b] = 1;
+            } else {  // OUT_S_DYN: Y_i = Y_{i-1} or y, into the other plane
+                const uint8_t old = a.Y[bo + p];
+                a.Y_out[bo + p] = (y || old) ? 1 : 0;
+                if (y && !old) a.changed[b] = 1;
+            }
+        }
+    }
+}
+
+// Peaks after several clip iterations: P = Q and Y from the planes.
+__global__ __launch_bounds__(256) void k_peaks_planes(FiltArgs a) {
+    const int b = blockIdx.y;
+    if (a.rej && ((*a.rej >> b) & 1u)) return;
+    const size_t HW = (size_t)a.H * a.W;
+    const size_t bo = (size_t)b * HW;
+    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < HW;
+         p += (size_t)gridDim.x * blockDim.x) {
+        if (!a.Y[bo + p]) continue;
+        const int gy = (int)(p / a.W), gx = (int)(p % a.W);
+        const float xv = a.X[bo + p];
+        if (!is_peak(a, bo, gy, gx, xv)) continue;
+        const float cv = a.C[bo + p], s = a.den[bo + p];  // den slot carries S here
+        const int idx = atomicAdd(&a.peak_cnt[b], 1);
+        if (idx < a.peak_cap) {
+            PeakRec rec;
+            rec.band = b;
+            rec.row = gy;
+            rec.col = gx;
+            rec.x = xv;
+            rec.c = cv;
+            rec.s = s;
+            rec.sig = (xv - cv) / sqrtf(s);
+            a.peak_raw[(size_t)b * a.peak_cap + idx] = rec;
+        }
+    }
+}
+
+__global__ void k_detect_init(int32_t* peak_cnt, int32_t* changed, int n_changed, int B) {
+    const int i = threadIdx.x + blockIdx.x * blockDim.x;
+    if (i < B) peak_cnt[i] = 0;
+    if (i < n_changed) changed[i] = 0;
+}
+
+// Marks bands active for the next iteration: active = not rejected and changed.
+template <int K, int IN, int OUT>
+hipError_t run_filter(lpf_ctx* c, const FiltArgs& a, int nbands) {
+    const int k = c->d.k;
+    const int sw = ((kTileW + 2 * k + 3) & ~3) + 4;
+    const size_t lds = sizeof(float) * (64 * sw + (kTileH + 2 * k) * (kTileW + 1));
+    const int nblocks = a.tiles_x * a.tiles_y * nbands;
+    auto kern = k_filter<K, IN, OUT>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kFiltThreads), lds, c->stream, a, c->taps);
+    return hipGetLastError();
+}
+
+template <int IN, int OUT>
+hipError_t dispatch_k(lpf_ctx* c, const FiltArgs& a, int nbands) {
+    switch (c->d.k) {
+        case 15: return run_filter<15, IN, OUT>(c, a, nbands);
+        case 24: return run_filter<24, IN, OUT>(c, a, nbands);
+        case 36: return run_filter<36, IN, OUT>(c, a, nbands);
+        default: return run_filter<0, IN, OUT>(c, a, nbands);
+    }
+}
+
+FiltArgs base_args(lpf_ctx* c, int slot) {
+    FiltArgs a{};
+    a.X = c->buf.cache + (size_t)slot * c->d.plane;
+    a.C = c->buf.centre;
+    a.M = c->d.masked ? c->buf.mask : nullptr;
+    a.Y = c->buf.clip;
+    a.den = c->buf.den;
+    a.inv_den = c->buf.inv_den;
+    a.rej = c->buf.cache_rej + slot;
+    a.peak_cnt = c->buf.peak_cnt;
+    a.peak_raw = c->buf.peak_raw;
+    a.peak_cap = c->cfg.peak_cap;
+    a.kp = c->cfg.peak_halfwidth;
+    a.kappa = c->cfg.kappa;
+    a.H = c->cfg.H;
+    a.W = c->cfg.W;
+    a.B = c->cfg.B;
+    a.tiles_x = (a.W + kTileW - 1) / kTileW;
+    a.tiles_y = (a.H + kTileH - 1) / kTileH;
+    return a;
+}
+
+}  // namespace
+
+hipError_t launch_inv_den(lpf_ctx* c) {
+    FiltArgs a = base_args(c, 0);
+    a.M = c->d.masked ? c->buf.mask : nullptr;
+    a.out = c->buf.inv_den;
+    a.rej = nullptr;
+    return dispatch_k<IN_M, OUT_INV_DEN>(c, a, 1);
+}
+
+hipError_t launch_detect_init(lpf_ctx* c) {
+    const int nch = (kMaxIters + 1) * c->cfg.B;
+    hipLaunchKernelGGL(k_detect_init, dim3((nch + 255) / 256), dim3(256), 0, c->stream,
+                       c->buf.peak_cnt, c->buf.changed, nch, c->cfg.B);
+    return hipGetLastError();
+}
+
+// Clip planes: clip[j] = buf.clip + j * plane, j = 0, 1.  Iteration 1 writes
+// Y_1 into both; iteration i reads clip[(i-1)&1] and writes clip[i&1] whole.
+// A band that stops changing therefore holds equal planes, so the final
+// plane clip[iters&1] is its last mask whichever iteration it stopped at.
+hipError_t launch_filters(lpf_ctx* c, int slot) {
+    const int B = c->cfg.B;
+    const int iters = c->cfg.clip_iters;
+    const size_t plane = c->d.plane;
+    uint8_t* clip0 = c->buf.clip;
+    uint8_t* clip1 = c->buf.clip ? c->buf.clip + plane : nullptr;
+    hipError_t e;
+    FiltArgs a = base_args(c, slot);
+    a.out = c->buf.centre;
+    {
+        StageTimer tm(c, 2);
+        if ((e = dispatch_k<IN_MX, OUT_C_STATIC>(c, a, B)) != hipSuccess) return e;
+    }
+    StageTimer tm3(c, 3);
+    a = base_args(c, slot);
+    if (iters == 1) {
+        a.S_out = c->d.dyn ? c->buf.spread : nullptr;
+        a.Y_out = c->d.dyn ? clip1 : nullptr;
+        return dispatch_k<IN_ME, OUT_S_PEAKS>(c, a, B);
+    }
+    // Several iterations: S and Y planes are materialised and peaks are
+    // listed after the last iteration.
+    a.S_out = c->buf.spread;
+    a.Y_out = clip0;
+    a.Y_out2 = clip1;
+    a.changed = c->buf.changed + B;   // changed[1]
+    a.peak_cap = 0;                   // no peak records from this pass
+    a.kp = 0;
+    if ((e = dispatch_k<IN_ME, OUT_S_PEAKS>(c, a, B)) != hipSuccess) return e;
+    for (int it = 2; it <= iters; ++it) {
+        uint8_t* yin = ((it - 1) & 1) ? clip1 : clip0;
+        uint8_t* yout = (it & 1) ? clip1 : clip0;
+        const int32_t* act = c->buf.changed + (size_t)(it - 1) * B;
+        FiltArgs d = base_args(c, slot);
+        d.Y = yin;
+        d.active = act;
+        d.out = c->buf.den;
+        if ((e = dispatch_k<IN_W, OUT_RAW>(c, d, B)) != hipSuccess) return e;
+        FiltArgs cc = d;
+        cc.out = c->buf.centre;
+        if ((e = dispatch_k<IN_WX, OUT_C_DYN>(c, cc, B)) != hipSuccess) return e;
+        FiltArgs ss = d;
+        ss.out = nullptr;
+        ss.S_out = c->buf.spread;
+        ss.Y_out = yout;
+        ss.changed = c->buf.changed + (size_t)it * B;
+        if ((e = dispatch_k<IN_WE, OUT_S_DYN>(c, ss, B)) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_detect_init, dim3(1), dim3(64), 0, c->stream, c->buf.peak_cnt,
+                       (int32_t*)nullptr, 0, B);
+    FiltArgs p = base_args(c, slot);
+    p.Y = (iters & 1) ? clip1 : clip0;
+    p.den = c->buf.spread;  // k_peaks_planes reads S through the den slot
+    const int HW = c->cfg.H * c->cfg.W;
+    int gx = (HW + 255) / 256;
+    if (gx > 1024) gx = 1024;
+    hipLaunchKernelGGL(k_peaks_planes, dim3(gx, B), dim3(256), 0, c->stream, p);
+    return hipGetLastError();
+}
+
+}  // namespace lpf

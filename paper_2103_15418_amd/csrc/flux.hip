@@ -1,0 +1,209 @@
+// Flux measurement, backward fill and dynamic-spectrum windows (Sec. 2.2,
+// Fig. 3).
+//
+// The flux of a source in a band is the maximum pixel value of the
+// quality-controlled image in a (2k_f + 1)^2 box (clipped to the image)
+// around the source's pixel; a band discarded by QC reads as zeros, so its
+// flux is 0 and it is marked invalid.  Each measured source writes one value
+// per band into its ring F[slot][band][tau mod 64] with the step tau in
+// ring_t[slot][tau mod 64] and the valid-band bits in ring_v.  New sources
+// are also measured on the cached steps [max(t - T_bf, t_start), t - 1].
+// One lane per (source, band[, step]); the lists and their lengths come
+// from the catalogue kernel in device memory, so grids are fixed-size and
+// every lane runs a bounded grid-stride loop.
+
+#include "lpf_internal.h"
+
+namespace lpf {
+namespace {
+
+struct FluxArgs {
+    const float* cache;       // [Tc][B][H][W]
+    const int64_t* cache_t;   // [Tc]
+    const uint32_t* cache_rej;
+    int Tc, B, H, W, kf, T_bf;
+    int64_t t, t_start;
+    size_t plane;
+    const int32_t* list;      // measured or new slots
+    const int32_t* count;     // device count
+    const int32_t* src_row;
+    const int32_t* src_col;
+    float* ring;
+    int64_t* ring_t;
+    uint32_t* ring_v;
+};
+
+__device__ inline int pmod(int64_t a, int m) {
+    int64_t r = a % m;
+    return (int)(r < 0 ? r + m : r);
+}
+
+__device__ inline float box_max(const float* img, int H, int W, int i, int j, int k) {
+    const int r0 = i - k < 0 ? 0 : i - k, r1 = i + k >= H ? H - 1 : i + k;
+    const int c0 = j - k < 0 ? 0 : j - k, c1 = j + k >= W ? W - 1 : j + k;
+    float m = -INFINITY;
+    for (int r = r0; r <= r1; ++r)
+        for (int c = c0; c <= c1; ++c) m = fmaxf(m, img[(size_t)r * W + c]);
+    return m;
+}
+
+// Current step: every measured source, every band.
+__global__ __launch_bounds__(256) void k_flux(FluxArgs a) {
+    const int n = *a.count;
+    const int cs = pmod(a.t, a.Tc);
+    const uint32_t rej = a.cache_rej[cs];
+    const float* frame = a.cache + (size_t)cs * a.plane;
+    const int ri = pmod(a.t, kRing);
+    const uint32_t allb = (a.B == 32) ? 0xffffffffu : ((1u << a.B) - 1u);
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < (int64_t)n * a.B;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        const int s = a.list[w / a.B];
+        const int b = (int)(w % a.B);
+        const float f = ((rej >> b) & 1u)
+                            ? 0.0f
+                            : box_max(frame + (size_t)b * a.H * a.W, a.H, a.W, a.src_row[s],
+                                      a.src_col[s], a.kf);
+        a.ring[((size_t)s * a.B + b) * kRing + ri] = f;
+        if (b == 0) {
+            a.ring_t[(size_t)s * kRing + ri] = a.t;
+            a.ring_v[(size_t)s * kRing + ri] = ~rej & allb;
+        }
+    }
+}
+
+// Backward fill of the sources opened at this step.
+__global__ __launch_bounds__(256) void k_backfill(FluxArgs a) {
+    const int n = *a.count;
+    const int64_t per_src = (int64_t)a.T_bf * a.B;
+    const uint32_t allb = (a.B == 32) ? 0xffffffffu : ((1u << a.B) - 1u);
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < (int64_t)n * per_src;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        const int s = a.list[w / per_src];
+        const int rem = (int)(w % per_src);
+        const int d = rem / a.B, b = rem % a.B;
+        const int64_t tau = a.t - a.T_bf + d;
+        if (tau < a.t_start) continue;
+        const int cs = pmod(tau, a.Tc);
+        if (a.cache_t[cs] != tau) continue;  // step never ingested (gap)
+        const uint32_t rej = a.cache_rej[cs];
+        const float* frame = a.cache + (size_t)cs * a.plane;
+        const float f = ((rej >> b) & 1u)
+                            ? 0.0f
+                            : box_max(frame + (size_t)b * a.H * a.W, a.H, a.W, a.src_row[s],
+                                      a.src_col[s], a.kf);
+        const int ri = pmod(tau, kRing);
+        a.ring[((size_t)s * a.B + b) * kRing + ri] = f;
+        if (b == 0) {
+            a.ring_t[(size_t)s * kRing + ri] = tau;
+            a.ring_v[(size_t)s * kRing + ri] = ~rej & allb;
+        }
+    }
+}
+
+struct WinArgs {
+    int n, B;
+    const int32_t* slots;     // [n]
+    const int64_t* t_end;     // [n] window end per entry (device)
+    const float* ring;
+    const int64_t* ring_t;
+    const uint32_t* ring_v;
+    int32_t row_band[kGridRows];  // band on each grid row, -1 if none
+    float* out;               // [n][16][64]
+};
+
+// Network input windows: x[n][row][c] = F[slot][band(row)][tau], tau = t_end - 63 + c.
+__global__ __launch_bounds__(256) void k_windows(WinArgs a) {
+    const int64_t total = (int64_t)a.n * kGridRows * kRing;
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        const int n = (int)(w / (kGridRows * kRing));
+        const int row = (int)((w / kRing) % kGridRows);
+        const int c = (int)(w % kRing);
+        const int b = a.row_band[row];
+        float v = 0.0f;
+        if (b >= 0) {
+            const int s = a.slots[n];
+            const int64_t tau = a.t_end[n] - (kRing - 1) + c;
+            const int ri = pmod(tau, kRing);
+            if (a.ring_t[(size_t)s * kRing + ri] == tau && ((a.ring_v[(size_t)s * kRing + ri] >> b) & 1u))
+                v = a.ring[((size_t)s * a.B + b) * kRing + ri];
+        }
+        a.out[w] = v;
+    }
+}
+
+// Ended list -> (slots, t_end) for the window gather.
+__global__ void k_ended_ends(const int32_t* list, const int32_t* count, const int64_t* src_tend,
+                             int32_t* slots_out, int64_t* tend_out) {
+    const int n = *count;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int s = list[i];
+        slots_out[i] = s;
+        tend_out[i] = src_tend[s];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_flux(lpf_ctx* c, int slot, int64_t t) {
+    (void)slot;
+    FluxArgs a;
+    a.cache = c->buf.cache;
+    a.cache_t = c->buf.cache_t;
+    a.cache_rej = c->buf.cache_rej;
+    a.Tc = c->d.Tc;
+    a.B = c->cfg.B;
+    a.H = c->cfg.H;
+    a.W = c->cfg.W;
+    a.kf = c->cfg.flux_halfwidth;
+    a.T_bf = c->cfg.backfill_steps;
+    a.t = t;
+    a.t_start = c->t_start;
+    a.plane = c->d.plane;
+    a.src_row = c->buf.src_row;
+    a.src_col = c->buf.src_col;
+    a.ring = c->buf.ring;
+    a.ring_t = c->buf.ring_t;
+    a.ring_v = c->buf.ring_v;
+    a.list = c->buf.list_measured;
+    a.count = &c->buf.status->n_measured;
+    hipLaunchKernelGGL(k_flux, dim3(128), dim3(256), 0, c->stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (a.T_bf > 0) {
+        a.list = c->buf.list_new;
+        a.count = &c->buf.status->n_new;
+        hipLaunchKernelGGL(k_backfill, dim3(256), dim3(256), 0, c->stream, a);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+// Gathers windows for n entries: d_slots[n], d_tend[n] on the device.
+hipError_t launch_windows_gather(lpf_ctx* c, int n, const int32_t* d_slots, const int64_t* d_tend,
+                                 float* d_out) {
+    WinArgs a;
+    a.n = n;
+    a.B = c->cfg.B;
+    a.slots = d_slots;
+    a.t_end = d_tend;
+    a.ring = c->buf.ring;
+    a.ring_t = c->buf.ring_t;
+    a.ring_v = c->buf.ring_v;
+    for (int r = 0; r < kGridRows; ++r) a.row_band[r] = -1;
+    for (int b = 0; b < c->cfg.B; ++b) a.row_band[c->grid_rows[b]] = b;
+    a.out = d_out;
+    int blocks = (int)((((int64_t)n * kGridRows * kRing) + 255) / 256);
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_windows, dim3(blocks), dim3(256), 0, c->stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_ended_ends(lpf_ctx* c, int32_t* slots_out, int64_t* tend_out) {
+    hipLaunchKernelGGL(k_ended_ends, dim3(32), dim3(256), 0, c->stream, c->buf.list_ended,
+                       &c->buf.status->n_ended, c->buf.src_tend, slots_out, tend_out);
+    return hipGetLastError();
+}
+
+}  // namespace lpf

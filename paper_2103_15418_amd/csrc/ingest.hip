@@ -1,0 +1,296 @@
+// Quality control of one image cube (App. A) and its entry into the image
+// cache (Sec. 2.2, "measure from cached images").
+//
+// One streaming pass per cube (k_ingest) reads each pixel once and
+//   * copies it into the cache slot (device input),
+//   * accumulates the band sums sum(x), sum(x^2) in float64 and counts
+//     non-finite pixels,
+//   * scores it against the running per-pixel mean / std of accepted steps
+//     (zeta = |x - mean| / std, max per band),
+//   * writes the Welford update of (mean, M2) into the band's *other* state
+//     buffer.
+// A one-wave kernel (k_qc_decide) then reduces the per-block partials in a
+// fixed order, forms the robust z-scores of band means and RMS (median /
+// median absolute deviation across bands), takes the decision, and commits
+// the speculative Welford update of accepted bands by flipping their buffer
+// index.  Rejected bands keep their old statistics and are treated as all
+// zeros by every later stage (the cached bytes are left untouched).
+//
+// HBM traffic per subband-pixel: x 4 B, state read 8 B, state write 8 B,
+// cache write 4 B = 24 B, the algorithmic minimum of the stage.
+
+#include <cmath>
+
+#include "lpf_internal.h"
+
+namespace lpf {
+namespace {
+
+constexpr int kIngThreads = 256;
+
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline int wave_sum_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ inline float wave_max_f(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+struct PixAcc {
+    double sx = 0.0, sxx = 0.0;
+    int nf = 0;
+    float zmax = 0.0f;
+};
+
+__device__ inline void pixel_step(float x, float mu, float m2, bool score, float inv_nm1,
+                                  float inv_n1, PixAcc& a, float& mu_out, float& m2_out) {
+    double xd = (double)x;
+    a.sx += xd;
+    a.sxx += xd * xd;
+    a.nf += isfinite(x) ? 0 : 1;
+    float d = x - mu;
+    if (score) {
+        float s2 = m2 * inv_nm1;
+        if (s2 > 0.0f) a.zmax = fmaxf(a.zmax, fabsf(d) / sqrtf(s2));
+    }
+    float mu1 = fmaf(d, inv_n1, mu);
+    mu_out = mu1;
+    m2_out = fmaf(d, x - mu1, m2);
+}
+
+// grid: (nblk, B).  Block (blk, b) handles pixels [blk*chunk, min(HW, (blk+1)*chunk)).
+template <bool COPY, bool VEC>
+__global__ __launch_bounds__(kIngThreads) void k_ingest(
+    const float* __restrict__ src, float* __restrict__ cache_slot, const float* __restrict__ wf_mean,
+    const float* __restrict__ wf_m2, float* __restrict__ wf_mean_w, float* __restrict__ wf_m2_w,
+    const int32_t* __restrict__ wf_n, const int32_t* __restrict__ wf_cur,
+    const uint8_t* __restrict__ mask, size_t HW, size_t plane, int64_t chunk, int warm,
+    BandPartial* __restrict__ partials) {
+    const int b = blockIdx.y;
+    const int blk = blockIdx.x;
+    const int n = wf_n[b];
+    const int cur = wf_cur[b];
+    const bool armed = n >= warm && n >= 2;
+    const float inv_nm1 = armed ? 1.0f / (float)(n - 1) : 0.0f;
+    const float inv_n1 = 1.0f / (float)(n + 1);
+    const size_t boff = (size_t)b * HW;
+    const float* xs = src + boff;
+    float* xc = cache_slot + boff;
+    const float* mi = wf_mean + (size_t)cur * plane + boff;
+    const float* qi = wf_m2 + (size_t)cur * plane + boff;
+    float* mo = wf_mean_w + (size_t)(1 - cur) * plane + boff;
+    float* qo = wf_m2_w + (size_t)(1 - cur) * plane + boff;
+    const size_t p0 = (size_t)blk * chunk;
+    const size_t p1 = p0 + chunk < HW ? p0 + chunk : HW;
+    PixAcc a;
+    if (VEC) {
+        // HW % 4 == 0 and chunk % 4 == 0: every float4 is aligned and whole.
+        for (size_t p = p0 + 4 * threadIdx.x; p < p1; p += 4 * kIngThreads) {
+            float4 x = *reinterpret_cast<const float4*>(xs + p);
+            float4 mu = *reinterpret_cast<const float4*>(mi + p);
+            float4 m2 = *reinterpret_cast<const float4*>(qi + p);
+            uchar4 mk = mask ? *reinterpret_cast<const uchar4*>(mask + p) : make_uchar4(1, 1, 1, 1);
+            if (COPY) *reinterpret_cast<float4*>(xc + p) = x;
+            float4 mu1, q1;
+            pixel_step(x.x, mu.x, m2.x, armed && mk.x, inv_nm1, inv_n1, a, mu1.x, q1.x);
+            pixel_step(x.y, mu.y, m2.y, armed && mk.y, inv_nm1, inv_n1, a, mu1.y, q1.y);
+            pixel_step(x.z, mu.z, m2.z, armed && mk.z, inv_nm1, inv_n1, a, mu1.z, q1.z);
+            pixel_step(x.w, mu.w, m2.w, armed && mk.w, inv_nm1, inv_n1, a, mu1.w, q1.w);
+            *reinterpret_cast<float4*>(mo + p) = mu1;
+            *reinterpret_cast<float4*>(qo + p) = q1;
+        }
+    } else {
+        for (size_t p = p0 + threadIdx.x; p < p1; p += kIngThreads) {
+            float x = xs[p];
+            if (COPY) xc[p] = x;
+            bool mk = mask ? mask[p] != 0 : true;
+            float mu1, q1;
+            pixel_step(x, mi[p], qi[p], armed && mk, inv_nm1, inv_n1, a, mu1, q1);
+            mo[p] = mu1;
+            qo[p] = q1;
+        }
+    }
+    // Fixed-shape block reduction (deterministic).
+    __shared__ double s_sx[kIngThreads / 64], s_sxx[kIngThreads / 64];
+    __shared__ int s_nf[kIngThreads / 64];
+    __shared__ float s_z[kIngThreads / 64];
+    double sx = wave_sum_d(a.sx), sxx = wave_sum_d(a.sxx);
+    int nf = wave_sum_i(a.nf);
+    float z = wave_max_f(a.zmax);
+    const int w = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) {
+        s_sx[w] = sx;
+        s_sxx[w] = sxx;
+        s_nf[w] = nf;
+        s_z[w] = z;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        BandPartial bp;
+        bp.sx = 0.0;
+        bp.sxx = 0.0;
+        bp.nonfinite = 0;
+        bp.zmax = 0.0f;
+        for (int i = 0; i < kIngThreads / 64; ++i) {
+            bp.sx += s_sx[i];
+            bp.sxx += s_sxx[i];
+            bp.nonfinite += s_nf[i];
+            bp.zmax = fmaxf(bp.zmax, s_z[i]);
+        }
+        bp.pad[0] = bp.pad[1] = 0;
+        partials[(size_t)b * gridDim.x + blk] = bp;
+    }
+}
+
+__device__ void sort_small(double* v, int n) {
+    for (int i = 1; i < n; ++i) {
+        double x = v[i];
+        int j = i - 1;
+        while (j >= 0 && v[j] > x) {
+            v[j + 1] = v[j];
+            --j;
+        }
+        v[j + 1] = x;
+    }
+}
+
+__device__ double median_small(double* v, int n) {
+    sort_small(v, n);
+    return (n & 1) ? v[n / 2] : 0.5 * (v[n / 2 - 1] + v[n / 2]);
+}
+
+// Robust z of v over the bands flagged in use: (v - med) / max(MAD, floor |med|).
+__device__ void robust_z(const double* v, const bool* use, int B, double floor_rel, double* z) {
+    double tmp[kMaxB];
+    int m = 0;
+    for (int b = 0; b < B; ++b)
+        if (use[b]) tmp[m++] = v[b];
+    for (int b = 0; b < B; ++b) z[b] = 0.0;
+    if (m == 0) return;
+    double med = median_small(tmp, m);
+    m = 0;
+    for (int b = 0; b < B; ++b)
+        if (use[b]) tmp[m++] = fabs(v[b] - med);
+    double mad = median_small(tmp, m);
+    double fl = floor_rel * fabs(med);
+    if (fl > mad) mad = fl;
+    for (int b = 0; b < B; ++b) {
+        if (!use[b]) continue;
+        double dlt = v[b] - med;
+        z[b] = mad > 0.0 ? dlt / mad : (dlt == 0.0 ? 0.0 : INFINITY);
+    }
+}
+
+struct QcParams {
+    int B;
+    int nblk;
+    double npix;
+    double band_z, rms_z, rms_floor, zeta;
+    int warm;
+};
+
+__global__ __launch_bounds__(64) void k_qc_decide(QcParams q, const BandPartial* __restrict__ partials,
+                                                   int32_t* wf_n, int32_t* wf_cur, double* bandstats,
+                                                   int64_t* cache_t, uint32_t* cache_rej, int slot,
+                                                   int64_t t, DevStatus* status) {
+    __shared__ double s_mean[kMaxB], s_rms[kMaxB];
+    __shared__ int s_nf[kMaxB];
+    __shared__ float s_z[kMaxB];
+    const int b = threadIdx.x;
+    if (b < q.B) {
+        double sx = 0.0, sxx = 0.0;
+        int nf = 0;
+        float z = 0.0f;
+        const BandPartial* p = partials + (size_t)b * q.nblk;
+        for (int i = 0; i < q.nblk; ++i) {
+            sx += p[i].sx;
+            sxx += p[i].sxx;
+            nf += p[i].nonfinite;
+            z = fmaxf(z, p[i].zmax);
+        }
+        s_mean[b] = sx / q.npix;
+        s_rms[b] = sqrt(sxx / q.npix);
+        s_nf[b] = nf;
+        s_z[b] = z;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    bool ok[kMaxB];
+    double zm[kMaxB], zr[kMaxB];
+    for (int i = 0; i < q.B; ++i) ok[i] = s_nf[i] == 0;
+    robust_z(s_mean, ok, q.B, 0.0, zm);
+    if (q.rms_z > 0.0)
+        robust_z(s_rms, ok, q.B, q.rms_floor, zr);
+    else
+        for (int i = 0; i < q.B; ++i) zr[i] = 0.0;
+    uint32_t rej = 0;
+    for (int i = 0; i < q.B; ++i) {
+        const int n = wf_n[i];
+        const bool armed = n >= q.warm && n >= 2;
+        bool bad = !ok[i] || fabs(zm[i]) > q.band_z || (q.rms_z > 0.0 && fabs(zr[i]) > q.rms_z) ||
+                   (armed && (double)s_z[i] > q.zeta);
+        if (bad) rej |= 1u << i;
+        double* bs = bandstats + 6 * i;
+        bs[0] = s_mean[i];
+        bs[1] = s_rms[i];
+        bs[2] = zm[i];
+        bs[3] = zr[i];
+        bs[4] = armed ? (double)s_z[i] : 0.0;
+        bs[5] = (double)s_nf[i];
+        if (!bad) {  // commit the speculative Welford update
+            wf_n[i] = n + 1;
+            wf_cur[i] = 1 - wf_cur[i];
+        }
+    }
+    cache_t[slot] = t;
+    cache_rej[slot] = rej;
+    status->rejected = rej;
+}
+
+}  // namespace
+
+hipError_t launch_ingest(lpf_ctx* c, const float* src, bool copy, int slot) {
+    const auto& d = c->d;
+    const int B = c->cfg.B;
+    float* slotp = c->buf.cache + (size_t)slot * d.plane;
+    const int64_t chunk = (int64_t)((d.HW + d.nblk - 1) / d.nblk + 3) / 4 * 4;
+    const bool vec = (d.HW % 4) == 0;
+    dim3 grid(d.nblk, B);
+    const uint8_t* mk = d.masked ? c->buf.mask : nullptr;
+#define LPF_ING(C, V)                                                                        \
+    hipLaunchKernelGGL((k_ingest<C, V>), grid, dim3(kIngThreads), 0, c->stream, src, slotp,   \
+                       c->buf.wf_mean, c->buf.wf_m2, c->buf.wf_mean, c->buf.wf_m2, c->buf.wf_n, \
+                       c->buf.wf_cur, mk, d.HW, d.plane, chunk, c->cfg.qc_warmup, c->buf.partials)
+    if (copy && vec) LPF_ING(true, true);
+    else if (copy) LPF_ING(true, false);
+    else if (vec) LPF_ING(false, true);
+    else LPF_ING(false, false);
+#undef LPF_ING
+    return hipGetLastError();
+}
+
+hipError_t launch_qc_decide(lpf_ctx* c, int slot, int64_t t) {
+    QcParams q;
+    q.B = c->cfg.B;
+    q.nblk = c->d.nblk;
+    q.npix = (double)c->d.HW;
+    q.band_z = c->cfg.qc_band_z;
+    q.rms_z = c->cfg.qc_rms_z;
+    q.rms_floor = c->cfg.qc_rms_floor;
+    q.zeta = c->cfg.qc_pixel_zeta;
+    q.warm = c->cfg.qc_warmup;
+    hipLaunchKernelGGL(k_qc_decide, dim3(1), dim3(64), 0, c->stream, q, c->buf.partials, c->buf.wf_n,
+                       c->buf.wf_cur, c->buf.bandstats, c->buf.cache_t, c->buf.cache_rej, slot, t,
+                       c->buf.status);
+    return hipGetLastError();
+}
+
+}  // namespace lpf

@@ -1,0 +1,110 @@
+"""Helpers shared by the device-vs-oracle parity tests.
+
+Tolerances (FP32 device path vs the FP64 oracle):
+* centre C:  |C_dev - C| <= 1e-5 (G*(W|X|)) / (G*W)        (scale-aware: C ~ 0 on noise)
+* spread S:  |S_dev - S| <= 1e-5 (G*(W(|X| + |C|)^2)) / (G*W)
+* peaks (one clip iteration): with sig = (x - c) / sqrt(s) from the oracle,
+  every local maximum with sig > kappa + 1e-3 is listed and nothing with
+  sig <= kappa - 1e-3 is; each listed record's sig within 1e-5 (1 + |sig|)
+  (x, band, row, col exact; the threshold is monotone in kappa, so this is
+  the bracketing P(kappa + d) <= P_dev <= P(kappa - d));
+* QC band statistics: float64 on both sides, 1e-12 relative; decisions
+  identical unless a score is within 1e-5 (relative) of its threshold;
+* Welford state: 1e-5 of the pixel's RMS (mean) / sum of squares (M2);
+* fluxes and dynamic spectra: bitwise identical (pure selection);
+* network: per output 1e-5 of the condition scale (|W| |x| propagated).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from oracle.config import OracleConfig
+from oracle.filters import centre_spread, correlate_2d
+from oracle.pipeline import OracleStream
+
+PARAM_MAP = dict(kappa="kappa", bg_sigma="s", bg_halfwidth="k_bg", kernel="kernel",
+                 clip_iters="n_iter", peak_halfwidth="k_peak", flux_halfwidth="k_flux",
+                 dup_radius="r_dup", assoc_radius="r_assoc", monitor_steps="n_mon",
+                 backfill_steps="t_bf", qc_band_z="qc_band_z", qc_rms_z="qc_rms_z",
+                 qc_rms_floor="qc_rms_floor", qc_pixel_zeta="qc_pixel_zeta",
+                 qc_warmup="qc_warmup", max_sources="max_sources", peak_cap="peak_cap")
+
+
+def make_pair(B, H, W, sky_mask=None, grid_rows=None, **params):
+    """(device Context, OracleStream) with the same parameters."""
+    from paper_2103_15418_amd import Context
+    ctx = Context(B, H, W, sky_mask=sky_mask, grid_rows=grid_rows, **params)
+    ok = {PARAM_MAP[k]: v for k, v in params.items() if k in PARAM_MAP}
+    if "k_bg" in ok and ok["k_bg"] <= 0:
+        ok.pop("k_bg")
+    ocfg = OracleConfig(B=B, H=H, W=W, sky_mask=sky_mask, **ok)
+    if grid_rows is not None:
+        rows = list(grid_rows)
+        ocfg.grid_row = lambda b, rows=rows: rows[b]
+    return ctx, OracleStream(ocfg)
+
+
+def check_planes(Cd, Sd, X, M, g, rej, label=""):
+    """Dense C / S planes of one step (one clip iteration) against the oracle."""
+    for b in range(X.shape[0]):
+        if rej >> b & 1:
+            continue
+        C, S, den = centre_spread(X[b], M, g)
+        w = M.astype(np.float64)
+        pos = den > 0
+        safe = np.where(pos, den, 1.0)
+        scC = np.where(pos, correlate_2d(w * np.abs(X[b].astype(np.float64)), g) / safe, 0.0)
+        scS = np.where(pos, correlate_2d(w * (np.abs(X[b].astype(np.float64)) + np.abs(C)) ** 2, g) / safe, 0.0)
+        eC = np.abs(Cd[b].astype(np.float64) - C)
+        eS = np.abs(Sd[b].astype(np.float64) - S)
+        bad_c = eC > 1e-5 * scC + 1e-30
+        bad_s = eS > 1e-5 * scS + 1e-30
+        assert not bad_c.any(), (label, b, "C", float((eC / np.maximum(scC, 1e-30)).max()))
+        assert not bad_s.any(), (label, b, "S", float((eS / np.maximum(scS, 1e-30)).max()))
+
+
+def oracle_sig_map(Xb, M, g, k_peak):
+    """(Q local-max map, sig = (x - c)/sqrt(s) or +-inf) for one band, one iteration."""
+    from oracle.detect import local_max
+    C, S, den = centre_spread(Xb, M, g)
+    x = Xb.astype(np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        sig = np.where(S > 0, (x - C) / np.sqrt(S), np.where(x > C, np.inf, -np.inf))
+    sig = np.where(M & (den > 0), sig, -np.inf)
+    return local_max(Xb, M, k_peak), sig, C, S
+
+
+def check_peaks_bracket(peaks_dev, X, M, g, kappa, k_peak, rej, label="", delta=1e-3):
+    """Bracketing rule at one clip iteration; returns the number of excused differences."""
+    dev = {(int(p["band"]), int(p["row"]), int(p["col"])): p for p in peaks_dev}
+    excused = 0
+    for b in range(X.shape[0]):
+        if rej >> b & 1:
+            assert not any(k[0] == b for k in dev), (label, "peaks in a rejected band")
+            continue
+        Q, sig, C, S = oracle_sig_map(X[b], M, g, k_peak)
+        must = Q & (sig > kappa + delta)
+        may = Q & (sig > kappa - delta)
+        got = np.zeros_like(Q)
+        for (bb, i, j), p in dev.items():
+            if bb != b:
+                continue
+            got[i, j] = True
+            assert may[i, j], (label, b, i, j, float(sig[i, j]))
+            assert p["x"] == np.float32(X[b, i, j])
+            s_or = sig[i, j]
+            if np.isfinite(s_or):
+                assert abs(float(p["sig"]) - s_or) <= 1e-5 * (1 + abs(s_or)), (label, b, i, j)
+        missing = must & ~got
+        assert not missing.any(), (label, b, np.argwhere(missing)[:5].tolist())
+        excused += int((got ^ (Q & (sig > kappa))).sum())
+    return excused
+
+
+def cnn_scale(x, wts):
+    """Condition scale of each raw output: |W| |x| + |b| propagated (activations <= identity)."""
+    from oracle import cnn
+    aw = {k: (np.abs(v) if isinstance(v, np.ndarray) else v) for k, v in wts.items()}
+    aw["alpha"] = 1.0
+    return cnn.forward_raw(np.abs(x), aw)

@@ -1,0 +1,77 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+declared in include/lpf.h, and validates configurations without a device."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lpf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(lpf_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_four_stages():
+    names = declared_functions()
+    for n in ("lpf_ingest_frame", "lpf_detect", "lpf_extract_flux", "lpf_infer"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2103_15418_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("library not built")
+    lib = C.CDLL(P.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_config_validation_host_only():
+    import paper_2103_15418_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("library not built")
+    cfg = P.default_config(16, 1024, 1024)
+    n = P.workspace_size(cfg)
+    # cache (33 cubes) + Welford (4 planes) + centre dominate: > 37 planes of 64 MiB
+    assert n > 37 * 64 * 2 ** 20
+    for bad in (dict(B=17), dict(B=0), dict(H=5000), dict(ring_len=32), dict(clip_iters=0),
+                dict(peak_cap=600), dict(bg_halfwidth=41), dict(filter_precision=1),
+                dict(max_sources=0), dict(peak_halfwidth=0)):
+        c = P.default_config(16, 1024, 1024)
+        for k, v in bad.items():
+            setattr(c, k, v)
+        with pytest.raises(P.LpfError):
+            P.workspace_size(c)
+
+
+def test_weights_blob_size_and_packing():
+    import numpy as np
+
+    import paper_2103_15418_amd as P
+    import synth
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("library not built")
+    wts = synth.cnn_weights(seed=1)
+    blob = P.pack_weights(wts)
+    assert len(blob) == P.lib().lpf_model_weights_bytes()
+    arr = np.frombuffer(blob, dtype=np.float32)
+    assert arr[0] == wts["conv1.w"].ravel()[0] and arr[-1] == 0.0
+    bad = dict(wts)
+    bad["fc2.b"] = np.zeros(13, dtype=np.float32)
+    with pytest.raises(ValueError):
+        P.pack_weights(bad)
+
+
+def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
+    import paper_2103_15418_amd._abi as A
+    monkeypatch.setattr(A, "_lib", None)
+    monkeypatch.setattr(A, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        A.lib()
