@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after timing, copy 256 MiB device-to-device once (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -189,6 +191,13 @@ def main():
         "roofline": roof,
         "stages": stages,
     }
+    if args.calibrate_copy:
+        src = torch.ones(64 * 2 ** 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
         print(f"[bench] cpu baseline ({args.cpu_frames} oracle steps)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_frames)

@@ -89,6 +89,7 @@ Derived derive(const lpf_config* c) {
     d.plane = (size_t)c->B * d.HW;
     d.masked = c->sky_mask != nullptr;
     d.dyn = c->clip_iters > 1 || c->debug_planes != 0;
+    d.mwords = (c->W + 31) / 32;
     size_t nb = (d.HW + 8191) / 8192;  // ~8K pixels per ingest block
     if (nb < 1) nb = 1;
     d.nblk = (int)nb;
@@ -107,6 +108,7 @@ size_t carve(const lpf_config* c, const Derived& d, char* base, DevBufs* b) {
     b->wf_n = cv.take<int32_t>(kMaxB);
     b->wf_cur = cv.take<int32_t>(kMaxB);
     b->mask = cv.take<uint8_t>(d.HW);
+    b->mask_bits = cv.take<uint32_t>((size_t)c->H * d.mwords);
     b->inv_den = cv.take<float>(d.HW);
     b->centre = cv.take<float>(d.plane);
     b->spread = d.dyn ? cv.take<float>(d.plane) : nullptr;
@@ -118,7 +120,7 @@ size_t carve(const lpf_config* c, const Derived& d, char* base, DevBufs* b) {
     b->peak_cnt = cv.take<int32_t>(kMaxB);
     b->peak_raw = cv.take<PeakRec>((size_t)c->B * c->peak_cap);
     b->peak_sorted = cv.take<PeakRec>((size_t)c->B * c->peak_cap);
-    b->cat_keys = nullptr;
+    b->cat_dec = cv.take<int32_t>(kCatMaxPeaks);
     b->cat_order = cv.take<int32_t>(kCatMaxPeaks);
     b->cat_kept = cv.take<int32_t>(kCatMaxPeaks);
     b->cat_nbr = cv.take<int32_t>((size_t)kCatMaxPeaks * (kNbr + 1));
@@ -279,6 +281,7 @@ int lpf_create(const lpf_config* cfg, void* ws, size_t bytes, void* stream, lpf_
     if (e == hipSuccess && c->buf.clip) e = zero(c->buf.clip, 2 * d.plane);
     if (e == hipSuccess) e = zero(c->buf.src_id, cfg->max_sources * sizeof(int32_t));
     if (e == hipSuccess) e = launch_table_init(c);
+    if (e == hipSuccess) e = launch_pack_mask(c);
     if (e == hipSuccess) e = launch_inv_den(c);
     if (e == hipSuccess && d.masked) {
         // mask copy is from pageable host memory: finish before returning
@@ -547,88 +550,122 @@ int lpf_infer_windows(const lpf_model* m, const float* windows, int32_t n, float
 int lpf_infer(lpf_ctx* const* ctxs, int32_t n_ctx, const lpf_model* m, const int32_t* ids, int32_t n_ids,
               float* mu_out, float* L_out, int32_t* src_out, int32_t cap, int32_t* n_out) {
     if (!ctxs || n_ctx < 1 || !m || !n_out) return LPF_EINVAL;
-    if (ids && n_ctx != 1) return LPF_EINVAL;
+    if (ids && (n_ctx != 1 || n_ids < 0)) return LPF_EINVAL;
     for (int i = 0; i < n_ctx; ++i) {
         LPF_CHECK_CTX(ctxs[i]);
         if (ctxs[i]->phase != 3) return fail(ctxs[i], LPF_ESTATE, "infer needs extract_flux first");
     }
     lpf_ctx* c0 = ctxs[0];
     hipStream_t s = c0->stream;
-    // gather (ctx, slot, t_end) entries
-    struct Ent { int ctx; int32_t slot; int64_t tend; int32_t id; };
-    std::vector<Ent> ents;
-    for (int ci = 0; ci < n_ctx; ++ci) {
-        lpf_ctx* c = ctxs[ci];
-        LPF_HIP(c, hipStreamSynchronize(c->stream), "infer sync");
-        const int S = c->cfg.max_sources;
-        if (!ids) {
-            DevStatus st;
-            LPF_HIP(c, hipMemcpy(&st, c->buf.status, sizeof(st), hipMemcpyDeviceToHost), "status");
-            if (st.n_ended == 0) continue;
-            std::vector<int32_t> slots(st.n_ended), idv(S);
-            std::vector<int64_t> tend(S);
-            LPF_HIP(c, hipMemcpy(slots.data(), c->buf.list_ended, st.n_ended * sizeof(int32_t), hipMemcpyDeviceToHost), "ended");
-            LPF_HIP(c, hipMemcpy(idv.data(), c->buf.src_id, S * sizeof(int32_t), hipMemcpyDeviceToHost), "ids");
-            LPF_HIP(c, hipMemcpy(tend.data(), c->buf.src_tend, S * sizeof(int64_t), hipMemcpyDeviceToHost), "tend");
-            for (int32_t sl : slots) ents.push_back({ci, sl, tend[sl], idv[sl]});
-        } else {
-            std::vector<int32_t> idv(S), state(S);
-            std::vector<int64_t> tend(S);
-            LPF_HIP(c, hipMemcpy(idv.data(), c->buf.src_id, S * sizeof(int32_t), hipMemcpyDeviceToHost), "ids");
-            LPF_HIP(c, hipMemcpy(state.data(), c->buf.src_state, S * sizeof(int32_t), hipMemcpyDeviceToHost), "state");
-            LPF_HIP(c, hipMemcpy(tend.data(), c->buf.src_tend, S * sizeof(int64_t), hipMemcpyDeviceToHost), "tend");
-            for (int k = 0; k < n_ids; ++k) {
-                int slot = -1;
-                for (int sl = 0; sl < S; ++sl)
-                    if (state[sl] != kSrcFree && idv[sl] == ids[k]) { slot = sl; break; }
-                if (slot < 0) return fail(c, LPF_EINVAL, "source id not held");
-                ents.push_back({ci, slot, state[slot] == kSrcEnded ? tend[slot] : c->t_last, ids[k]});
-            }
-        }
-    }
-    // ended episodes are reported in (context, id) order
-    std::stable_sort(ents.begin(), ents.end(), [&](const Ent& a, const Ent& b) {
-        return a.ctx != b.ctx ? a.ctx < b.ctx : (ids ? false : a.id < b.id);
-    });
-    const int N = (int)ents.size();
-    *n_out = std::min(N, cap);
-    if (N == 0) return LPF_OK;
     const int mb = model_max_batch(m);
     float* win = model_window_buffer(m);
     float* dmu = model_mu_buffer(m);
     float* dL = model_L_buffer(m);
+    // Entries: per context a run of windows gathered on the device.  With
+    // ids == NULL the ended list of each context (slot order) is used and the
+    // rows are reordered by id on the host afterwards.
+    struct Run { int ctx; int n; std::vector<int32_t> id; };
+    std::vector<Run> runs;
+    int N = 0;
+    for (int ci = 0; ci < n_ctx; ++ci) {
+        lpf_ctx* c = ctxs[ci];
+        Run r{ci, 0, {}};
+        if (!ids) {
+            DevStatus st;
+            LPF_HIP(c, hipMemcpyAsync(&st, c->buf.status, sizeof(st), hipMemcpyDeviceToHost, c->stream), "status");
+            LPF_HIP(c, hipStreamSynchronize(c->stream), "infer sync");
+            r.n = st.n_ended;
+            if (r.n == 0) continue;
+            std::vector<lpf_source> ev(r.n);
+            LPF_HIP(c, hipMemcpyAsync(ev.data(), c->buf.events + st.n_new, r.n * sizeof(lpf_source),
+                                      hipMemcpyDeviceToHost, c->stream), "events");
+            LPF_HIP(c, launch_ended_ends(c, c->buf.infer_slots, c->buf.infer_tend), "ended list");
+            LPF_HIP(c, hipStreamSynchronize(c->stream), "infer sync");
+            r.id.resize(r.n);
+            for (int k = 0; k < r.n; ++k) r.id[k] = ev[k].id;
+        } else {
+            const int S = c->cfg.max_sources;
+            std::vector<int32_t> idv(S), state(S);
+            std::vector<int64_t> tend(S);
+            LPF_HIP(c, hipStreamSynchronize(c->stream), "infer sync");
+            LPF_HIP(c, hipMemcpy(idv.data(), c->buf.src_id, S * sizeof(int32_t), hipMemcpyDeviceToHost), "ids");
+            LPF_HIP(c, hipMemcpy(state.data(), c->buf.src_state, S * sizeof(int32_t), hipMemcpyDeviceToHost), "state");
+            LPF_HIP(c, hipMemcpy(tend.data(), c->buf.src_tend, S * sizeof(int64_t), hipMemcpyDeviceToHost), "tend");
+            std::vector<int32_t> sl(n_ids);
+            std::vector<int64_t> te(n_ids);
+            for (int k = 0; k < n_ids; ++k) {
+                int slot = -1;
+                for (int q = 0; q < S; ++q)
+                    if (state[q] != kSrcFree && idv[q] == ids[k]) { slot = q; break; }
+                if (slot < 0) return fail(c, LPF_EINVAL, "source id not held");
+                sl[k] = slot;
+                te[k] = state[slot] == kSrcEnded ? tend[slot] : c->t_last;
+            }
+            if (n_ids > 0) {
+                LPF_HIP(c, hipMemcpy(c->buf.infer_slots, sl.data(), n_ids * sizeof(int32_t), hipMemcpyHostToDevice), "slots H2D");
+                LPF_HIP(c, hipMemcpy(c->buf.infer_tend, te.data(), n_ids * sizeof(int64_t), hipMemcpyHostToDevice), "tend H2D");
+            }
+            r.n = n_ids;
+            r.id.assign(ids, ids + n_ids);
+        }
+        if (r.n > 0) {
+            N += r.n;
+            runs.push_back(std::move(r));
+        }
+    }
+    // rows in (context, id) order for the ended episodes, caller order for ids
+    std::vector<int> row_ctx, row_id, row_src;  // row_src: index in gathered order
+    {
+        int base = 0;
+        for (const auto& r : runs) {
+            std::vector<int> perm(r.n);
+            for (int k = 0; k < r.n; ++k) perm[k] = k;
+            if (!ids) std::sort(perm.begin(), perm.end(), [&](int x, int y) { return r.id[x] < r.id[y]; });
+            for (int k : perm) {
+                row_ctx.push_back(r.ctx);
+                row_id.push_back(r.id[k]);
+                row_src.push_back(base + k);
+            }
+            base += r.n;
+        }
+    }
+    *n_out = std::min(N, cap);
+    if (N == 0) return LPF_OK;
     std::vector<float> hmu((size_t)N * 4), hL((size_t)N * 10);
-    for (int i0 = 0; i0 < N; i0 += mb) {
-        const int cnt = std::min(mb, N - i0);
-        // windows per context run: upload (slot, t_end) and gather
-        int j = i0;
-        while (j < i0 + cnt) {
-            int k = j;
-            while (k < i0 + cnt && ents[k].ctx == ents[j].ctx) ++k;
-            lpf_ctx* c = ctxs[ents[j].ctx];
-            std::vector<int32_t> sl(k - j);
-            std::vector<int64_t> te(k - j);
-            for (int q = j; q < k; ++q) { sl[q - j] = ents[q].slot; te[q - j] = ents[q].tend; }
-            LPF_HIP(c, hipMemcpy(c->buf.infer_slots, sl.data(), sl.size() * sizeof(int32_t), hipMemcpyHostToDevice), "slots H2D");
-            LPF_HIP(c, hipMemcpy(c->buf.infer_tend, te.data(), te.size() * sizeof(int64_t), hipMemcpyHostToDevice), "tend H2D");
-            LPF_HIP(c, launch_windows_gather(c, k - j, c->buf.infer_slots, c->buf.infer_tend,
-                                             win + (size_t)(j - i0) * kGridRows * kRing), "windows");
-            LPF_HIP(c, hipStreamSynchronize(c->stream), "windows sync");
-            j = k;
+    // process the gathered rows in chunks of the model's batch
+    int g = 0;  // gathered index of the chunk start
+    size_t run_i = 0;
+    int run_off = 0;
+    while (g < N) {
+        const int cnt = std::min(mb, N - g);
+        int filled = 0;
+        while (filled < cnt) {
+            const Run& r = runs[run_i];
+            const int take = std::min(cnt - filled, r.n - run_off);
+            lpf_ctx* c = ctxs[r.ctx];
+            LPF_HIP(c, launch_windows_gather(c, take, c->buf.infer_slots + run_off, c->buf.infer_tend + run_off,
+                                             win + (size_t)filled * kGridRows * kRing), "windows");
+            if (c->stream != s) LPF_HIP(c, hipStreamSynchronize(c->stream), "windows sync");
+            filled += take;
+            run_off += take;
+            if (run_off == r.n) { ++run_i; run_off = 0; }
         }
         {
             StageTimer tm(c0, 6);
             LPF_HIP(c0, cnn_forward(m, win, cnt, dmu, dL, s), "cnn");
         }
-        LPF_HIP(c0, hipMemcpyAsync(hmu.data() + (size_t)i0 * 4, dmu, cnt * 4 * sizeof(float), hipMemcpyDeviceToHost, s), "mu D2H");
-        LPF_HIP(c0, hipMemcpyAsync(hL.data() + (size_t)i0 * 10, dL, cnt * 10 * sizeof(float), hipMemcpyDeviceToHost, s), "L D2H");
+        LPF_HIP(c0, hipMemcpyAsync(hmu.data() + (size_t)g * 4, dmu, cnt * 4 * sizeof(float), hipMemcpyDeviceToHost, s), "mu D2H");
+        LPF_HIP(c0, hipMemcpyAsync(hL.data() + (size_t)g * 10, dL, cnt * 10 * sizeof(float), hipMemcpyDeviceToHost, s), "L D2H");
         LPF_HIP(c0, hipStreamSynchronize(s), "infer sync");
+        g += cnt;
     }
     const int nw = *n_out;
-    if (mu_out) std::memcpy(mu_out, hmu.data(), (size_t)nw * 4 * sizeof(float));
-    if (L_out) std::memcpy(L_out, hL.data(), (size_t)nw * 10 * sizeof(float));
-    if (src_out)
-        for (int i = 0; i < nw; ++i) { src_out[2 * i] = ents[i].ctx; src_out[2 * i + 1] = ents[i].id; }
+    for (int i = 0; i < nw; ++i) {
+        const int k = row_src[i];
+        if (mu_out) std::memcpy(mu_out + (size_t)i * 4, hmu.data() + (size_t)k * 4, 4 * sizeof(float));
+        if (L_out) std::memcpy(L_out + (size_t)i * 10, hL.data() + (size_t)k * 10, 10 * sizeof(float));
+        if (src_out) { src_out[2 * i] = row_ctx[i]; src_out[2 * i + 1] = row_id[i]; }
+    }
     return LPF_OK;
 }
 

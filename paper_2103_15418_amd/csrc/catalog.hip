@@ -23,6 +23,8 @@ namespace lpf {
 namespace {
 
 constexpr int kCatThreads = 1024;
+constexpr int kLdsPeaks = (kCatMaxPeaks * 2) / (kNbr + 1);  // neighbour lists that fit the key area
+constexpr int kLdsKept = 512;                                // kept peaks with LDS candidate lists
 
 struct CatArgs {
     int B, peak_cap, max_sources, n_mon;
@@ -34,7 +36,8 @@ struct CatArgs {
     int32_t* order;     // [kCatMaxPeaks] bij-rank by visiting position
     int32_t* nbr;       // [kCatMaxPeaks][kNbr + 1]
     int32_t* cand;      // [kCatMaxPeaks][kCand + 1]
-    int32_t* kept;      // [kCatMaxPeaks] kept peaks (bij rank) in visiting order
+    int32_t* kept;      // [kCatMaxPeaks] kept peaks (visiting positions) in visiting order
+    int32_t* dec;       // [kCatMaxPeaks] association decisions (large steps)
     int32_t* free_list; // [max_sources]
     int32_t* src_id;
     int32_t* src_row;
@@ -75,6 +78,36 @@ __device__ void bitonic_sort(uint64_t* k, int n) {
     }
 }
 
+__device__ inline uint64_t shfl_xor_u64(uint64_t x, int m) {
+    const int lo = __shfl_xor((int)(uint32_t)x, m, 64);
+    const int hi = __shfl_xor((int)(uint32_t)(x >> 32), m, 64);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// Ascending sort of n (a power of two) keys; every thread of the block calls
+// it.  Up to 64 keys are sorted in the registers of wave 0 (shuffle network,
+// no block barriers); larger lists use the block-wide network in LDS.
+__device__ void sort_keys(uint64_t* k, int n) {
+    if (n <= 64) {
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            uint64_t x = lane < n ? k[lane] : ~0ull;
+            for (int size = 2; size <= 64; size <<= 1) {
+                for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                    const uint64_t y = shfl_xor_u64(x, stride);
+                    const bool up = (lane & size) == 0;
+                    const bool lower = (lane & stride) == 0;
+                    x = (lower == up) ? (x < y ? x : y) : (x < y ? y : x);
+                }
+            }
+            if (lane < n) k[lane] = x;
+        }
+        __syncthreads();
+    } else {
+        bitonic_sort(k, n);
+    }
+}
+
 // Exclusive block scan of one int per thread; returns the prefix, *total = sum.
 __device__ int block_scan(int v, int* s_tmp, int* total) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -111,10 +144,14 @@ __device__ inline float dist2(int a, int b) {
 }
 
 __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
-    __shared__ uint64_t s_keys[kCatMaxPeaks];        // 64 KB: sort keys, later live lists
+    __shared__ uint64_t s_keys[kCatMaxPeaks];        // 64 KB: sort keys / neighbour lists / live lists
     __shared__ int32_t s_pos[kCatMaxPeaks];          // 32 KB: positions in visiting order
     __shared__ uint8_t s_flag[kCatMaxPeaks];         //  8 KB: kept flags
     __shared__ uint32_t s_taken[kMaxSources / 32];   //  8 KB: taken bitmap
+    __shared__ int32_t s_cand[kLdsKept * (kCand + 1)];  // 18 KB: candidate lists
+    __shared__ int32_t s_dec[kLdsKept];              //  2 KB: association decisions
+    __shared__ uint64_t s_wkey[(kCatThreads / 64) * kCand];  // per-wave candidate keys
+    __shared__ int32_t s_wslot[(kCatThreads / 64) * kCand];
     __shared__ int s_off[kMaxB + 1];
     __shared__ int s_tmp[kCatThreads / 64 + 1];
     __shared__ int s_P, s_K, s_nlive, s_held, s_nfree, s_nnew, s_drop, s_next;
@@ -125,16 +162,29 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
     const int64_t t = a.t;
 
     // ---- 0. release previous ended records; end episodes left over by a gap
-    for (int s = tid; s < S; s += kCatThreads) {
-        int st = a.src_state[s];
-        if (st == kSrcEnded) {
-            st = kSrcFree;
-        } else if (st == kSrcLive && t - a.src_tlast[s] > a.n_mon) {
-            st = kSrcEnded;
-            a.src_tend[s] = a.src_tlast[s] + a.n_mon;
+    for (int s0 = tid; s0 < S; s0 += 8 * kCatThreads) {
+        int st[8];
+        int64_t tl[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int s = s0 + i * kCatThreads;
+            st[i] = s < S ? a.src_state[s] : kSrcFree;
+            tl[i] = s < S ? a.src_tlast[s] : 0;
         }
-        a.src_state[s] = st;
-        a.src_new[s] = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int s = s0 + i * kCatThreads;
+            if (s >= S) continue;
+            int v = st[i];
+            if (v == kSrcEnded) {
+                v = kSrcFree;
+            } else if (v == kSrcLive && t - tl[i] > a.n_mon) {
+                v = kSrcEnded;
+                a.src_tend[s] = tl[i] + a.n_mon;
+            }
+            a.src_state[s] = v;
+            a.src_new[s] = 0;
+        }
     }
     for (int w = tid; w < (S + 31) / 32; w += kCatThreads) s_taken[w] = 0u;
     if (tid == 0) {
@@ -169,7 +219,7 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
         }
     }
     __syncthreads();
-    if (P > 1) bitonic_sort(s_keys, Ppad);
+    if (P > 1) sort_keys(s_keys, Ppad);
     for (int n = tid; n < P; n += kCatThreads) {
         const uint32_t ref = (uint32_t)(s_keys[n] & 0xffffffffu);
         a.peak_sorted[n] = a.peak_raw[ref];
@@ -186,7 +236,7 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
         }
     }
     __syncthreads();
-    if (P > 1) bitonic_sort(s_keys, Ppad);
+    if (P > 1) sort_keys(s_keys, Ppad);
     for (int q = tid; q < P; q += kCatThreads) {
         const int n = (int)(s_keys[q] & 0xffffffffu);
         a.order[q] = n;
@@ -195,10 +245,12 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
     __syncthreads();
 
     // ---- 3. duplicate removal: neighbour lists, then greedy resolution.
-    // nbr[q] = {count, up to kNbr earlier-visited peaks within dup_radius}.
+    // nbr[q] = {count, up to kNbr earlier-visited peaks within dup_radius};
+    // held in LDS (the sort-key area) for steps with at most kLdsPeaks peaks.
+    int32_t* nbr = P <= kLdsPeaks ? reinterpret_cast<int32_t*>(s_keys) : a.nbr;
     for (int q = tid; q < P; q += kCatThreads) {
         const int pq = s_pos[q];
-        int32_t* nb = a.nbr + (size_t)q * (kNbr + 1);
+        int32_t* nb = nbr + (size_t)q * (kNbr + 1);
         int cnt = 0;
         for (int r = 0; r < q; ++r) {
             if (dist2(pq, s_pos[r]) <= a.r_dup2) {
@@ -212,56 +264,79 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
     if (tid == 0) {
         int K = 0;
         for (int q = 0; q < P; ++q) {
-            const int32_t* nb = a.nbr + (size_t)q * (kNbr + 1);
+            const int32_t* nb = nbr + (size_t)q * (kNbr + 1);
             const int cnt = nb[0];
             bool keep = true;
-            if (cnt > kNbr) {  // long list: test against every kept peak so far
-                for (int r = 0; r < K && keep; ++r)
-                    if (dist2(s_pos[q], s_pos[a.kept[r]]) <= a.r_dup2) keep = false;
+            if (cnt > kNbr) {  // long list: test every earlier peak that was kept
+                for (int r = 0; r < q && keep; ++r)
+                    if (s_flag[r] && dist2(s_pos[q], s_pos[r]) <= a.r_dup2) keep = false;
             } else {
                 for (int r = 0; r < cnt && keep; ++r)
                     if (s_flag[nb[1 + r]]) keep = false;
             }
             s_flag[q] = keep ? 1 : 0;
-            if (keep) a.kept[K++] = q;
+            K += keep;
         }
         s_K = K;
     }
     __syncthreads();
     const int K = s_K;
+    {   // kept list in visiting order (parallel compaction)
+        const int per = (P + kCatThreads - 1) / kCatThreads;
+        const int q0 = tid * per, q1 = min(P, q0 + per);
+        int nk = 0;
+        for (int q = q0; q < q1; ++q) nk += s_flag[q];
+        int tot;
+        int ok = block_scan(nk, s_tmp, &tot);
+        for (int q = q0; q < q1; ++q)
+            if (s_flag[q]) a.kept[ok++] = q;
+    }
+    __syncthreads();
 
     // ---- 4a. live sources (compacted, slot order) and the free list
     int32_t* s_live = reinterpret_cast<int32_t*>(s_keys);        // [S <= 8192 fast path]
     int32_t* s_lpos = s_live + kCatMaxPeaks;
     {
-        const int per = (S + kCatThreads - 1) / kCatThreads;
-        const int s0 = tid * per, s1 = min(S, s0 + per);
-        int nl = 0, nf = 0, nh = 0;
-        for (int s = s0; s < s1; ++s) {
-            const int st = a.src_state[s];
-            nl += st == kSrcLive;
-            nf += st == kSrcFree;
-            nh += st != kSrcFree;
-        }
-        int tot;
-        int ol = block_scan(nl, s_tmp, &tot);
-        if (tid == 0) s_nlive = tot;
-        int of = block_scan(nf, s_tmp, &tot);
-        if (tid == 0) s_nfree = tot;
-        int oh = block_scan(nh, s_tmp, &tot);
-        (void)oh;
-        if (tid == 0) s_held = tot;
-        for (int s = s0; s < s1; ++s) {
-            const int st = a.src_state[s];
-            if (st == kSrcLive) {
-                if (ol < kCatMaxPeaks) {
-                    s_live[ol] = s;
-                    s_lpos[ol] = pack_pos(a.src_row[s], a.src_col[s]);
-                }
-                ++ol;
-            } else if (st == kSrcFree) {
-                a.free_list[of++] = s;
+        // rounds of 8 consecutive slots per thread: loads are issued together and
+        // the scan keeps slot order
+        int base_l = 0, base_f = 0, base_h = 0;
+        for (int base = 0; base < S; base += 8 * kCatThreads) {
+            const int s0 = base + tid * 8;
+            int st[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) st[i] = s0 + i < S ? a.src_state[s0 + i] : -1;
+            int nl = 0, nf = 0, nh = 0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                nl += st[i] == kSrcLive;
+                nf += st[i] == kSrcFree;
+                nh += st[i] == kSrcLive || st[i] == kSrcEnded;
             }
+            int tl, tf, th;
+            int ol = base_l + block_scan(nl, s_tmp, &tl);
+            int of = base_f + block_scan(nf, s_tmp, &tf);
+            block_scan(nh, s_tmp, &th);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int sl = s0 + i;
+                if (st[i] == kSrcLive) {
+                    if (ol < kCatMaxPeaks) {
+                        s_live[ol] = sl;
+                        s_lpos[ol] = pack_pos(a.src_row[sl], a.src_col[sl]);
+                    }
+                    ++ol;
+                } else if (st[i] == kSrcFree) {
+                    a.free_list[of++] = sl;
+                }
+            }
+            base_l += tl;
+            base_f += tf;
+            base_h += th;
+        }
+        if (tid == 0) {
+            s_nlive = base_l;
+            s_nfree = base_f;
+            s_held = base_h;
         }
     }
     __syncthreads();
@@ -270,50 +345,72 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
 
     // ---- 4b. association candidates of each kept peak, sorted by (d^2, id).
     // cand[kq] = {count or -1 (too many / table not staged), up to kCand slots}.
-    for (int kq = tid; kq < K; kq += kCatThreads) {
-        int32_t* out = a.cand + (size_t)kq * (kCand + 1);
-        if (!live_in_lds) {
-            out[0] = -1;
-            continue;
-        }
-        const int pq = s_pos[a.kept[kq]];
-        float cd[kCand];
-        int cid[kCand], cs[kCand];
-        int cnt = 0;
-        for (int l = 0; l < L; ++l) {
-            const float d = dist2(pq, s_lpos[l]);
-            if (d > a.r_assoc2) continue;
-            if (cnt == kCand) {
-                cnt = kCand + 1;
-                break;
+    // One wave per kept peak scans the live list 64 sources at a time.
+    int32_t* cand = K <= kLdsKept ? s_cand : a.cand;
+    int32_t* dec = K <= kLdsKept ? s_dec : a.dec;
+    {
+        const int wave = tid >> 6, lane = tid & 63;
+        uint64_t* wkey = s_wkey + wave * kCand;
+        int32_t* wslot = s_wslot + wave * kCand;
+        for (int kq = wave; kq < K; kq += kCatThreads / 64) {
+            int32_t* out = cand + (size_t)kq * (kCand + 1);
+            if (!live_in_lds) {
+                if (lane == 0) out[0] = -1;
+                continue;
             }
-            const int s = s_live[l];
-            const int id = a.src_id[s];
-            int m = cnt++;
-            while (m > 0 && (cd[m - 1] > d || (cd[m - 1] == d && cid[m - 1] > id))) {
-                cd[m] = cd[m - 1];
-                cid[m] = cid[m - 1];
-                cs[m] = cs[m - 1];
-                --m;
+            const int pq = s_pos[a.kept[kq]];
+            int cnt = 0;
+            for (int l0 = 0; l0 < L && cnt <= kCand; l0 += 64) {
+                const int l = l0 + lane;
+                const bool hit = l < L && dist2(pq, s_lpos[l]) <= a.r_assoc2;
+                const uint64_t bal = __ballot(hit);
+                const int nh = __popcll(bal);
+                if (cnt + nh > kCand) {
+                    cnt = kCand + 1;
+                    break;
+                }
+                if (hit) {
+                    const int at = cnt + __popcll(bal & ((1ull << lane) - 1ull));
+                    const int s = s_live[l];
+                    const uint32_t d2 = (uint32_t)dist2(pq, s_lpos[l]);
+                    wkey[at] = ((uint64_t)d2 << 32) | (uint32_t)a.src_id[s];
+                    wslot[at] = s;
+                }
+                cnt += nh;
             }
-            cd[m] = d;
-            cid[m] = id;
-            cs[m] = s;
-        }
-        if (cnt > kCand) {
-            out[0] = -1;
-        } else {
-            out[0] = cnt;
-            for (int m = 0; m < cnt; ++m) out[1 + m] = cs[m];
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) {
+                if (cnt > kCand) {
+                    out[0] = -1;
+                } else {
+                    // insertion sort of <= kCand (d^2, id) keys
+                    for (int i = 1; i < cnt; ++i) {
+                        const uint64_t kk = wkey[i];
+                        const int ss = wslot[i];
+                        int j = i - 1;
+                        while (j >= 0 && wkey[j] > kk) {
+                            wkey[j + 1] = wkey[j];
+                            wslot[j + 1] = wslot[j];
+                            --j;
+                        }
+                        wkey[j + 1] = kk;
+                        wslot[j + 1] = ss;
+                    }
+                    out[0] = cnt;
+                    for (int m = 0; m < cnt; ++m) out[1 + m] = wslot[m];
+                }
+            }
         }
     }
     __syncthreads();
 
-    // ---- 4c. greedy resolution (visiting order)
+    // ---- 4c. greedy resolution in visiting order (one lane, LDS data only):
+    // dec[kq] = matched slot (>= 0), -1 - r for the r-th new source, or
+    // INT32_MIN for a peak dropped at capacity.
     if (tid == 0) {
-        int held = s_held, nnew = 0, drop = 0, next = s_next;
+        int held = s_held, nnew = 0, drop = 0;
         for (int kq = 0; kq < K; ++kq) {
-            const int32_t* cl = a.cand + (size_t)kq * (kCand + 1);
+            const int32_t* cl = cand + (size_t)kq * (kCand + 1);
             int match = -1;
             if (cl[0] < 0) {
                 // exact scan of the whole table (sources opened this step are taken)
@@ -321,7 +418,7 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
                 float bd = 0.0f;
                 int bid = 0;
                 for (int s = 0; s < S; ++s) {
-                    if (a.src_state[s] != kSrcLive) continue;
+                    if (a.src_state[s] != kSrcLive || a.src_new[s]) continue;
                     if ((s_taken[s >> 5] >> (s & 31)) & 1u) continue;
                     const float d = dist2(pq, pack_pos(a.src_row[s], a.src_col[s]));
                     if (d > a.r_assoc2) continue;
@@ -343,17 +440,31 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
             }
             if (match >= 0) {
                 s_taken[match >> 5] |= 1u << (match & 31);
-                a.src_tlast[match] = t;
-                continue;
-            }
-            if (held >= S || nnew >= s_nfree) {
+                dec[kq] = match;
+            } else if (held >= S || nnew >= s_nfree) {
                 ++drop;
-                continue;
+                dec[kq] = INT32_MIN;
+            } else {
+                ++held;
+                dec[kq] = -1 - nnew;
+                ++nnew;
             }
-            const int s = a.free_list[nnew++];
-            ++held;
+        }
+        s_nnew = nnew;
+        s_drop = drop;
+        s_held = held;
+    }
+    __syncthreads();
+    // ---- 4d. apply the decisions (parallel)
+    for (int kq = tid; kq < K; kq += kCatThreads) {
+        const int dq = dec[kq];
+        if (dq >= 0) {
+            a.src_tlast[dq] = t;
+        } else if (dq != INT32_MIN) {
+            const int r = -1 - dq;
+            const int s = a.free_list[r];
             const int n = a.order[a.kept[kq]];
-            a.src_id[s] = next++;
+            a.src_id[s] = s_next + r;
             a.src_row[s] = a.peak_sorted[n].row;
             a.src_col[s] = a.peak_sorted[n].col;
             a.src_state[s] = kSrcLive;
@@ -361,70 +472,82 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
             a.src_tlast[s] = t;
             a.src_tend[s] = -1;
             a.src_new[s] = 1;
-            s_taken[s >> 5] |= 1u << (s & 31);  // a new source cannot be matched again
         }
-        s_nnew = nnew;
-        s_drop = drop;
-        s_next = next;
-        s_held = held;
     }
     __syncthreads();
+    if (tid == 0) s_next += s_nnew;
+    __syncthreads();
 
-    // ---- 5. end of monitoring, lists, events
+    // ---- 5. end of monitoring, lists, events (rounds of 8 slots per thread)
     {
-        const int per = (S + kCatThreads - 1) / kCatThreads;
-        const int s0 = tid * per, s1 = min(S, s0 + per);
-        int nm = 0, nn = 0, ne = 0;
-        for (int s = s0; s < s1; ++s) {
-            int st = a.src_state[s];
-            if (st == kSrcLive) {
-                ++nm;
-                if (a.src_new[s]) ++nn;
-                if (t - a.src_tlast[s] == a.n_mon) {
-                    st = kSrcEnded;
-                    a.src_state[s] = st;
-                    a.src_tend[s] = t;
+        int base_m = 0, base_n = 0, base_e = 0;
+        int tn_all = s_nnew;  // new events come first in the event list
+        for (int base = 0; base < S; base += 8 * kCatThreads) {
+            const int s0 = base + tid * 8;
+            int st[8], nw[8];
+            int64_t tl[8], te8[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const bool in = s0 + i < S;
+                st[i] = in ? a.src_state[s0 + i] : -1;
+                nw[i] = in ? a.src_new[s0 + i] : 0;
+                tl[i] = in ? a.src_tlast[s0 + i] : 0;
+                te8[i] = in ? a.src_tend[s0 + i] : 0;
+            }
+            int nm = 0, nn = 0, ne = 0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int sl = s0 + i;
+                if (st[i] == kSrcLive) {
+                    ++nm;
+                    nn += nw[i] != 0;
+                    if (t - tl[i] == a.n_mon) {
+                        st[i] = kSrcEnded;
+                        te8[i] = t;
+                        a.src_state[sl] = kSrcEnded;
+                        a.src_tend[sl] = t;
+                    }
+                }
+                ne += st[i] == kSrcEnded;
+                if (nw[i])
+                    for (int r = 0; r < kRing; ++r) a.ring_t[(size_t)sl * kRing + r] = INT64_MIN;
+            }
+            int tm, tn, te;
+            int om = base_m + block_scan(nm, s_tmp, &tm);
+            int on = base_n + block_scan(nn, s_tmp, &tn);
+            int oe = base_e + block_scan(ne, s_tmp, &te);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int sl = s0 + i;
+                if (st[i] < 0) continue;
+                const bool measured = st[i] == kSrcLive || (st[i] == kSrcEnded && te8[i] == t);
+                if (measured) a.list_measured[om++] = sl;
+                if (nw[i] || st[i] == kSrcEnded) {
+                    lpf_source ev;
+                    ev.id = a.src_id[sl];
+                    ev.row = a.src_row[sl];
+                    ev.col = a.src_col[sl];
+                    ev.t_first = a.src_tfirst[sl];
+                    ev.t_last_det = tl[i];
+                    ev.t_end = te8[i];
+                    if (nw[i]) {
+                        a.list_new[on] = sl;
+                        ev.event = LPF_EVENT_NEW;
+                        a.events[on++] = ev;
+                    }
+                    if (st[i] == kSrcEnded) {
+                        a.list_ended[oe] = sl;
+                        ev.event = LPF_EVENT_ENDED;
+                        a.events[tn_all + oe] = ev;
+                        ++oe;
+                    }
                 }
             }
-            if (st == kSrcEnded) ++ne;
-            if (a.src_new[s])
-                for (int r = 0; r < kRing; ++r) a.ring_t[(size_t)s * kRing + r] = INT64_MIN;
+            base_m += tm;
+            base_n += tn;
+            base_e += te;
         }
-        int tm, tn, te;
-        int om = block_scan(nm, s_tmp, &tm);
-        int on = block_scan(nn, s_tmp, &tn);
-        int oe = block_scan(ne, s_tmp, &te);
-        for (int s = s0; s < s1; ++s) {
-            const int st = a.src_state[s];
-            const bool measured = st == kSrcLive || (st == kSrcEnded && a.src_tend[s] == t);
-            if (measured) a.list_measured[om++] = s;
-            if (a.src_new[s]) {
-                a.list_new[on] = s;
-                lpf_source ev;
-                ev.id = a.src_id[s];
-                ev.row = a.src_row[s];
-                ev.col = a.src_col[s];
-                ev.event = LPF_EVENT_NEW;
-                ev.t_first = a.src_tfirst[s];
-                ev.t_last_det = a.src_tlast[s];
-                ev.t_end = a.src_tend[s];
-                a.events[on] = ev;
-                ++on;
-            }
-            if (st == kSrcEnded) {
-                a.list_ended[oe] = s;
-                lpf_source ev;
-                ev.id = a.src_id[s];
-                ev.row = a.src_row[s];
-                ev.col = a.src_col[s];
-                ev.event = LPF_EVENT_ENDED;
-                ev.t_first = a.src_tfirst[s];
-                ev.t_last_det = a.src_tlast[s];
-                ev.t_end = a.src_tend[s];
-                a.events[tn + oe] = ev;
-                ++oe;
-            }
-        }
+        const int tm = base_m, tn = base_n, te = base_e;
         if (tid == 0) {
             DevStatus* st = a.status;
             st->n_peaks = P;
@@ -473,6 +596,7 @@ hipError_t launch_catalog(lpf_ctx* c, int64_t t) {
     a.nbr = c->buf.cat_nbr;
     a.cand = c->buf.cat_cand;
     a.kept = c->buf.cat_kept;
+    a.dec = c->buf.cat_dec;
     a.free_list = c->buf.free_list;
     a.src_id = c->buf.src_id;
     a.src_row = c->buf.src_row;

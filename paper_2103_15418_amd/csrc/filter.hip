@@ -50,6 +50,8 @@ struct FiltArgs {
     const uint8_t* Y;    // [B][H][W] clip mask
     const float* den;    // [B][H][W]
     const float* inv_den;  // [H][W]
+    const uint32_t* mbits; // [H][mwords] sky mask, bit j of word w = column 32 w + j (null = all)
+    int mwords;
     float* out;          // output plane(s)
     float* S_out;        // optional spread plane
     uint8_t* Y_out;      // optional clip plane
@@ -163,6 +165,61 @@ __device__ inline bool is_peak(const FiltArgs& a, size_t bo, int y, int x, float
     return true;
 }
 
+// Per-output epilogue: normalisation, threshold, peak test, stores.
+template <int OUT>
+__device__ inline void epilogue(const FiltArgs& a, int b, size_t bo, int gy, int gx, float v) {
+    const size_t p = (size_t)gy * a.W + gx;
+    if (OUT == OUT_INV_DEN) {
+        a.out[p] = v > 0.0f ? 1.0f / v : 0.0f;
+    } else if (OUT == OUT_RAW) {
+        a.out[bo + p] = v;
+    } else if (OUT == OUT_C_STATIC) {
+        a.out[bo + p] = v * a.inv_den[p];
+    } else if (OUT == OUT_C_DYN) {
+        const float dn = a.den[bo + p];
+        a.out[bo + p] = dn > 0.0f ? v / dn : 0.0f;
+    } else {
+        float s, dpos;
+        if (OUT == OUT_S_PEAKS) {
+            const float id = a.inv_den[p];
+            s = v * id;
+            dpos = id;
+        } else {
+            const float dn = a.den[bo + p];
+            s = dn > 0.0f ? v / dn : 0.0f;
+            dpos = dn;
+        }
+        const float cv = a.C[bo + p];
+        const float xv = a.X[bo + p];
+        const bool m = a.M ? a.M[p] != 0 : true;
+        const bool y = m && dpos > 0.0f && xv > cv + a.kappa * sqrtf(s);
+        if (a.S_out) a.S_out[bo + p] = s;
+        if (OUT == OUT_S_PEAKS) {
+            if (a.Y_out) a.Y_out[bo + p] = y ? 1 : 0;
+            if (a.Y_out2) a.Y_out2[bo + p] = y ? 1 : 0;
+            if (y && is_peak(a, bo, gy, gx, xv)) {
+                const int idx = atomicAdd(&a.peak_cnt[b], 1);
+                if (idx < a.peak_cap) {
+                    PeakRec rec;
+                    rec.band = b;
+                    rec.row = gy;
+                    rec.col = gx;
+                    rec.x = xv;
+                    rec.c = cv;
+                    rec.s = s;
+                    rec.sig = (xv - cv) / sqrtf(s);
+                    a.peak_raw[(size_t)b * a.peak_cap + idx] = rec;
+                }
+            }
+            if (y && a.changed) a.changed[b] = 1;
+        } else {  // OUT_S_DYN: Y_i = Y_{i-1} or y, into the other plane
+            const uint8_t old = a.Y[bo + p];
+            a.Y_out[bo + p] = (y || old) ? 1 : 0;
+            if (y && !old) a.changed[b] = 1;
+        }
+    }
+}
+
 template <int K, int IN, int OUT>
 __global__ __launch_bounds__(kFiltThreads) void k_filter(FiltArgs a, Taps tp) {
     extern __shared__ float lds[];
@@ -221,57 +278,144 @@ __global__ __launch_bounds__(kFiltThreads) void k_filter(FiltArgs a, Taps tp) {
     for (int q = 0; q < R; ++q) {
         const int gy = y0 + rb * R + q;
         if (gy >= a.H) break;
-        const size_t p = (size_t)gy * a.W + gx;
-        const float v = acc[q];
-        if (OUT == OUT_INV_DEN) {
-            a.out[p] = v > 0.0f ? 1.0f / v : 0.0f;
-        } else if (OUT == OUT_RAW) {
-            a.out[bo + p] = v;
-        } else if (OUT == OUT_C_STATIC) {
-            a.out[bo + p] = v * a.inv_den[p];
-        } else if (OUT == OUT_C_DYN) {
-            const float dn = a.den[bo + p];
-            a.out[bo + p] = dn > 0.0f ? v / dn : 0.0f;
+        epilogue<OUT>(a, b, bo, gy, gx, acc[q]);
+    }
+}
+
+// Fast path (compile-time half-width K, W % 4 == 0): 64-column x 128-row
+// tiles, 512 threads.  The row pass reads its 16 + 2K inputs straight from
+// global memory as aligned float4 groups into registers (no staging), only
+// the row results go through LDS ((128 + 2K) x 65 floats), so three
+// workgroups fit on a CU.
+constexpr int kTH2 = 128;
+constexpr int kThreads2 = 512;
+
+template <int IN>
+__device__ inline void load_group(const FiltArgs& a, size_t bo, size_t rowoff, int gx, uint32_t mb4,
+                                  float* e) {
+    // four consecutive inputs at columns gx..gx+3 (all inside the image);
+    // mb4: their sky-mask bits
+    const size_t p = rowoff + gx;
+    float m0 = (float)(mb4 & 1u), m1 = (float)((mb4 >> 1) & 1u), m2 = (float)((mb4 >> 2) & 1u),
+          m3 = (float)((mb4 >> 3) & 1u);
+    if (IN == IN_M) {
+        e[0] = m0; e[1] = m1; e[2] = m2; e[3] = m3;
+        return;
+    }
+    if (IN == IN_W || IN == IN_WX || IN == IN_WE) {
+        const uchar4 yk = *reinterpret_cast<const uchar4*>(a.Y + bo + p);
+        if (yk.x) m0 = 0.0f;
+        if (yk.y) m1 = 0.0f;
+        if (yk.z) m2 = 0.0f;
+        if (yk.w) m3 = 0.0f;
+    }
+    if (IN == IN_W) {
+        e[0] = m0; e[1] = m1; e[2] = m2; e[3] = m3;
+        return;
+    }
+    const float4 x = *reinterpret_cast<const float4*>(a.X + bo + p);
+    if (IN == IN_MX || IN == IN_WX) {
+        e[0] = m0 * x.x; e[1] = m1 * x.y; e[2] = m2 * x.z; e[3] = m3 * x.w;
+        return;
+    }
+    const float4 cc = *reinterpret_cast<const float4*>(a.C + bo + p);
+    const float r0 = x.x - cc.x, r1 = x.y - cc.y, r2 = x.z - cc.z, r3 = x.w - cc.w;
+    e[0] = m0 * r0 * r0; e[1] = m1 * r1 * r1; e[2] = m2 * r2 * r2; e[3] = m3 * r3 * r3;
+}
+
+template <int K, int IN, int OUT>
+__global__ __launch_bounds__(kThreads2) void k_filter_fast(FiltArgs a, Taps tp) {
+    constexpr int ROWS = kTH2 + 2 * K;        // input rows per tile
+    constexpr int RW = kTileW + 1;            // rowbuf stride
+    constexpr int SHIFT = (4 - (K % 4)) % 4;  // (x0 - K + cb) mod 4
+    constexpr int NV = (SHIFT + R + 2 * K + 3) / 4;  // float4 groups per row task
+    __shared__ float rowbuf[ROWS * RW];
+    const int nt = a.tiles_x * a.tiles_y;
+    const int lin = xcd_remap(blockIdx.x, gridDim.x);
+    const int b = lin / nt;
+    const int tile = lin % nt;
+    if (OUT != OUT_INV_DEN) {
+        if (a.rej && ((*a.rej >> b) & 1u)) return;
+        if (a.active && !a.active[b]) return;
+    }
+    const int ty = tile / a.tiles_x, tx = tile % a.tiles_x;
+    const int y0 = ty * kTH2, x0 = tx * kTileW;
+    const size_t bo = (size_t)b * a.H * a.W;
+    const int tid = threadIdx.x;
+
+    // Row pass: task = (input row r, column block cb of 16 outputs).
+    for (int task = tid; task < ROWS * 4; task += kThreads2) {
+        const int r = task >> 2, cb = (task & 3) * R;
+        const int gy = y0 - K + r;
+        float acc[R];
+        if (gy < 0 || gy >= a.H) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) acc[q] = 0.0f;
         } else {
-            float s, dpos;
-            if (OUT == OUT_S_PEAKS) {
-                const float id = a.inv_den[p];
-                s = v * id;
-                dpos = id;
-            } else {
-                const float dn = a.den[bo + p];
-                s = dn > 0.0f ? v / dn : 0.0f;
-                dpos = dn;
+            const size_t rowoff = (size_t)gy * a.W;
+            const int a0 = x0 - K + cb - SHIFT;  // multiple of 4
+            // sky-mask words covering columns a0 .. a0 + 4 NV - 1
+            constexpr int NW = (4 * NV + 31) / 32 + 1;
+            const int i0 = a0 >> 5;  // floor division (a0 may be negative)
+            uint32_t mw[NW];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const int wi = i0 + w;
+                mw[w] = !a.mbits ? 0xffffffffu
+                                 : (wi >= 0 && wi < a.mwords ? a.mbits[(size_t)gy * a.mwords + wi] : 0u);
             }
-            const float cv = a.C[bo + p];
-            const float xv = a.X[bo + p];
-            const bool m = a.M ? a.M[p] != 0 : true;
-            const bool y = m && dpos > 0.0f && xv > cv + a.kappa * sqrtf(s);
-            if (a.S_out) a.S_out[bo + p] = s;
-            if (OUT == OUT_S_PEAKS) {
-                if (a.Y_out) a.Y_out[bo + p] = y ? 1 : 0;
-                if (a.Y_out2) a.Y_out2[bo + p] = y ? 1 : 0;
-                if (y && is_peak(a, bo, gy, gx, xv)) {
-                    const int idx = atomicAdd(&a.peak_cnt[b], 1);
-                    if (idx < a.peak_cap) {
-                        PeakRec rec;
-                        rec.band = b;
-                        rec.row = gy;
-                        rec.col = gx;
-                        rec.x = xv;
-                        rec.c = cv;
-                        rec.s = s;
-                        rec.sig = (xv - cv) / sqrtf(s);
-                        a.peak_raw[(size_t)b * a.peak_cap + idx] = rec;
-                    }
+            const int sh0 = a0 & 31;
+            float v[NV * 4];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                const int gx = a0 + 4 * j;
+                if (gx >= 0 && gx + 3 < a.W) {
+                    const int pbit = sh0 + 4 * j;   // bit offset from word i0
+                    const int wsel = pbit >> 5;
+                    uint32_t wv = mw[0];
+#pragma unroll
+                    for (int w = 1; w < NW; ++w) wv = wsel == w ? mw[w] : wv;
+                    load_group<IN>(a, bo, rowoff, gx, (wv >> (pbit & 31)) & 0xFu, v + 4 * j);
+                } else {
+                    v[4 * j] = v[4 * j + 1] = v[4 * j + 2] = v[4 * j + 3] = 0.0f;
                 }
-                if (y && a.changed) a.changed[b] = 1;
-            } else {  // OUT_S_DYN: Y_i = Y_{i-1} or y, into the other plane
-                const uint8_t old = a.Y[bo + p];
-                a.Y_out[bo + p] = (y || old) ? 1 : 0;
-                if (y && !old) a.changed[b] = 1;
+            }
+#pragma unroll
+            for (int q = 0; q < R; ++q) acc[q] = 0.0f;
+#pragma unroll
+            for (int u = 0; u <= 2 * K; ++u) {
+                const float g = tp.g[u];
+#pragma unroll
+                for (int q = 0; q < R; ++q) acc[q] = fmaf(g, v[SHIFT + q + u], acc[q]);
             }
         }
+        float* dst = rowbuf + r * RW + cb;
+#pragma unroll
+        for (int q = 0; q < R; ++q) dst[q] = acc[q];
+    }
+    __syncthreads();
+
+    // Column pass: thread -> column c, rows rb*16 .. rb*16+15 (8 row blocks).
+    const int c = tid & 63, rb = tid >> 6;
+    float w[R + 2 * K];
+#pragma unroll
+    for (int i = 0; i < R + 2 * K; ++i) w[i] = rowbuf[(rb * R + i) * RW + c];
+    float acc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = 0.0f;
+#pragma unroll
+    for (int u = 0; u <= 2 * K; ++u) {
+        const float g = tp.g[u];
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] = fmaf(g, w[q + u], acc[q]);
+    }
+    const int gx = x0 + c;
+    if (gx >= a.W) return;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int gy = y0 + rb * R + q;
+        if (gy >= a.H) break;
+        epilogue<OUT>(a, b, bo, gy, gx, acc[q]);
     }
 }
 
@@ -303,6 +447,21 @@ __global__ __launch_bounds__(256) void k_peaks_planes(FiltArgs a) {
     }
 }
 
+// Packs the uint8 sky mask into bits: word w of row i holds columns 32w .. 32w+31.
+__global__ void k_pack_mask(const uint8_t* __restrict__ m, uint32_t* __restrict__ bits, int H, int W,
+                            int mwords) {
+    const int64_t n = (int64_t)H * mwords;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int row = (int)(i / mwords), w = (int)(i % mwords);
+        uint32_t v = 0u;
+        for (int j = 0; j < 32; ++j) {
+            const int col = 32 * w + j;
+            if (col < W && m[(size_t)row * W + col]) v |= 1u << j;
+        }
+        bits[i] = v;
+    }
+}
+
 __global__ void k_detect_init(int32_t* peak_cnt, int32_t* changed, int n_changed, int B) {
     const int i = threadIdx.x + blockIdx.x * blockDim.x;
     if (i < B) peak_cnt[i] = 0;
@@ -324,14 +483,26 @@ hipError_t run_filter(lpf_ctx* c, const FiltArgs& a, int nbands) {
     return hipGetLastError();
 }
 
+template <int K, int IN, int OUT>
+hipError_t run_fast(lpf_ctx* c, FiltArgs a, int nbands) {
+    a.tiles_y = (a.H + kTH2 - 1) / kTH2;
+    const int nblocks = a.tiles_x * a.tiles_y * nbands;
+    hipLaunchKernelGGL((k_filter_fast<K, IN, OUT>), dim3(nblocks), dim3(kThreads2), 0, c->stream, a,
+                       c->taps);
+    return hipGetLastError();
+}
+
 template <int IN, int OUT>
 hipError_t dispatch_k(lpf_ctx* c, const FiltArgs& a, int nbands) {
-    switch (c->d.k) {
-        case 15: return run_filter<15, IN, OUT>(c, a, nbands);
-        case 24: return run_filter<24, IN, OUT>(c, a, nbands);
-        case 36: return run_filter<36, IN, OUT>(c, a, nbands);
-        default: return run_filter<0, IN, OUT>(c, a, nbands);
+    if (a.W % 4 == 0) {
+        switch (c->d.k) {
+            case 15: return run_fast<15, IN, OUT>(c, a, nbands);
+            case 24: return run_fast<24, IN, OUT>(c, a, nbands);
+            case 36: return run_fast<36, IN, OUT>(c, a, nbands);
+            default: break;
+        }
     }
+    return run_filter<0, IN, OUT>(c, a, nbands);
 }
 
 FiltArgs base_args(lpf_ctx* c, int slot) {
@@ -342,6 +513,8 @@ FiltArgs base_args(lpf_ctx* c, int slot) {
     a.Y = c->buf.clip;
     a.den = c->buf.den;
     a.inv_den = c->buf.inv_den;
+    a.mbits = c->d.masked ? c->buf.mask_bits : nullptr;
+    a.mwords = c->d.mwords;
     a.rej = c->buf.cache_rej + slot;
     a.peak_cnt = c->buf.peak_cnt;
     a.peak_raw = c->buf.peak_raw;
@@ -357,6 +530,15 @@ FiltArgs base_args(lpf_ctx* c, int slot) {
 }
 
 }  // namespace
+
+hipError_t launch_pack_mask(lpf_ctx* c) {
+    const int64_t n = (int64_t)c->cfg.H * c->d.mwords;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_pack_mask, dim3(blocks), dim3(256), 0, c->stream, c->buf.mask, c->buf.mask_bits,
+                       c->cfg.H, c->cfg.W, c->d.mwords);
+    return hipGetLastError();
+}
 
 hipError_t launch_inv_den(lpf_ctx* c) {
     FiltArgs a = base_args(c, 0);

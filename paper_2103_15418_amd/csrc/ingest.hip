@@ -9,8 +9,8 @@
 //     (zeta = |x - mean| / std, max per band),
 //   * writes the Welford update of (mean, M2) into the band's *other* state
 //     buffer.
-// A one-wave kernel (k_qc_decide) then reduces the per-block partials in a
-// fixed order, forms the robust z-scores of band means and RMS (median /
+// A one-workgroup kernel (k_qc_decide, a wave per band) then reduces the
+// per-block partials in a fixed order, forms the robust z-scores of band means and RMS (median /
 // median absolute deviation across bands), takes the decision, and commits
 // the speculative Welford update of accepted bands by flipping their buffer
 // index.  Rejected bands keep their old statistics and are treated as all
@@ -150,43 +150,44 @@ __global__ __launch_bounds__(kIngThreads) void k_ingest(
     }
 }
 
-__device__ void sort_small(double* v, int n) {
-    for (int i = 1; i < n; ++i) {
-        double x = v[i];
-        int j = i - 1;
-        while (j >= 0 && v[j] > x) {
-            v[j + 1] = v[j];
-            --j;
-        }
-        v[j + 1] = x;
+// Median of the entries of v flagged in use, computed by lanes 0..B-1 of one
+// wave: each lane ranks its value (ties by index) and scatters it to its
+// rank, so no lane runs a serial sort.  tmp: LDS scratch of kMaxB doubles.
+__device__ double wave_median(double v, bool use, int B, double* tmp) {
+    const int lane = threadIdx.x & 63;
+    __shared__ double s_v[kMaxB];
+    __shared__ int s_use[kMaxB];
+    if (lane < B) {
+        s_v[lane] = v;
+        s_use[lane] = use;
     }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    int m = 0, rank = 0;
+    for (int j = 0; j < B; ++j) {
+        if (!s_use[j]) continue;
+        ++m;
+        if (lane < B && use && (s_v[j] < v || (s_v[j] == v && j < lane))) ++rank;
+    }
+    if (lane < B && use) tmp[rank] = v;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    double med = 0.0;
+    if (m > 0) med = (m & 1) ? tmp[m / 2] : 0.5 * (tmp[m / 2 - 1] + tmp[m / 2]);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    return med;
 }
 
-__device__ double median_small(double* v, int n) {
-    sort_small(v, n);
-    return (n & 1) ? v[n / 2] : 0.5 * (v[n / 2 - 1] + v[n / 2]);
-}
-
-// Robust z of v over the bands flagged in use: (v - med) / max(MAD, floor |med|).
-__device__ void robust_z(const double* v, const bool* use, int B, double floor_rel, double* z) {
-    double tmp[kMaxB];
-    int m = 0;
-    for (int b = 0; b < B; ++b)
-        if (use[b]) tmp[m++] = v[b];
-    for (int b = 0; b < B; ++b) z[b] = 0.0;
-    if (m == 0) return;
-    double med = median_small(tmp, m);
-    m = 0;
-    for (int b = 0; b < B; ++b)
-        if (use[b]) tmp[m++] = fabs(v[b] - med);
-    double mad = median_small(tmp, m);
-    double fl = floor_rel * fabs(med);
+// Robust z of lane b's value: (v - med) / max(MAD, floor |med|), 0 if unused.
+__device__ double wave_robust_z(double v, bool use, int B, double floor_rel, double* tmp) {
+    const double med = wave_median(v, use, B, tmp);
+    double mad = wave_median(fabs(v - med), use, B, tmp);
+    const double fl = floor_rel * fabs(med);
     if (fl > mad) mad = fl;
-    for (int b = 0; b < B; ++b) {
-        if (!use[b]) continue;
-        double dlt = v[b] - med;
-        z[b] = mad > 0.0 ? dlt / mad : (dlt == 0.0 ? 0.0 : INFINITY);
-    }
+    if (!use) return 0.0;
+    const double dlt = v - med;
+    return mad > 0.0 ? dlt / mad : (dlt == 0.0 ? 0.0 : INFINITY);
 }
 
 struct QcParams {
@@ -197,52 +198,57 @@ struct QcParams {
     int warm;
 };
 
-__global__ __launch_bounds__(64) void k_qc_decide(QcParams q, const BandPartial* __restrict__ partials,
-                                                   int32_t* wf_n, int32_t* wf_cur, double* bandstats,
-                                                   int64_t* cache_t, uint32_t* cache_rej, int slot,
-                                                   int64_t t, DevStatus* status) {
-    __shared__ double s_mean[kMaxB], s_rms[kMaxB];
+// One wave per band reduces that band's block partials (lane l sums blocks
+// l, l+64, ... in order, then a fixed butterfly), then lane 0 of the block
+// takes the decision.
+__global__ __launch_bounds__(1024) void k_qc_decide(QcParams q, const BandPartial* __restrict__ partials,
+                                                     int32_t* wf_n, int32_t* wf_cur, double* bandstats,
+                                                     int64_t* cache_t, uint32_t* cache_rej, int slot,
+                                                     int64_t t, DevStatus* status) {
+    __shared__ double s_mean[kMaxB], s_rms[kMaxB], s_tmp[kMaxB];
     __shared__ int s_nf[kMaxB];
     __shared__ float s_z[kMaxB];
-    const int b = threadIdx.x;
+    const int b = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (b < q.B) {
         double sx = 0.0, sxx = 0.0;
         int nf = 0;
         float z = 0.0f;
         const BandPartial* p = partials + (size_t)b * q.nblk;
-        for (int i = 0; i < q.nblk; ++i) {
+        for (int i = lane; i < q.nblk; i += 64) {
             sx += p[i].sx;
             sxx += p[i].sxx;
             nf += p[i].nonfinite;
             z = fmaxf(z, p[i].zmax);
         }
-        s_mean[b] = sx / q.npix;
-        s_rms[b] = sqrt(sxx / q.npix);
-        s_nf[b] = nf;
-        s_z[b] = z;
+        sx = wave_sum_d(sx);
+        sxx = wave_sum_d(sxx);
+        nf = wave_sum_i(nf);
+        z = wave_max_f(z);
+        if (lane == 0) {
+            s_mean[b] = sx / q.npix;
+            s_rms[b] = sqrt(sxx / q.npix);
+            s_nf[b] = nf;
+            s_z[b] = z;
+        }
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    bool ok[kMaxB];
-    double zm[kMaxB], zr[kMaxB];
-    for (int i = 0; i < q.B; ++i) ok[i] = s_nf[i] == 0;
-    robust_z(s_mean, ok, q.B, 0.0, zm);
-    if (q.rms_z > 0.0)
-        robust_z(s_rms, ok, q.B, q.rms_floor, zr);
-    else
-        for (int i = 0; i < q.B; ++i) zr[i] = 0.0;
-    uint32_t rej = 0;
-    for (int i = 0; i < q.B; ++i) {
+    if (threadIdx.x >= 64) return;   // the decision: lanes 0..B-1 of wave 0
+    const int i = threadIdx.x;
+    const bool in = i < q.B;
+    const bool ok = in && s_nf[i] == 0;
+    const double zm = wave_robust_z(in ? s_mean[i] : 0.0, ok, q.B, 0.0, s_tmp);
+    const double zr = q.rms_z > 0.0 ? wave_robust_z(in ? s_rms[i] : 0.0, ok, q.B, q.rms_floor, s_tmp) : 0.0;
+    bool bad = false;
+    if (in) {
         const int n = wf_n[i];
         const bool armed = n >= q.warm && n >= 2;
-        bool bad = !ok[i] || fabs(zm[i]) > q.band_z || (q.rms_z > 0.0 && fabs(zr[i]) > q.rms_z) ||
-                   (armed && (double)s_z[i] > q.zeta);
-        if (bad) rej |= 1u << i;
+        bad = !ok || fabs(zm) > q.band_z || (q.rms_z > 0.0 && fabs(zr) > q.rms_z) ||
+              (armed && (double)s_z[i] > q.zeta);
         double* bs = bandstats + 6 * i;
         bs[0] = s_mean[i];
         bs[1] = s_rms[i];
-        bs[2] = zm[i];
-        bs[3] = zr[i];
+        bs[2] = zm;
+        bs[3] = zr;
         bs[4] = armed ? (double)s_z[i] : 0.0;
         bs[5] = (double)s_nf[i];
         if (!bad) {  // commit the speculative Welford update
@@ -250,6 +256,9 @@ __global__ __launch_bounds__(64) void k_qc_decide(QcParams q, const BandPartial*
             wf_cur[i] = 1 - wf_cur[i];
         }
     }
+    const uint64_t bal = __ballot(bad);
+    const uint32_t rej = (uint32_t)(bal & 0xffffffffull);
+    if (i != 0) return;
     cache_t[slot] = t;
     cache_rej[slot] = rej;
     status->rejected = rej;
@@ -287,7 +296,7 @@ hipError_t launch_qc_decide(lpf_ctx* c, int slot, int64_t t) {
     q.rms_floor = c->cfg.qc_rms_floor;
     q.zeta = c->cfg.qc_pixel_zeta;
     q.warm = c->cfg.qc_warmup;
-    hipLaunchKernelGGL(k_qc_decide, dim3(1), dim3(64), 0, c->stream, q, c->buf.partials, c->buf.wf_n,
+    hipLaunchKernelGGL(k_qc_decide, dim3(1), dim3(64 * c->cfg.B), 0, c->stream, q, c->buf.partials, c->buf.wf_n,
                        c->buf.wf_cur, c->buf.bandstats, c->buf.cache_t, c->buf.cache_rej, slot, t,
                        c->buf.status);
     return hipGetLastError();

@@ -76,6 +76,7 @@ struct DevBufs {
     int32_t* wf_n;         // [B]
     int32_t* wf_cur;       // [B]
     uint8_t* mask;         // [H][W]
+    uint32_t* mask_bits;   // [H][mwords] packed sky mask
     float* inv_den;        // [H][W] 1 / (G * M), 0 where G * M = 0
     float* centre;         // [B][H][W]
     float* spread;         // [B][H][W] (debug or iterations > 1)
@@ -88,7 +89,7 @@ struct DevBufs {
     PeakRec* peak_raw;     // [B][peak_cap]
     PeakRec* peak_sorted;  // [B * peak_cap]
     // catalogue scratch
-    uint64_t* cat_keys;    // [kCatMaxPeaks] global spill for sorting
+    int32_t* cat_dec;      // [kCatMaxPeaks] association decisions (large steps)
     int32_t* cat_order;    // [kCatMaxPeaks]
     int32_t* cat_kept;     // [kCatMaxPeaks]
     int32_t* cat_nbr;      // [kCatMaxPeaks][kNbr]
@@ -123,6 +124,7 @@ struct Derived {
     int nblk;      // ingest blocks per band
     size_t HW;
     size_t plane;  // B * H * W
+    int mwords;    // 32-bit words per packed mask row
     bool masked;
     bool dyn;      // iterations > 1 or debug planes: materialise S / Y
 };
@@ -180,6 +182,7 @@ hipError_t launch_qc_decide(lpf_ctx* c, int slot, int64_t t);
 hipError_t launch_detect_init(lpf_ctx* c);
 hipError_t launch_filters(lpf_ctx* c, int slot);
 hipError_t launch_inv_den(lpf_ctx* c);
+hipError_t launch_pack_mask(lpf_ctx* c);
 hipError_t launch_catalog(lpf_ctx* c, int64_t t);
 hipError_t launch_flux(lpf_ctx* c, int slot, int64_t t);
 hipError_t launch_table_init(lpf_ctx* c);
