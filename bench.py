@@ -76,6 +76,49 @@ def cpu_baseline(spec_name, n_frames):
                       f"numpy float64, one process, {dt:.1f} s"}
 
 
+def precision_errors(code, st, pool, Context, Model, synth):
+    """Max / median error relative to the FP64 oracle's condition scale: C and S
+    on band 0 of step 0, network outputs on 32 seeded windows."""
+    import torch
+    from oracle import cnn as ocnn
+    from oracle.filters import centre_spread, correlate_2d, taps_1d
+    spec = st.spec
+    c = Context(spec.B, spec.H, spec.W, sky_mask=st.mask, filter_precision=code, debug_planes=1)
+    c.ingest(0, pool[0])
+    c.detect(want=False)
+    Cd, Sd = c.debug_read("centre")[0], c.debug_read("spread")[0]
+    del c
+    X = pool[0, 0].cpu().numpy()
+    M = st.mask.astype(bool)
+    g = taps_1d(0, 8.0, 24)
+    C, S, den = centre_spread(X, M, g)
+    pos = (den > 0) & M
+    safe = np.where(den > 0, den, 1.0)
+    scC = correlate_2d(M * np.abs(X.astype(np.float64)), g) / safe
+    scS = correlate_2d(M * (np.abs(X.astype(np.float64)) + np.abs(C)) ** 2, g) / safe
+    eC = (np.abs(Cd - C) / np.maximum(scC, 1e-30))[pos]
+    eS = (np.abs(Sd - S) / np.maximum(scS, 1e-30))[pos]
+    wts = synth.cnn_weights()
+    x = (np.random.default_rng(0).standard_normal((32, 16, 64)) * 2.0).astype(np.float32)
+    m = Model(wts, precision=code, max_batch=32)
+    mu, L = m.infer_windows(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    raw = ocnn.forward_raw(x.astype(np.float64), wts)
+    mo, Lo = ocnn.head(raw)
+    a = x.astype(np.float64)[:, None]
+    for l in range(1, 5):
+        a = ocnn.act(ocnn.conv3x3(a, wts[f"conv{l}.w"], wts[f"conv{l}.b"]), wts["alpha"])
+    h = ocnn.act(a.reshape(len(x), -1) @ wts["fc1.w"].astype(np.float64).T + wts["fc1.b"], wts["alpha"])
+    sc = np.abs(h) @ np.abs(wts["fc2.w"].astype(np.float64)).T + np.abs(wts["fc2.b"])
+    en = np.concatenate([np.abs(mu.cpu().numpy() - mo) / sc[:, :4], np.abs(L.cpu().numpy() - Lo) / sc[:, 4:]], 1)
+    return {"scale": "|error| / condition scale (filters: G*(M|x|) and G*(M(|x|+|c|)^2) over G*M; "
+                     "network: |W_fc2||h| + |b_fc2| with exact hidden activations h)",
+            "centre": [float(eC.max()), float(np.median(eC))],
+            "spread": [float(eS.max()), float(np.median(eS))],
+            "network_mu": [float(en[:, :4].max()), float(np.median(en[:, :4]))],
+            "network_L": [float(en[:, 4:].max()), float(np.median(en[:, 4:]))]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +128,7 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--no-precision-forms", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, copy 256 MiB device-to-device once (reference for HBM counters)")
     args = ap.parse_args()
@@ -107,39 +151,48 @@ def main():
     for i, f in enumerate(frames):
         pool[i].copy_(torch.from_numpy(f))
     del frames
-    ctx = Context(B, H, W, sky_mask=st.mask)
-    model = Model(synth.cnn_weights(), max_batch=1024)
-    torch.cuda.synchronize()
+    def run(precision, steps, warmup):
+        """Times `steps` steps after `warmup`; returns (elapsed s, latencies, stage profile, windows)."""
+        ctx = Context(B, H, W, sky_mask=st.mask, filter_precision=precision)
+        model = Model(synth.cnn_weights(), precision=precision, max_batch=1024)
+        torch.cuda.synchronize()
+        n_inf = [0]
 
-    n_inferred = [0]
+        def step(t):
+            ctx.ingest(t, pool[t % n_pool])
+            ctx.detect(want=False)
+            ctx.extract_flux()
+            mu, L, src = model.infer([ctx])
+            n_inf[0] += len(mu)
 
-    def step(t):
-        ctx.ingest(t, pool[t % n_pool])
-        ctx.detect(want=False)
-        ctx.extract_flux()
-        mu, L, src = model.infer([ctx])
-        n_inferred[0] += len(mu)
+        for t in range(warmup):
+            step(t)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        ctx.profile_read()
+        n_inf[0] = 0
+        lat = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            f0 = time.perf_counter()
+            step(warmup + i)
+            lat.append(time.perf_counter() - f0)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = ctx.profile_read()
+        cfg = ctx.cfg
+        del ctx, model
+        return el, lat, prof, n_inf[0], cfg
 
-    print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
-    for t in range(args.warmup):
-        step(t)
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    ctx.profile_read()
-    n_inferred[0] = 0
-    lat = []
-    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        f0 = time.perf_counter()
-        step(args.warmup + i)
-        lat.append(time.perf_counter() - f0)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = ctx.profile_read()
-    ctx.profile(False)
+    print(f"[bench] fp32: warmup {args.warmup}, timing {args.steps} steps", file=sys.stderr, flush=True)
+    elapsed, lat, prof, n_windows, cfg = run(0, args.steps, args.warmup)
+    n_inferred = [n_windows]
 
+    class _C:  # configuration of the timed run, for the stage rooflines
+        pass
+    ctx = _C()
+    ctx.cfg = cfg
     px_step = B * H * W
     value = args.steps * px_step / elapsed
     stages = {}
@@ -191,6 +244,18 @@ def main():
         "roofline": roof,
         "stages": stages,
     }
+    # precision forms: bf16 / fp16 operands on MFMA (filters and network), float32 accumulation
+    if not args.no_precision_forms:
+        forms = {}
+        for code, name in ((1, "bf16"), (2, "fp16")):
+            print(f"[bench] {name}: timing {args.steps} steps", file=sys.stderr, flush=True)
+            el, lt, pr, nw, _ = run(code, args.steps, args.warmup)
+            forms[name] = {"value": args.steps * px_step / el, "ms_per_step": el / args.steps * 1e3,
+                           "p99_ms": float(np.percentile(np.array(lt) * 1e3, 99)),
+                           "stage_avg_ms": {k: round(v[0] / v[1], 5) for k, v in pr.items() if v[1]},
+                           "windows_inferred": nw}
+            forms[name]["error_vs_fp64"] = precision_errors(code, st, pool, Context, Model, synth)
+        out["precision_forms"] = forms
     if args.calibrate_copy:
         src = torch.ones(64 * 2 ** 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

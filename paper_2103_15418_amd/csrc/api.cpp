@@ -69,7 +69,12 @@ int validate(const lpf_config* c, std::string* why) {
     if (c->qc_warmup < 0) return bad("qc_warmup must be >= 0");
     if (c->max_sources < 1 || c->max_sources > kMaxSources) return bad("max_sources in 1..65536");
     if (c->peak_cap < 1 || (int64_t)c->peak_cap * c->B > kCatMaxPeaks) return bad("B * peak_cap must be <= 8192");
-    if (c->filter_precision != LPF_PREC_FP32) return bad("filter_precision: only FP32 is available");
+    if (c->filter_precision != LPF_PREC_FP32 && c->filter_precision != LPF_PREC_BF16 &&
+        c->filter_precision != LPF_PREC_FP16)
+        return bad("unknown filter_precision");
+    if (c->filter_precision != LPF_PREC_FP32 &&
+        (c->clip_iters != 1 || c->W % 4 != 0 || (k != 15 && k != 24 && k != 36)))
+        return bad("16-bit filters need clip_iters = 1, W % 4 = 0 and half-width 15, 24 or 36");
     if (c->grid_rows) {
         bool used[kGridRows] = {};
         for (int b = 0; b < c->B; ++b) {

@@ -23,6 +23,8 @@
 namespace lpf {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 struct ModelLayout {
     // float offsets inside the weight area
@@ -30,8 +32,11 @@ struct ModelLayout {
 };
 
 struct CnnWork {
-    float* act_a;     // [maxb][16][64][64]
+    float* act_a;     // [maxb][16][64][64] (float32 network)
     float* act_b;
+    void* act16_a;    // [maxb][16][64][64] (16-bit network)
+    void* act16_b;
+    void* w16;        // 16-bit weights: conv2..4 [9][Cout][Cin], fc1 [128][65536]
     float* part;      // [128][maxb_pad][128] fc1 split-K partials
     float* hidden;    // [maxb][128]
     float* windows;   // [maxb][16][64]
@@ -62,6 +67,12 @@ constexpr int kSplitK = 512;
 constexpr int kNSplit = kFlat / kSplitK;  // 128
 
 size_t align64(size_t x) { return (x + 63) & ~size_t(63); }
+
+// element offsets of the 16-bit weight copies
+constexpr size_t kW16o2 = 0, kW16o3 = kW16o2 + 9 * 32 * 32, kW16o4 = kW16o3 + 9 * 32 * 64,
+                 kW16of1 = kW16o4 + 9 * 64 * 64, kW16total = kW16of1 + (size_t)kFlat * kHidden;
+
+
 
 ModelLayout make_layout() {
     ModelLayout L{};
@@ -208,6 +219,156 @@ __global__ __launch_bounds__(256) void k_fc1_mfma(const float* __restrict__ a, c
     }
 }
 
+// ---- 16-bit (bf16 / fp16) network: same layers, 16-bit operands, float32 accumulation
+template <typename T> struct V8;
+template <> struct V8<__bf16> { typedef bf16x8 type; };
+template <> struct V8<_Float16> { typedef f16x8 type; };
+
+template <typename T>
+__device__ inline floatx16 mfma32(typename V8<T>::type a, typename V8<T>::type b, floatx16 c);
+template <>
+__device__ inline floatx16 mfma32<__bf16>(bf16x8 a, bf16x8 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+template <>
+__device__ inline floatx16 mfma32<_Float16>(f16x8 a, f16x8 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_conv1_16(const float* __restrict__ x, const float* __restrict__ w,
+                                                  const float* __restrict__ bias, T* __restrict__ out,
+                                                  int n_total, float alpha) {
+    const int64_t total = (int64_t)n_total * kGH * kGW * 32;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % 32);
+        const int64_t pix = i / 32;
+        const int col = (int)(pix % kGW);
+        const int row = (int)((pix / kGW) % kGH);
+        const int64_t n = pix / (kGW * kGH);
+        const float* xi = x + n * kGH * kGW;
+        float acc = bias[c];
+        for (int kh = 0; kh < 3; ++kh) {
+            const int r = row + kh - 1;
+            if (r < 0 || r >= kGH) continue;
+            for (int kw = 0; kw < 3; ++kw) {
+                const int q = col + kw - 1;
+                if (q < 0 || q >= kGW) continue;
+                acc = fmaf(w[(kh * 3 + kw) * 32 + c], xi[r * kGW + q], acc);
+            }
+        }
+        out[i] = (T)act_fn(acc, alpha);
+    }
+}
+
+// conv Cin -> Cout on v_mfma_f32_32x32x16_{bf16,f16}: a lane feeds 8 consecutive
+// input channels of one pixel (one 16-byte NHWC load) and 8 consecutive input
+// channels of one output channel's weights ([9][Cout][Cin] layout).
+template <typename T, int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv16(const T* __restrict__ in, const T* __restrict__ w,
+                                                const float* __restrict__ bias, T* __restrict__ out,
+                                                float alpha) {
+    typedef typename V8<T>::type vec;
+    constexpr int ROWS = 64 / COUT;
+    const int n = blockIdx.x / (kGH / ROWS);
+    const int h0 = (blockIdx.x % (kGH / ROWS)) * ROWS;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int rloc, px0, co0;
+    if (COUT == 64) {
+        rloc = 0;
+        px0 = (wave & 1) * 32;
+        co0 = (wave >> 1) * 32;
+    } else {
+        rloc = wave >> 1;
+        px0 = (wave & 1) * 32;
+        co0 = 0;
+    }
+    const int m = lane & 31, kg = lane >> 5;
+    const int row = h0 + rloc;
+    floatx16 acc = {};
+    vec zero = {};
+#pragma unroll 1
+    for (int kh = 0; kh < 3; ++kh) {
+        const int r = row + kh - 1;
+        const bool rv = r >= 0 && r < kGH;
+#pragma unroll
+        for (int kw = 0; kw < 3; ++kw) {
+            const int col = px0 + m + kw - 1;
+            const bool valid = rv && col >= 0 && col < kGW;
+            const T* ap = in + (((size_t)n * kGH + (rv ? r : 0)) * kGW + (valid ? col : 0)) * CIN + kg * 8;
+            const T* bp = w + ((size_t)(kh * 3 + kw) * COUT + co0 + m) * CIN + kg * 8;
+#pragma unroll
+            for (int c0 = 0; c0 < CIN; c0 += 16) {
+                const vec av = valid ? *reinterpret_cast<const vec*>(ap + c0) : zero;
+                const vec bv = *reinterpret_cast<const vec*>(bp + c0);
+                acc = mfma32<T>(av, bv, acc);
+            }
+        }
+    }
+    T* dst = out + ((size_t)n * kGH + row) * kGW * COUT;
+    const float bj = bias[co0 + m];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int px = px0 + 8 * (v / 4) + 4 * kg + (v % 4);
+        dst[(size_t)px * COUT + co0 + m] = (T)act_fn(acc[v] + bj, alpha);
+    }
+}
+
+// fc1 split-K on 16-bit operands: A = act [n][65536] (NHWC flatten), B = W1 [128][65536].
+template <typename T>
+__global__ __launch_bounds__(256) void k_fc1_16(const T* __restrict__ a, const T* __restrict__ w,
+                                                float* __restrict__ part, int n_total, int ld_part) {
+    typedef typename V8<T>::type vec;
+    const int ks = blockIdx.x, mb = blockIdx.y;
+    const int k0 = ks * kSplitK;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m = lane & 31, kg = lane >> 5;
+    const int co0 = wave * 32;
+    const int n = mb * 32 + m;
+    const bool valid = n < n_total;
+    const T* ap = a + (size_t)(valid ? n : 0) * kFlat + k0 + kg * 8;
+    const T* bp = w + (size_t)(co0 + m) * kFlat + k0 + kg * 8;
+    floatx16 acc = {};
+    vec zero = {};
+#pragma unroll 8
+    for (int k = 0; k < kSplitK; k += 16) {
+        const vec av = valid ? *reinterpret_cast<const vec*>(ap + k) : zero;
+        const vec bv = *reinterpret_cast<const vec*>(bp + k);
+        acc = mfma32<T>(av, bv, acc);
+    }
+    float* dst = part + (size_t)ks * ld_part * kHidden;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int r = mb * 32 + 8 * (v / 4) + 4 * kg + (v % 4);
+        dst[(size_t)r * kHidden + co0 + m] = acc[v];
+    }
+}
+
+// float32 device layouts -> 16-bit copies: conv [(kh*3+kw)*Cin+cin][Cout] -> [kh*3+kw][Cout][Cin],
+// fc1 [k][128] -> [128][k].
+template <typename T>
+__global__ void k_to16(const float* __restrict__ W, T* __restrict__ w16, ModelLayout lay, size_t o2, size_t o3,
+                       size_t o4, size_t of1) {
+    const size_t nth = (size_t)gridDim.x * blockDim.x;
+    const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    auto conv = [&](size_t src, size_t dst, int cin, int cout) {
+        for (size_t i = tid; i < (size_t)9 * cin * cout; i += nth) {
+            const int kk = (int)(i / ((size_t)cin * cout));
+            const int ci = (int)((i / cout) % cin);
+            const int co = (int)(i % cout);
+            w16[dst + ((size_t)kk * cout + co) * cin + ci] = (T)W[src + i];
+        }
+    };
+    conv(lay.w2, o2, 32, 32);
+    conv(lay.w3, o3, 32, 64);
+    conv(lay.w4, o4, 64, 64);
+    for (size_t i = tid; i < (size_t)kFlat * kHidden; i += nth) {
+        const size_t k = i / kHidden, j = i % kHidden;
+        w16[of1 + j * kFlat + k] = (T)W[lay.f1 + i];
+    }
+}
+
 // hidden[n][j] = phi(sum_ks part[ks][n][j] + b[j]) in a fixed order.
 __global__ void k_fc1_reduce(const float* __restrict__ part, const float* __restrict__ bias,
                              float* __restrict__ hidden, int n_total, int ld_part, float alpha) {
@@ -290,10 +451,12 @@ size_t blob_floats() {
 
 int pad32(int n) { return (n + 31) / 32 * 32; }
 
-size_t work_bytes(int maxb) {
-    const size_t act = (size_t)maxb * kGH * kGW * 64 * sizeof(float);
+size_t work_bytes(int precision, int maxb) {
+    const size_t elt = precision == LPF_PREC_FP32 ? sizeof(float) : 2;
+    const size_t act = (size_t)maxb * kGH * kGW * 64 * elt;
     size_t b = 0;
     b += 2 * align64(act);
+    if (precision != LPF_PREC_FP32) b += align64(kW16total * 2);
     b += align64((size_t)kNSplit * pad32(maxb) * kHidden * sizeof(float));
     b += align64((size_t)maxb * kHidden * sizeof(float));
     b += align64((size_t)maxb * kGH * kGW * sizeof(float));
@@ -304,6 +467,29 @@ size_t work_bytes(int maxb) {
 
 }  // namespace
 
+template <typename T>
+hipError_t forward16(const lpf_model* m, const float* windows, int n, hipStream_t s) {
+    const ModelLayout& lay = m->lay;
+    const float* W = m->wts;
+    const CnnWork& w = m->work;
+    const T* w16 = static_cast<const T*>(w.w16);
+    T* a = static_cast<T*>(w.act16_a);
+    T* b = static_cast<T*>(w.act16_b);
+    int blocks = (int)(((int64_t)n * kGH * kGW * 32 + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL((k_conv1_16<T>), dim3(blocks), dim3(256), 0, s, windows, W + lay.w1, W + lay.b1, a, n,
+                       m->alpha);
+    hipLaunchKernelGGL((k_conv16<T, 32, 32>), dim3(n * (kGH / 2)), dim3(256), 0, s, a, w16 + kW16o2,
+                       W + lay.b2, b, m->alpha);
+    hipLaunchKernelGGL((k_conv16<T, 32, 64>), dim3(n * kGH), dim3(256), 0, s, b, w16 + kW16o3, W + lay.b3, a,
+                       m->alpha);
+    hipLaunchKernelGGL((k_conv16<T, 64, 64>), dim3(n * kGH), dim3(256), 0, s, a, w16 + kW16o4, W + lay.b4, b,
+                       m->alpha);
+    hipLaunchKernelGGL((k_fc1_16<T>), dim3(kNSplit, (n + 31) / 32), dim3(256), 0, s, b, w16 + kW16of1, w.part,
+                       n, pad32(m->max_batch));
+    return hipGetLastError();
+}
+
 // Runs the network on n device windows (n <= max_batch).
 hipError_t cnn_forward(const lpf_model* m, const float* windows, int n, float* mu, float* L,
                        hipStream_t s) {
@@ -311,19 +497,28 @@ hipError_t cnn_forward(const lpf_model* m, const float* windows, int n, float* m
     const ModelLayout& lay = m->lay;
     const float* W = m->wts;
     const CnnWork& w = m->work;
-    int blocks = (int)(((int64_t)n * kGH * kGW * 32 + 255) / 256);
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_conv1, dim3(blocks), dim3(256), 0, s, windows, W + lay.w1, W + lay.b1, w.act_a, n,
-                       m->alpha);
-    hipLaunchKernelGGL((k_conv_mfma<32, 32>), dim3(n * (kGH / 2)), dim3(256), 0, s, w.act_a, W + lay.w2,
-                       W + lay.b2, w.act_b, m->alpha);
-    hipLaunchKernelGGL((k_conv_mfma<32, 64>), dim3(n * kGH), dim3(256), 0, s, w.act_b, W + lay.w3,
-                       W + lay.b3, w.act_a, m->alpha);
-    hipLaunchKernelGGL((k_conv_mfma<64, 64>), dim3(n * kGH), dim3(256), 0, s, w.act_a, W + lay.w4,
-                       W + lay.b4, w.act_b, m->alpha);
     const int ldp = pad32(m->max_batch);
-    hipLaunchKernelGGL(k_fc1_mfma, dim3(kNSplit, (n + 31) / 32), dim3(256), 0, s, w.act_b, W + lay.f1, w.part,
-                       n, ldp);
+    hipError_t e = hipSuccess;
+    if (m->precision == LPF_PREC_BF16) {
+        e = forward16<__bf16>(m, windows, n, s);
+    } else if (m->precision == LPF_PREC_FP16) {
+        e = forward16<_Float16>(m, windows, n, s);
+    } else {
+        int blocks = (int)(((int64_t)n * kGH * kGW * 32 + 255) / 256);
+        if (blocks > 4096) blocks = 4096;
+        hipLaunchKernelGGL(k_conv1, dim3(blocks), dim3(256), 0, s, windows, W + lay.w1, W + lay.b1, w.act_a, n,
+                           m->alpha);
+        hipLaunchKernelGGL((k_conv_mfma<32, 32>), dim3(n * (kGH / 2)), dim3(256), 0, s, w.act_a, W + lay.w2,
+                           W + lay.b2, w.act_b, m->alpha);
+        hipLaunchKernelGGL((k_conv_mfma<32, 64>), dim3(n * kGH), dim3(256), 0, s, w.act_b, W + lay.w3,
+                           W + lay.b3, w.act_a, m->alpha);
+        hipLaunchKernelGGL((k_conv_mfma<64, 64>), dim3(n * kGH), dim3(256), 0, s, w.act_a, W + lay.w4,
+                           W + lay.b4, w.act_b, m->alpha);
+        hipLaunchKernelGGL(k_fc1_mfma, dim3(kNSplit, (n + 31) / 32), dim3(256), 0, s, w.act_b, W + lay.f1,
+                           w.part, n, ldp);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fc1_reduce, dim3((n * kHidden + 255) / 256), dim3(256), 0, s, w.part, W + lay.fb1,
                        w.hidden, n, ldp, m->alpha);
     hipLaunchKernelGGL(k_fc2_head, dim3((n * kOut + 255) / 256), dim3(256), 0, s, w.hidden, W + lay.f2,
@@ -339,9 +534,10 @@ int model_max_batch(const lpf_model* m) { return m->max_batch; }
 size_t model_blob_bytes() { return (blob_floats() + 1) * sizeof(float); }
 
 int model_workspace_size(int precision, int maxb, size_t* bytes) {
-    if (precision != LPF_PREC_FP32) return LPF_EINVAL;
+    if (precision != LPF_PREC_FP32 && precision != LPF_PREC_BF16 && precision != LPF_PREC_FP16)
+        return LPF_EINVAL;
     if (maxb < 1 || maxb > 65536) return LPF_EINVAL;
-    *bytes = align64(make_layout().total * sizeof(float)) + work_bytes(maxb) +
+    *bytes = align64(make_layout().total * sizeof(float)) + work_bytes(precision, maxb) +
              align64(blob_floats() * sizeof(float));
     return LPF_OK;
 }
@@ -364,9 +560,21 @@ int model_create(const void* weights, size_t bytes, int precision, int maxb, voi
     char* p = static_cast<char*>(ws);
     m->wts = reinterpret_cast<float*>(p);
     p += align64(m->lay.total * sizeof(float));
-    const size_t act = align64((size_t)maxb * kGH * kGW * 64 * sizeof(float));
-    m->work.act_a = reinterpret_cast<float*>(p); p += act;
-    m->work.act_b = reinterpret_cast<float*>(p); p += act;
+    const size_t elt = precision == LPF_PREC_FP32 ? sizeof(float) : 2;
+    const size_t act = align64((size_t)maxb * kGH * kGW * 64 * elt);
+    m->work.act_a = nullptr;
+    m->work.act_b = nullptr;
+    m->work.act16_a = nullptr;
+    m->work.act16_b = nullptr;
+    m->work.w16 = nullptr;
+    if (precision == LPF_PREC_FP32) {
+        m->work.act_a = reinterpret_cast<float*>(p); p += act;
+        m->work.act_b = reinterpret_cast<float*>(p); p += act;
+    } else {
+        m->work.act16_a = p; p += act;
+        m->work.act16_b = p; p += act;
+        m->work.w16 = p; p += align64(kW16total * 2);
+    }
     m->work.part = reinterpret_cast<float*>(p);
     p += align64((size_t)kNSplit * pad32(maxb) * kHidden * sizeof(float));
     m->work.hidden = reinterpret_cast<float*>(p); p += align64((size_t)maxb * kHidden * sizeof(float));
@@ -377,6 +585,15 @@ int model_create(const void* weights, size_t bytes, int precision, int maxb, voi
     hipError_t e = hipMemcpyAsync(staging, weights, blob_floats() * sizeof(float), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_relayout, dim3(1024), dim3(256), 0, s, staging, m->wts, m->lay);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && precision == LPF_PREC_BF16) {
+        hipLaunchKernelGGL((k_to16<__bf16>), dim3(1024), dim3(256), 0, s, m->wts,
+                           static_cast<__bf16*>(m->work.w16), m->lay, kW16o2, kW16o3, kW16o4, kW16of1);
+        e = hipGetLastError();
+    } else if (e == hipSuccess && precision == LPF_PREC_FP16) {
+        hipLaunchKernelGGL((k_to16<_Float16>), dim3(1024), dim3(256), 0, s, m->wts,
+                           static_cast<_Float16*>(m->work.w16), m->lay, kW16o2, kW16o3, kW16o4, kW16of1);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);

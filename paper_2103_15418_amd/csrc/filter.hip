@@ -33,6 +33,23 @@ namespace {
 
 constexpr int R = 16;  // outputs per thread per pass
 
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+template <typename T> struct V8;
+template <> struct V8<__bf16> { typedef bf16x8 type; };
+template <> struct V8<_Float16> { typedef f16x8 type; };
+template <typename T>
+__device__ inline floatx4 mfma16(typename V8<T>::type a, typename V8<T>::type b, floatx4 c);
+template <>
+__device__ inline floatx4 mfma16<__bf16>(bf16x8 a, bf16x8 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+template <>
+__device__ inline floatx4 mfma16<_Float16>(f16x8 a, f16x8 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
 enum InMode { IN_MX = 0, IN_ME = 1, IN_W = 2, IN_WX = 3, IN_WE = 4, IN_M = 5 };
 enum OutMode {
     OUT_C_STATIC = 0,    // C = v * inv_den
@@ -217,6 +234,77 @@ __device__ inline void epilogue(const FiltArgs& a, int b, size_t bo, int gy, int
             a.Y_out[bo + p] = (y || old) ? 1 : 0;
             if (y && !old) a.changed[b] = 1;
         }
+    }
+}
+
+// NQ vertically consecutive outputs (rows gy0 .. gy0+NQ-1, column gx; only the
+// first nvalid inside the image).  All loads are issued before any store or
+// atomic so their latencies overlap; the common outputs run without branches.
+template <int OUT, int NQ>
+__device__ inline void epilogue_col(const FiltArgs& a, int b, size_t bo, int gy0, int gx, const float* v,
+                                    int nvalid) {
+    if (OUT == OUT_C_STATIC) {
+        float id[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) id[q] = q < nvalid ? a.inv_den[(size_t)(gy0 + q) * a.W + gx] : 0.0f;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+            if (q < nvalid) a.out[bo + (size_t)(gy0 + q) * a.W + gx] = v[q] * id[q];
+    } else if (OUT == OUT_S_PEAKS) {
+        float id[NQ], cv[NQ], xv[NQ];
+        bool mk[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const size_t p = (size_t)(gy0 + q) * a.W + gx;
+            const bool in = q < nvalid;
+            id[q] = in ? a.inv_den[p] : 0.0f;
+            cv[q] = in ? a.C[bo + p] : 0.0f;
+            xv[q] = in ? a.X[bo + p] : 0.0f;
+            mk[q] = in && (a.M ? a.M[p] != 0 : true);
+        }
+        bool y[NQ];
+        float s[NQ];
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            s[q] = v[q] * id[q];
+            y[q] = mk[q] && id[q] > 0.0f && xv[q] > cv[q] + a.kappa * sqrtf(s[q]);
+            any |= y[q];
+        }
+        if (a.S_out || a.Y_out || a.Y_out2) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                if (q >= nvalid) continue;
+                const size_t p = bo + (size_t)(gy0 + q) * a.W + gx;
+                if (a.S_out) a.S_out[p] = s[q];
+                if (a.Y_out) a.Y_out[p] = y[q] ? 1 : 0;
+                if (a.Y_out2) a.Y_out2[p] = y[q] ? 1 : 0;
+            }
+        }
+        if (any) {
+            for (int q = 0; q < NQ; ++q) {
+                if (!y[q]) continue;
+                const int gy = gy0 + q;
+                if (is_peak(a, bo, gy, gx, xv[q])) {
+                    const int idx = atomicAdd(&a.peak_cnt[b], 1);
+                    if (idx < a.peak_cap) {
+                        PeakRec rec;
+                        rec.band = b;
+                        rec.row = gy;
+                        rec.col = gx;
+                        rec.x = xv[q];
+                        rec.c = cv[q];
+                        rec.s = s[q];
+                        rec.sig = (xv[q] - cv[q]) / sqrtf(s[q]);
+                        a.peak_raw[(size_t)b * a.peak_cap + idx] = rec;
+                    }
+                }
+            }
+            if (a.changed) a.changed[b] = 1;
+        }
+    } else {
+        for (int q = 0; q < NQ; ++q)
+            if (q < nvalid) epilogue<OUT>(a, b, bo, gy0 + q, gx, v[q]);
     }
 }
 
@@ -411,11 +499,127 @@ __global__ __launch_bounds__(kThreads2) void k_filter_fast(FiltArgs a, Taps tp) 
     }
     const int gx = x0 + c;
     if (gx >= a.W) return;
+    // quarters of 4 outputs keep the epilogue's registers below the filter's
+    constexpr int EQ = 4;
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-        const int gy = y0 + rb * R + q;
-        if (gy >= a.H) break;
-        epilogue<OUT>(a, b, bo, gy, gx, acc[q]);
+    for (int hf = 0; hf < R / EQ; ++hf) {
+        const int gy0 = y0 + rb * R + EQ * hf;
+        const int nv = a.H - gy0 < EQ ? (a.H - gy0 > 0 ? a.H - gy0 : 0) : EQ;
+        epilogue_col<OUT, EQ>(a, b, bo, gy0, gx, acc + EQ * hf, nv);
+    }
+}
+
+// 16-bit precision form (bf16 / fp16 operands, float32 accumulation): both
+// passes of the separable filter as banded matrix products on
+// v_mfma_f32_16x16x32.  For a 16 x 16 output block the row pass is
+// In[16 rows][k] x T[k][16], T[k][n] = g[k - n] (0 <= k - n <= 2K), k over the
+// 16 + 2K input columns; the column pass is T'[16][k] x RR[k][16] over 16 + 2K
+// input rows with the same band.  The taps live in registers for the whole
+// tile; the row results are stored transposed (column-major, 16-bit) in LDS
+// so each lane's 8 consecutive rows are one 16-byte read.  The epilogue
+// (normalisation, threshold, peaks) is the float32 one.
+template <typename T, int K, int IN, int OUT>
+__global__ __launch_bounds__(kThreads2) void k_filter_mfma(FiltArgs a, Taps tp) {
+    typedef typename V8<T>::type vec;
+    constexpr int TH = kTH2, TW = kTileW;
+    constexpr int NKS = (16 + 2 * K + 31) / 32;                 // 32-wide k steps per block
+    constexpr int RNEED = (TH + 2 * K + 15) / 16 * 16;
+    constexpr int RCOL = TH - 16 + 32 * NKS;                    // rows the column pass reads
+    constexpr int RIN = RNEED > RCOL ? RNEED : RCOL;            // row-pass rows (multiple of 16)
+    constexpr int RS = RIN + 8;                                 // LDS stride (elements)
+    // fp16 has a narrow range: squared residuals are scaled by 2^-8 and back
+    constexpr bool SCALE = sizeof(T) == 2 && !__is_same(T, __bf16) && IN == IN_ME;
+    __shared__ T rrt[TW * RS];
+    const int nt = a.tiles_x * a.tiles_y;
+    const int lin = xcd_remap(blockIdx.x, gridDim.x);
+    const int b = lin / nt;
+    const int tile = lin % nt;
+    if (a.rej && ((*a.rej >> b) & 1u)) return;
+    const int ty = tile / a.tiles_x, tx = tile % a.tiles_x;
+    const int y0 = ty * TH, x0 = tx * TW;
+    const size_t bo = (size_t)b * a.H * a.W;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int li = lane & 15, lg = lane >> 4;
+    vec tv[NKS];
+#pragma unroll
+    for (int st = 0; st < NKS; ++st) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int idx = 32 * st + 8 * lg + e - li;
+            tv[st][e] = (T)((idx >= 0 && idx <= 2 * K) ? tp.g[idx] : 0.0f);
+        }
+    }
+    // ---- row pass
+    for (int blk = wave; blk < (RIN / 16) * (TW / 16); blk += kThreads2 / 64) {
+        const int rb = blk / (TW / 16), cb = blk % (TW / 16);
+        const int gy = y0 - K + rb * 16 + li;
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const bool rowin = gy >= 0 && gy < a.H;
+        const size_t rowoff = (size_t)(rowin ? gy : 0) * a.W;
+#pragma unroll
+        for (int st = 0; st < NKS; ++st) {
+            const int c0 = x0 + cb * 16 - K + 32 * st + 8 * lg;  // 8 consecutive input columns
+            float e8[8];
+            uint32_t mb = 0xffu;
+            if (a.mbits && rowin) {
+                const int w0 = c0 >> 5;
+                const uint32_t lo = (w0 >= 0 && w0 < a.mwords) ? a.mbits[(size_t)gy * a.mwords + w0] : 0u;
+                const uint32_t hi = (w0 + 1 >= 0 && w0 + 1 < a.mwords) ? a.mbits[(size_t)gy * a.mwords + w0 + 1] : 0u;
+                const uint64_t both = ((uint64_t)hi << 32) | lo;
+                mb = (uint32_t)(both >> (c0 & 31)) & 0xffu;
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int g4 = c0 + 4 * h;
+                if (rowin && g4 >= 0 && g4 + 3 < a.W) {
+                    if (K % 4 == 0) {
+                        load_group<IN>(a, bo, rowoff, g4, (mb >> (4 * h)) & 0xFu, e8 + 4 * h);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const size_t p = rowoff + g4 + q;
+                            const float m = (float)((mb >> (4 * h + q)) & 1u);
+                            const float x = a.X[bo + p];
+                            if (IN == IN_MX) {
+                                e8[4 * h + q] = m * x;
+                            } else {
+                                const float r = x - a.C[bo + p];
+                                e8[4 * h + q] = m * r * r;
+                            }
+                        }
+                    }
+                } else {
+                    e8[4 * h] = e8[4 * h + 1] = e8[4 * h + 2] = e8[4 * h + 3] = 0.0f;
+                }
+            }
+            vec av;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) av[e] = (T)(SCALE ? e8[e] * (1.0f / 256.0f) : e8[e]);
+            acc = mfma16<T>(av, tv[st], acc);
+        }
+        // acc[v] = RR[row rb*16 + 4 lg + v][col cb*16 + li] -> transposed LDS
+        T* d = rrt + (cb * 16 + li) * RS + rb * 16 + 4 * lg;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) d[v] = (T)acc[v];
+    }
+    __syncthreads();
+    // ---- column pass + epilogue
+    for (int blk = wave; blk < (TH / 16) * (TW / 16); blk += kThreads2 / 64) {
+        const int ob = blk / (TW / 16), cb = blk % (TW / 16);
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        const T* src = rrt + (cb * 16 + li) * RS + ob * 16 + 8 * lg;
+#pragma unroll
+        for (int st = 0; st < NKS; ++st) {
+            const vec bv = *reinterpret_cast<const vec*>(src + 32 * st);
+            acc = mfma16<T>(tv[st], bv, acc);
+        }
+        const int gx = x0 + cb * 16 + li;
+        if (gx >= a.W) continue;
+        const int gy0 = y0 + ob * 16 + 4 * lg;
+        float vv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) vv[v] = SCALE ? acc[v] * 256.0f : acc[v];
+        epilogue_col<OUT, 4>(a, b, bo, gy0, gx, vv, a.H - gy0 < 4 ? (a.H - gy0 > 0 ? a.H - gy0 : 0) : 4);
     }
 }
 
@@ -492,8 +696,31 @@ hipError_t run_fast(lpf_ctx* c, FiltArgs a, int nbands) {
     return hipGetLastError();
 }
 
+template <typename T, int K, int IN, int OUT>
+hipError_t run_mfma(lpf_ctx* c, FiltArgs a, int nbands) {
+    a.tiles_y = (a.H + kTH2 - 1) / kTH2;
+    const int nblocks = a.tiles_x * a.tiles_y * nbands;
+    hipLaunchKernelGGL((k_filter_mfma<T, K, IN, OUT>), dim3(nblocks), dim3(kThreads2), 0, c->stream, a,
+                       c->taps);
+    return hipGetLastError();
+}
+
+template <typename T, int IN, int OUT>
+hipError_t dispatch_mfma(lpf_ctx* c, const FiltArgs& a, int nbands) {
+    switch (c->d.k) {
+        case 15: return run_mfma<T, 15, IN, OUT>(c, a, nbands);
+        case 24: return run_mfma<T, 24, IN, OUT>(c, a, nbands);
+        case 36: return run_mfma<T, 36, IN, OUT>(c, a, nbands);
+        default: return hipErrorInvalidValue;  // configuration validation prevents this
+    }
+}
+
 template <int IN, int OUT>
 hipError_t dispatch_k(lpf_ctx* c, const FiltArgs& a, int nbands) {
+    if ((IN == IN_MX || IN == IN_ME) && c->cfg.filter_precision == LPF_PREC_BF16)
+        return dispatch_mfma<__bf16, IN, OUT>(c, a, nbands);
+    if ((IN == IN_MX || IN == IN_ME) && c->cfg.filter_precision == LPF_PREC_FP16)
+        return dispatch_mfma<_Float16, IN, OUT>(c, a, nbands);
     if (a.W % 4 == 0) {
         switch (c->d.k) {
             case 15: return run_fast<15, IN, OUT>(c, a, nbands);
