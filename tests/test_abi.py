@@ -42,7 +42,8 @@ def test_config_validation_host_only():
     # cache (33 cubes) + Welford (4 planes) + centre dominate: > 37 planes of 64 MiB
     assert n > 37 * 64 * 2 ** 20
     for bad in (dict(B=17), dict(B=0), dict(H=5000), dict(ring_len=32), dict(clip_iters=0),
-                dict(peak_cap=600), dict(bg_halfwidth=41), dict(filter_precision=1),
+                dict(peak_cap=600), dict(bg_halfwidth=41), dict(filter_precision=3),
+                dict(filter_precision=1, clip_iters=2), dict(filter_precision=2, bg_halfwidth=10),
                 dict(max_sources=0), dict(peak_halfwidth=0)):
         c = P.default_config(16, 1024, 1024)
         for k, v in bad.items():
