@@ -119,6 +119,64 @@ def precision_errors(code, st, pool, Context, Model, synth):
             "network_L": [float(en[:, 4:].max()), float(np.median(en[:, 4:]))]}
 
 
+def _gen_serving_frame(args):
+    k, t = args
+    import synth
+    spec = synth.spec_serving_streams()[k]
+    return (k, t), synth.Stream(spec).frame(t)
+
+
+def serving(args, precision, pools, specs, masks, seconds, cadence_s, jitter_s, seed=0):
+    """Serving form: all streams admitted under the HBM budget, frames arriving at
+    cadence_s +- jitter_s per stream for `seconds`; returns latency statistics."""
+    import threading
+
+    import torch
+    import synth
+    from paper_2103_15418_amd import Model, Server, now_ns, workspace_size, default_config
+    model = Model(synth.cnn_weights(), precision=precision, max_batch=1024)
+    budget = int(args.serve_budget_gb * 2 ** 30)
+    srv = Server(model, budget)
+    sids = [srv.admit(s.B, s.H, s.W, sky_mask=m, filter_precision=precision) for s, m in zip(specs, masks)]
+    used, _, _ = srv.usage()
+    n_steps = max(1, int(round(seconds / cadence_s)))
+    rng = np.random.default_rng(seed)
+    t0 = now_ns() + int(0.05e9)
+    arrivals = []
+    for k, sid in enumerate(sids):
+        for t in range(n_steps):
+            arrivals.append((t0 + int((t * cadence_s + rng.uniform(-jitter_s, jitter_s)) * 1e9), k, t))
+    arrivals.sort()
+
+    def submitter():
+        for when, k, t in arrivals:
+            while True:
+                d = when - now_ns()
+                if d <= 0:
+                    break
+                time.sleep(min(d, 2e6) / 1e9)
+            srv.submit(sids[k], t, pools[k][t % len(pools[k])], arrival_ns=when)
+
+    th = threading.Thread(target=submitter)
+    wall0 = time.perf_counter()
+    th.start()
+    th.join()
+    srv.drain()
+    wall = time.perf_counter() - wall0
+    res = srv.poll(cap=len(arrivals) + 16)
+    srv.close_all()
+    lat = (res["done_ns"] - res["arrival_ns"]) / 1e6
+    px = sum(specs[int(r["stream_id"])].B * specs[int(r["stream_id"])].H * specs[int(r["stream_id"])].W
+             for r in res)
+    return {"streams": len(sids), "frames": int(len(res)), "cadence_s": cadence_s, "jitter_s": jitter_s,
+            "seconds": seconds, "errors": int(np.sum(res["status"] != 0)),
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "max": float(lat.max())},
+            "deadline_met": float(np.mean(lat < cadence_s * 1e3)),
+            "subband_px_per_s": px / wall, "workspace_gb": used / 2 ** 30,
+            "budget_gb": args.serve_budget_gb}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +187,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--no-precision-forms", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="real-time serving run (1 s cadence +- 100 ms); 600 reproduces the full scenario")
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, copy 256 MiB device-to-device once (reference for HBM counters)")
     args = ap.parse_args()
@@ -256,6 +318,30 @@ def main():
                            "windows_inferred": nw}
             forms[name]["error_vs_fp64"] = precision_errors(code, st, pool, Context, Model, synth)
         out["precision_forms"] = forms
+    if not args.no_serving:
+        del pool
+        torch.cuda.empty_cache()
+        specs = synth.spec_serving_streams()
+        masks = [synth.sky_mask(s.H, s.W) for s in specs]
+        n_distinct = 3
+        print(f"[bench] serving: generating {n_distinct} cubes for each of {len(specs)} streams",
+              file=sys.stderr, flush=True)
+        jobs = [(k, t) for k in range(len(specs)) for t in range(n_distinct)]
+        if args.workers > 1:
+            with mp.get_context("fork").Pool(args.workers) as gp:
+                gen = dict(gp.imap_unordered(_gen_serving_frame, jobs))
+        else:
+            gen = dict(_gen_serving_frame(j) for j in jobs)
+        pools = [[torch.from_numpy(gen[(k, t)]).cuda() for t in range(n_distinct)] for k in range(len(specs))]
+        del gen
+        serve = {}
+        print(f"[bench] serving: real time, {args.serve_seconds:.0f} s", file=sys.stderr, flush=True)
+        serve["realtime_fp32"] = serving(args, 0, pools, specs, masks, args.serve_seconds, 1.0, 0.1)
+        for code, name in ((0, "fp32"), (1, "bf16")):
+            print(f"[bench] serving: {name} at 100x the cadence", file=sys.stderr, flush=True)
+            serve[f"stress_{name}"] = serving(args, code, pools, specs, masks, 2.0, 0.01, 0.001, seed=1)
+        out["serving"] = serve
+        del pools
     if args.calibrate_copy:
         src = torch.ones(64 * 2 ** 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -242,6 +242,58 @@ int lpf_profile_read(lpf_ctx* ctx, double* ms, int64_t* counts);
 int lpf_sync(lpf_ctx* ctx);
 const char* lpf_last_error(const lpf_ctx* ctx);
 
+/* ---- serving loop -----------------------------------------------------------
+ * Several image streams of different shapes served concurrently on one GPU
+ * (Sec. 3.5: the pipeline must keep up with the 1 s cadence of the stream).
+ * A dispatcher thread owned by the server takes frames in arrival order and
+ * launches each on its stream's own HIP stream as soon as that stream's
+ * previous frame is done, so work of different streams overlaps on the
+ * device; the network runs once per dispatch round on the episodes that ended
+ * in all streams whose frames completed (pooled batch).  Streams are admitted
+ * while the sum of their workspaces fits the HBM budget; closing a stream
+ * frees its memory for later admissions.  Server memory (workspaces, HIP
+ * streams) is allocated by the server and released by close / destroy. */
+typedef struct lpf_server lpf_server;
+
+typedef struct {
+    int32_t stream_id;
+    int64_t t;
+    int64_t arrival_ns, done_ns; /* host steady clock, as given / measured     */
+    uint32_t rejected_bands;
+    int32_t n_peaks, n_new, n_ended;
+    int32_t status;              /* LPF_OK or the error of this frame           */
+} lpf_frame_result;
+
+/* model: network for the pooled inference (not owned).  record != 0 keeps
+ * every frame's peaks, events and inference outputs for lpf_server_fetch
+ * (tests; adds synchronisation per frame). */
+int lpf_server_create(const lpf_model* model, size_t hbm_budget_bytes, int32_t record, lpf_server** out);
+void lpf_server_destroy(lpf_server* srv);
+/* Admits a stream if its workspace fits the remaining budget (LPF_ENOMEM
+ * otherwise, nothing allocated).  *stream_id: handle for submit / close. */
+int lpf_server_admit(lpf_server* srv, const lpf_config* cfg, int32_t* stream_id);
+/* Waits for the stream's submitted frames, destroys it and frees its memory. */
+int lpf_server_close(lpf_server* srv, int32_t stream_id);
+/* Queues one frame.  cube: [B][H][W] float32 (device memory if on_device);
+ * it must stay valid until the frame is reported done.  arrival_ns: the
+ * frame's arrival time on the host steady clock (latency origin). */
+int lpf_server_submit(lpf_server* srv, int32_t stream_id, int64_t t, const float* cube, int32_t on_device,
+                      int64_t arrival_ns);
+/* Completed frames since the last poll (at most cap); non-blocking. */
+int lpf_server_poll(lpf_server* srv, lpf_frame_result* out, int32_t cap, int32_t* n);
+/* Blocks until every submitted frame is done. */
+int lpf_server_drain(lpf_server* srv);
+/* Recorded outputs of frame (stream_id, t) (record mode): peaks in (band,
+ * row, col) order, events as lpf_detect, inference rows (mu [4], L [10], id)
+ * for the episodes that ended at t.  Any output pointer may be NULL. */
+int lpf_server_fetch(lpf_server* srv, int32_t stream_id, int64_t t, lpf_peak* peaks, int32_t peak_cap,
+                     int32_t* n_peaks, lpf_source* events, int32_t ev_cap, int32_t* n_events, float* mu,
+                     float* L, int32_t* ids, int32_t inf_cap, int32_t* n_inf);
+/* Bytes of budget in use / workspace bytes a configuration would need. */
+int lpf_server_usage(const lpf_server* srv, size_t* used, size_t* budget, int32_t* n_streams);
+/* Host time server steady clock (ns), for arrival stamps. */
+int64_t lpf_now_ns(void);
+
 #ifdef __cplusplus
 }
 #endif

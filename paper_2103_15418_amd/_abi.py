@@ -102,6 +102,17 @@ def lib() -> C.CDLL:
         "lpf_profile_enable": (i32, [vp, i32]),
         "lpf_profile_read": (i32, [vp, vp, vp]),
         "lpf_last_error": (C.c_char_p, [vp]),
+        "lpf_server_create": (i32, [vp, sz, i32, C.POINTER(vp)]),
+        "lpf_server_destroy": (None, [vp]),
+        "lpf_server_admit": (i32, [vp, C.POINTER(Config), C.POINTER(i32)]),
+        "lpf_server_close": (i32, [vp, i32]),
+        "lpf_server_submit": (i32, [vp, i32, i64, vp, i32, i64]),
+        "lpf_server_poll": (i32, [vp, vp, i32, C.POINTER(i32)]),
+        "lpf_server_drain": (i32, [vp]),
+        "lpf_server_fetch": (i32, [vp, i32, i64, vp, i32, C.POINTER(i32), vp, i32, C.POINTER(i32),
+                                   vp, vp, vp, i32, C.POINTER(i32)]),
+        "lpf_server_usage": (i32, [vp, C.POINTER(sz), C.POINTER(sz), C.POINTER(i32)]),
+        "lpf_now_ns": (i64, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -332,3 +343,110 @@ class Model:
         if rc != LPF_OK:
             raise LpfError(rc, "infer_windows")
         return mu, L
+
+
+FRAME_DTYPE = np.dtype([("stream_id", "<i4"), ("pad0", "<i4"), ("t", "<i8"), ("arrival_ns", "<i8"),
+                        ("done_ns", "<i8"), ("rejected_bands", "<u4"), ("n_peaks", "<i4"),
+                        ("n_new", "<i4"), ("n_ended", "<i4"), ("status", "<i4"), ("pad1", "<i4")])
+
+
+def now_ns() -> int:
+    return int(lib().lpf_now_ns())
+
+
+class Server:
+    """Serving loop over several streams (see include/lpf.h).  Frames handed
+    to submit() must stay alive until reported done; the server keeps a
+    reference to torch tensors until then."""
+
+    def __init__(self, model: "Model", hbm_budget_bytes: int, record: bool = False):
+        h = C.c_void_p()
+        rc = lib().lpf_server_create(model.h, int(hbm_budget_bytes), 1 if record else 0, C.byref(h))
+        if rc != LPF_OK:
+            raise LpfError(rc, "lpf_server_create")
+        self.h = h
+        self.model = model
+        self._keep = {}
+        self._masks = []
+
+    def close_all(self):
+        if getattr(self, "h", None) is not None:
+            lib().lpf_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
+
+    def __del__(self):
+        self.close_all()
+
+    def admit(self, B: int, H: int, W: int, sky_mask=None, grid_rows=None, **params) -> int:
+        cfg = default_config(B, H, W, **params)
+        keep = []
+        if sky_mask is not None:
+            m = np.ascontiguousarray(sky_mask, dtype=np.uint8)
+            keep.append(m)
+            cfg.sky_mask = m.ctypes.data
+        if grid_rows is not None:
+            r = np.ascontiguousarray(grid_rows, dtype=np.int32)
+            keep.append(r)
+            cfg.grid_rows = r.ctypes.data
+        sid = C.c_int32(-1)
+        rc = lib().lpf_server_admit(self.h, C.byref(cfg), C.byref(sid))
+        if rc != LPF_OK:
+            raise LpfError(rc, "admit")
+        return int(sid.value)
+
+    def close(self, sid: int):
+        rc = lib().lpf_server_close(self.h, int(sid))
+        if rc != LPF_OK:
+            raise LpfError(rc, "close")
+        for key in [k for k in self._keep if k[0] == sid]:
+            del self._keep[key]
+
+    def submit(self, sid: int, t: int, cube, arrival_ns: Optional[int] = None):
+        torch = _torch()
+        if isinstance(cube, torch.Tensor):
+            assert cube.is_cuda and cube.dtype == torch.float32 and cube.is_contiguous()
+            ptr, on_dev = cube.data_ptr(), 1
+        else:
+            cube = np.ascontiguousarray(cube, dtype=np.float32)
+            ptr, on_dev = cube.ctypes.data, 0
+        self._keep[(sid, int(t))] = cube
+        rc = lib().lpf_server_submit(self.h, int(sid), int(t), C.c_void_p(ptr), on_dev,
+                                     int(arrival_ns if arrival_ns is not None else now_ns()))
+        if rc != LPF_OK:
+            raise LpfError(rc, "submit")
+
+    def poll(self, cap: int = 4096) -> np.ndarray:
+        out = np.zeros(cap, dtype=FRAME_DTYPE)
+        n = C.c_int32(0)
+        rc = lib().lpf_server_poll(self.h, C.c_void_p(out.ctypes.data), cap, C.byref(n))
+        if rc != LPF_OK:
+            raise LpfError(rc, "poll")
+        res = out[:n.value].copy()
+        for r in res:
+            self._keep.pop((int(r["stream_id"]), int(r["t"])), None)
+        return res
+
+    def drain(self):
+        lib().lpf_server_drain(self.h)
+
+    def fetch(self, sid: int, t: int, peak_cap: int = 8192, ev_cap: int = 16384, inf_cap: int = 16384):
+        peaks = np.zeros(peak_cap, dtype=PEAK_DTYPE)
+        ev = np.zeros(ev_cap, dtype=SOURCE_DTYPE)
+        mu = np.zeros((inf_cap, 4), dtype=np.float32)
+        L = np.zeros((inf_cap, 10), dtype=np.float32)
+        ids = np.zeros(inf_cap, dtype=np.int32)
+        np_, ne, ni = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        rc = lib().lpf_server_fetch(self.h, int(sid), int(t), C.c_void_p(peaks.ctypes.data), peak_cap,
+                                    C.byref(np_), C.c_void_p(ev.ctypes.data), ev_cap, C.byref(ne),
+                                    C.c_void_p(mu.ctypes.data), C.c_void_p(L.ctypes.data),
+                                    C.c_void_p(ids.ctypes.data), inf_cap, C.byref(ni))
+        if rc != LPF_OK:
+            raise LpfError(rc, "fetch")
+        return (peaks[:np_.value].copy(), ev[:ne.value].copy(), mu[:ni.value].copy(),
+                L[:ni.value].copy(), ids[:ni.value].copy())
+
+    def usage(self):
+        u, b, n = C.c_size_t(0), C.c_size_t(0), C.c_int32(0)
+        lib().lpf_server_usage(self.h, C.byref(u), C.byref(b), C.byref(n))
+        return int(u.value), int(b.value), int(n.value)

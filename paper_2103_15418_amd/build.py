@@ -19,7 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblpf.so")
-SOURCES = ["api.cpp", "ingest.hip", "filter.hip", "catalog.hip", "flux.hip", "cnn.hip"]
+SOURCES = ["api.cpp", "serve.cpp", "ingest.hip", "filter.hip", "catalog.hip", "flux.hip", "cnn.hip"]
 ARCH = os.environ.get("LPF_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -55,7 +55,7 @@ def build(verbose: bool = False, jobs: int = 6) -> str:
     if failed:
         raise RuntimeError("HIP build failed: " + ", ".join(failed))
     tmp_lib = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp_lib, *objs]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp_lib, *objs, "-lpthread"]
     subprocess.run(cmd, check=True)
     os.replace(tmp_lib, LIB)
     return LIB

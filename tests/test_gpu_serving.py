@@ -1,0 +1,121 @@
+"""Serving loop: several streams of uneven shape and band count served
+together.  Each stream's peaks, events and network outputs must be the same
+alone and in the mix (bitwise: every stream's kernels are independent and the
+network computes each window independently of its batch), admission follows
+the HBM budget, and the served peaks obey the oracle's bracketing rule."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.config import OracleConfig
+from oracle.pipeline import OracleStream
+
+from parity import check_peaks_bracket
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def small_specs(T):
+    out = []
+    for k, (b, h, w, mask) in enumerate([(4, 128, 128, False), (8, 160, 192, True), (16, 128, 96, False)]):
+        out.append(synth.StreamSpec(
+            name=f"mix{k}", B=b, H=h, W=w, T=T,
+            freqs_mhz=(synth.two_group_freqs(b) if b in (8, 16) else np.linspace(60, 70, b)),
+            n_sources=3, amp=(15.0, 20.0), dm=(0.0, 30.0), width_choices=(2,), t0=(2.0, 6.0),
+            integer_centres=True, place_box=(24, min(h, w) - 24), mask=mask, mask_shrink=24,
+            min_sep=20.0, seed=77 + k, cfg=5, stream=k))
+    return out
+
+
+def run_server(model, streams, frames, record=True, budget=1 << 36):
+    from paper_2103_15418_amd import Server
+    srv = Server(model, budget, record=record)
+    sids = []
+    for st in streams:
+        s = st.spec
+        sids.append(srv.admit(s.B, s.H, s.W, sky_mask=st.mask, monitor_steps=6, backfill_steps=6,
+                              kappa=6.0, qc_warmup=3))
+    T = len(frames[0])
+    stamp = 0
+    for t in range(T):                       # interleaved arrivals
+        for i, sid in enumerate(sids):
+            srv.submit(sid, t, frames[i][t], arrival_ns=stamp)
+            stamp += 1000
+    srv.drain()
+    res = srv.poll(cap=T * len(sids) + 8)
+    out = {}
+    for i, sid in enumerate(sids):
+        for t in range(T):
+            out[(i, t)] = srv.fetch(sid, t)
+    srv.close_all()
+    return out, res
+
+
+def test_each_stream_same_alone_and_in_the_mix():
+    torch = _torch_cuda()
+    from paper_2103_15418_amd import Model
+    T = 14
+    streams = [synth.Stream(s) for s in small_specs(T)]
+    frames = [[torch.from_numpy(st.frame(t)).cuda() for t in range(T)] for st in streams]
+    model = Model(synth.cnn_weights(seed=9), max_batch=16)
+    mix, res = run_server(model, streams, frames)
+    assert len(res) == T * len(streams) and np.all(res["status"] == 0)
+    n_inf = 0
+    for i, st in enumerate(streams):
+        alone, _ = run_server(model, [st], [frames[i]])
+        for t in range(T):
+            a = alone[(0, t)]
+            m = mix[(i, t)]
+            for x, y in zip(a, m):
+                assert x.shape == y.shape and x.tobytes() == y.tobytes(), (i, t)
+            n_inf += len(a[4])
+    assert n_inf > 0   # episodes ended and went through the network
+
+
+def test_served_peaks_follow_the_oracle():
+    torch = _torch_cuda()
+    from paper_2103_15418_amd import Model
+    T = 6
+    st = synth.Stream(small_specs(T)[1])
+    frames = [torch.from_numpy(st.frame(t)).cuda() for t in range(T)]
+    model = Model(synth.cnn_weights(seed=9), max_batch=16)
+    out, _ = run_server(model, [st], [frames])
+    s = st.spec
+    orc = OracleStream(OracleConfig(B=s.B, H=s.H, W=s.W, sky_mask=st.mask, kappa=6.0, n_mon=6, t_bf=6,
+                                    qc_warmup=3))
+    for t in range(T):
+        orc.ingest(t, frames[t].cpu().numpy())
+        peaks_o, new_o, ended_o = orc.detect()
+        orc.extract_flux()
+        check_peaks_bracket(out[(0, t)][0], orc.cache[t], orc.M, orc.g, 6.0, 3, orc.rejected[t], f"t={t}")
+        assert [int(e["id"]) for e in out[(0, t)][1]] == list(new_o) + list(ended_o)
+
+
+def test_admission_by_hbm_budget():
+    _torch_cuda()
+    from paper_2103_15418_amd import LpfError, Model, Server, default_config, workspace_size
+    model = Model(synth.cnn_weights(seed=9), max_batch=8)
+    shapes = [(16, 256, 256), (8, 192, 192), (16, 320, 320)]
+    sizes = [workspace_size(default_config(*sh)) for sh in shapes]
+    budget = sizes[0] + sizes[1] + sizes[2] - 1   # the third does not fit while both are held
+    srv = Server(model, budget)
+    a = srv.admit(*shapes[0])
+    srv.admit(*shapes[1])
+    with pytest.raises(LpfError) as err:
+        srv.admit(*shapes[2])
+    assert err.value.code == -2            # LPF_ENOMEM
+    used, bud, n = srv.usage()
+    assert used == sizes[0] + sizes[1] and n == 2 and bud == budget
+    srv.close(a)                           # memory freed -> the waiting stream fits
+    srv.admit(*shapes[2])
+    used, _, n = srv.usage()
+    assert used == sizes[1] + sizes[2] and n == 2
+    srv.close_all()
