@@ -219,16 +219,27 @@ def main():
         model = Model(synth.cnn_weights(), precision=precision, max_batch=1024)
         torch.cuda.synchronize()
         n_inf = [0]
+        pending = []
 
         def step(t):
+            # the network's results of step t are collected during step t + 1,
+            # so the host enqueues the next frame while the device finishes
             ctx.ingest(t, pool[t % n_pool])
             ctx.detect(want=False)
             ctx.extract_flux()
-            mu, L, src = model.infer([ctx])
-            n_inf[0] += len(mu)
+            pending.append(model.infer_async([ctx]))
+            if len(pending) > 1:
+                mu, L, src = model.collect(pending.pop(0))
+                n_inf[0] += len(mu)
+
+        def drain():
+            while pending:
+                mu, L, src = model.collect(pending.pop(0))
+                n_inf[0] += len(mu)
 
         for t in range(warmup):
             step(t)
+        drain()
         torch.cuda.synchronize()
         ctx.profile(True)
         ctx.profile_read()
@@ -240,6 +251,7 @@ def main():
             f0 = time.perf_counter()
             step(warmup + i)
             lat.append(time.perf_counter() - f0)
+        drain()
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         prof = ctx.profile_read()

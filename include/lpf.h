@@ -89,7 +89,7 @@ typedef struct {
     int32_t qc_warmup;        /* accepted frames before the pixel test arms     */
     int32_t max_sources;      /* source table capacity, 1..65536                */
     int32_t peak_cap;         /* per band per step; B * peak_cap <= 8192        */
-    int32_t filter_precision; /* LPF_PREC_FP32 (others reserved)                */
+    int32_t filter_precision; /* LPF_PREC_FP32, or BF16 / FP16 operands on MFMA  */
     int32_t debug_planes;     /* 1: also keep S (and the clip mask) readable    */
 } lpf_config;
 
@@ -186,7 +186,9 @@ int lpf_read_spectrum(lpf_ctx* ctx, int32_t source_id, float* out, uint8_t* vali
 size_t lpf_model_weights_bytes(void);
 
 /* Device workspace for a model of the given precision serving batches of up
- * to max_batch windows (larger requests are processed in chunks). */
+ * to max_batch windows (larger synchronous requests are processed in chunks).
+ * The model also allocates, once at creation, its inference stream, events
+ * and four pinned host result blocks of 16 max_batch + 4 words each. */
 int lpf_model_workspace_size(int32_t precision, int32_t max_batch, size_t* bytes);
 
 /* Uploads and re-lays-out the weights (host blob) into dev_workspace on
@@ -196,22 +198,46 @@ int lpf_model_create(const void* weights, size_t bytes, int32_t precision, int32
                      void* dev_workspace, size_t ws_bytes, void* hip_stream, lpf_model** out);
 void lpf_model_destroy(lpf_model* model);
 
-/* Runs the network on the dynamic spectra of sources of one or more
- * contexts, batched together, on the first context's stream.  source_ids:
- * NULL = every episode that ended at the context's last detect (all
- * contexts); else n_ids ids of ctxs[0] (n_ctx must be 1).  Outputs (host):
- * mu_out [N][4] (DM, width, amplitude, arrival), L_out [N][10] packed
- * row-major lower triangle with softplus diagonal, src_out [N][2]
- * (context index, source id); at most cap rows.  *n_out: rows written.
- * Synchronises. */
+/* Runs the network (Sec. 2.3.2-2.3.3) on the dynamic spectra (Sec. 2.2,
+ * Fig. 3) of sources of one or more contexts, batched together on the
+ * model's own inference stream (ordered after each context's stream by
+ * events).  source_ids: NULL = every episode that ended at the context's
+ * last detect (all contexts); else n_ids ids of ctxs[0] (n_ctx must be 1).
+ * Outputs (host): mu_out [N][4] (DM, width, amplitude, arrival), L_out
+ * [N][10] packed row-major lower triangle with softplus diagonal, src_out
+ * [N][2] (context index, source id), rows in (context, id) order for
+ * source_ids == NULL; at most cap rows.  *n_out: rows written.  Synchronises
+ * (once, on the results, when the ended episodes fit the model's batch). */
 int lpf_infer(lpf_ctx* const* ctxs, int32_t n_ctx, const lpf_model* model,
               const int32_t* source_ids, int32_t n_ids, float* mu_out, float* L_out,
               int32_t* src_out, int32_t cap, int32_t* n_out);
 
 /* The network alone on device windows: windows [n][16][64] float32, mu_out
- * [n][4], L_out [n][10] device float32.  Asynchronous on hip_stream. */
+ * [n][4], L_out [n][10] device float32.  Asynchronous with respect to the
+ * host; ordered after earlier work on hip_stream, and later work on
+ * hip_stream is ordered after it. */
 int lpf_infer_windows(const lpf_model* model, const float* windows, int32_t n, float* mu_out,
                       float* L_out, void* hip_stream);
+
+/* Asynchronous form of lpf_infer over the episodes that ended at the last
+ * detect of each context (Sec. 2.2 episode end -> Sec. 2.3 inference): the
+ * counts stay on the device, the windows are gathered there, the network
+ * runs on the model's stream and the results are copied into a pinned host
+ * slot; nothing waits.  Each context's later work is ordered after the
+ * gather, so the caller may ingest the next frame at once.  *ticket
+ * identifies the results for lpf_infer_collect.  At most 4 tickets may be
+ * outstanding per model (LPF_EFULL otherwise).  Episodes beyond the model's
+ * max_batch are not inferred; lpf_infer_collect reports them. */
+int lpf_infer_async(lpf_ctx* const* ctxs, int32_t n_ctx, lpf_model* model, int64_t* ticket);
+
+/* Waits for a ticket of lpf_infer_async and writes its rows as lpf_infer
+ * does (host outputs, (context, id) order, at most cap rows, *n_out rows).
+ * Returns LPF_EFULL when more episodes ended than the model's max_batch
+ * (the first max_batch in gather order were inferred), LPF_EINVAL for an
+ * unknown or already collected ticket.  Tickets may be collected in any
+ * order. */
+int lpf_infer_collect(lpf_model* model, int64_t ticket, float* mu_out, float* L_out, int32_t* src_out,
+                      int32_t cap, int32_t* n_out);
 
 /* ---- inspection (tests, diagnostics) ------------------------------------- */
 enum {

@@ -96,6 +96,8 @@ def lib() -> C.CDLL:
         "lpf_model_create": (i32, [vp, sz, i32, i32, vp, sz, vp, C.POINTER(vp)]),
         "lpf_model_destroy": (None, [vp]),
         "lpf_infer": (i32, [vp, i32, vp, vp, i32, vp, vp, vp, i32, C.POINTER(i32)]),
+        "lpf_infer_async": (i32, [vp, i32, vp, C.POINTER(C.c_int64)]),
+        "lpf_infer_collect": (i32, [vp, C.c_int64, vp, vp, vp, i32, C.POINTER(i32)]),
         "lpf_infer_windows": (i32, [vp, vp, i32, vp, vp, vp]),
         "lpf_debug_read": (i32, [vp, i32, vp, sz]),
         "lpf_sync": (i32, [vp]),
@@ -328,6 +330,31 @@ class Model:
                              C.c_void_p(L.ctypes.data), C.c_void_p(src.ctypes.data), cap, C.byref(n))
         if rc != LPF_OK:
             raise LpfError(rc, f"infer: {lib().lpf_last_error(ctxs[0].h).decode()}")
+        k = n.value
+        return mu[:k].copy(), L[:k].copy(), src[:k].copy()
+
+    def infer_async(self, ctxs: List[Context]) -> int:
+        """Enqueues inference over the episodes that ended at each context's
+        last detect; returns a ticket for collect() (nothing waits)."""
+        arr = (C.c_void_p * len(ctxs))(*[c.h for c in ctxs])
+        t = C.c_int64(-1)
+        rc = lib().lpf_infer_async(arr, len(ctxs), self.h, C.byref(t))
+        if rc != LPF_OK:
+            raise LpfError(rc, f"infer_async: {lib().lpf_last_error(ctxs[0].h).decode()}")
+        return int(t.value)
+
+    def collect(self, ticket: int, cap: Optional[int] = None, strict: bool = True):
+        """Waits for a ticket; returns (mu, L, src) as infer() does.  With
+        strict=False an overflow of the model's batch is returned, not raised."""
+        cap = self.max_batch if cap is None else cap
+        mu = np.zeros((cap, 4), dtype=np.float32)
+        L = np.zeros((cap, 10), dtype=np.float32)
+        src = np.zeros((cap, 2), dtype=np.int32)
+        n = C.c_int32(0)
+        rc = lib().lpf_infer_collect(self.h, int(ticket), C.c_void_p(mu.ctypes.data), C.c_void_p(L.ctypes.data),
+                                     C.c_void_p(src.ctypes.data), cap, C.byref(n))
+        if rc != LPF_OK and (strict or rc != LPF_EFULL):
+            raise LpfError(rc, "collect")
         k = n.value
         return mu[:k].copy(), L[:k].copy(), src[:k].copy()
 

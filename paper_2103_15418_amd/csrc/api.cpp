@@ -13,14 +13,18 @@
 
 namespace lpf {
 hipError_t launch_windows_gather(lpf_ctx* c, int n, const int32_t* d_slots, const int64_t* d_tend,
-                                 float* d_out);
+                                 float* d_out, hipStream_t s);
 hipError_t launch_ended_ends(lpf_ctx* c, int32_t* slots_out, int64_t* tend_out);
-hipError_t cnn_forward(const lpf_model* m, const float* windows, int n, float* mu, float* L,
-                       hipStream_t s);
+hipError_t cnn_forward(const lpf_model* m, const float* windows, const int* n_dev, int n_cap, float* mu,
+                       float* L, hipStream_t s);
+hipError_t launch_gather_begin(int32_t* hdr, hipStream_t s);
+hipError_t launch_gather_ended(lpf_ctx* c, int ci, int32_t* hdr, float* out, int32_t* rows, int cap,
+                               hipStream_t s);
 float* model_window_buffer(const lpf_model* m);
 float* model_mu_buffer(const lpf_model* m);
 float* model_L_buffer(const lpf_model* m);
 int model_max_batch(const lpf_model* m);
+float* model_host_rows(const lpf_model* m, size_t n);
 size_t model_blob_bytes();
 int model_workspace_size(int precision, int maxb, size_t* bytes);
 int model_create(const void* weights, size_t bytes, int precision, int maxb, void* ws, size_t ws_bytes,
@@ -95,6 +99,7 @@ Derived derive(const lpf_config* c) {
     d.masked = c->sky_mask != nullptr;
     d.dyn = c->clip_iters > 1 || c->debug_planes != 0;
     d.mwords = (c->W + 31) / 32;
+    d.strip = c->filter_precision == LPF_PREC_FP32 && c->W % 4 == 0 && (d.k == 15 || d.k == 24 || d.k == 36);
     size_t nb = (d.HW + 8191) / 8192;  // ~8K pixels per ingest block
     if (nb < 1) nb = 1;
     d.nblk = (int)nb;
@@ -116,6 +121,7 @@ size_t carve(const lpf_config* c, const Derived& d, char* base, DevBufs* b) {
     b->mask_bits = cv.take<uint32_t>((size_t)c->H * d.mwords);
     b->inv_den = cv.take<float>(d.HW);
     b->centre = cv.take<float>(d.plane);
+    b->resid = d.strip ? cv.take<float>(d.plane) : nullptr;
     b->spread = d.dyn ? cv.take<float>(d.plane) : nullptr;
     b->clip = d.dyn ? cv.take<uint8_t>(2 * d.plane) : nullptr;
     b->den = c->clip_iters > 1 ? cv.take<float>(d.plane) : nullptr;
@@ -305,6 +311,7 @@ void lpf_destroy(lpf_ctx* c) {
     if (!c) return;
     if (!c->poisoned) (void)hipStreamSynchronize(c->stream);
     for (auto& e : c->prof_pool) (void)hipEventDestroy(e);
+    if (c->ev_ready) (void)hipEventDestroy(c->ev_ready);
     delete c;
 }
 
@@ -333,6 +340,7 @@ int lpf_ingest_frame(lpf_ctx* c, int64_t t, const float* cube, int32_t on_device
     c->t_last = t;
     c->n_frames++;
     c->phase = 1;
+    c->host_n_ended = -1;
     if (rej_out) {
         uint32_t r = 0;
         LPF_HIP(c, hipMemcpyAsync(&r, &c->buf.status->rejected, sizeof(r), hipMemcpyDeviceToHost, c->stream),
@@ -360,6 +368,7 @@ int lpf_detect(lpf_ctx* c, lpf_peak* peaks, int32_t cap, int32_t* n_peaks, lpf_s
     DevStatus st;
     LPF_HIP(c, hipMemcpyAsync(&st, c->buf.status, sizeof(st), hipMemcpyDeviceToHost, c->stream), "detect D2H");
     LPF_HIP(c, hipStreamSynchronize(c->stream), "detect sync");
+    c->host_n_ended = st.n_ended;
     if (n_peaks) *n_peaks = st.n_peaks;
     if (peaks && cap > 0 && st.n_peaks > 0) {
         const int n = std::min(cap, st.n_peaks);
@@ -371,9 +380,14 @@ int lpf_detect(lpf_ctx* c, lpf_peak* peaks, int32_t cap, int32_t* n_peaks, lpf_s
         std::vector<lpf_source> tmp(nev);
         LPF_HIP(c, hipMemcpy(tmp.data(), c->buf.events, nev * sizeof(lpf_source), hipMemcpyDeviceToHost),
                 "events D2H");
+        c->host_ended_ids.resize(st.n_ended);
+        for (int k = 0; k < st.n_ended; ++k) c->host_ended_ids[k] = tmp[st.n_new + k].id;
         std::sort(tmp.begin() + st.n_new, tmp.end(),
                   [](const lpf_source& a, const lpf_source& b) { return a.id < b.id; });
         std::memcpy(events, tmp.data(), std::min(ev_cap, nev) * sizeof(lpf_source));
+    } else {
+        c->host_ended_ids.clear();
+        if (st.n_ended > 0) c->host_n_ended = -1;   // ids not read: inference reads them itself
     }
     if (st.overflow_bands || st.n_dropped) return fail(c, LPF_EFULL, "peak or source capacity reached");
     return LPF_OK;
@@ -541,15 +555,87 @@ void lpf_model_destroy(lpf_model* m) { model_destroy(m); }
 
 int lpf_infer_windows(const lpf_model* m, const float* windows, int32_t n, float* mu, float* L, void* stream) {
     if (!m || (n > 0 && (!windows || !mu || !L)) || n < 0) return LPF_EINVAL;
+    if (n == 0) return LPF_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int mb = model_max_batch(m);
+    const int mb = m->max_batch;
+    // the model's buffers are used in order on its own stream, between two events
+    if (hipEventRecord(m->ev_in, s) != hipSuccess) return LPF_EDEVICE;
+    if (hipStreamWaitEvent(m->istream, m->ev_in, 0) != hipSuccess) return LPF_EDEVICE;
     for (int i = 0; i < n; i += mb) {
         const int cnt = std::min(mb, n - i);
-        hipError_t e = cnn_forward(m, windows + (size_t)i * kGridRows * kRing, cnt, mu + (size_t)i * 4,
-                                   L + (size_t)i * 10, s);
+        hipError_t e = cnn_forward(m, windows + (size_t)i * kGridRows * kRing, nullptr, cnt, mu + (size_t)i * 4,
+                                   L + (size_t)i * 10, m->istream);
         if (e != hipSuccess) return LPF_EDEVICE;
     }
+    if (hipEventRecord(m->ev_out, m->istream) != hipSuccess) return LPF_EDEVICE;
+    if (hipStreamWaitEvent(s, m->ev_out, 0) != hipSuccess) return LPF_EDEVICE;
     return LPF_OK;
+}
+
+int lpf_infer_async(lpf_ctx* const* ctxs, int32_t n_ctx, lpf_model* m, int64_t* ticket) {
+    if (!ctxs || n_ctx < 1 || !m || !ticket) return LPF_EINVAL;
+    for (int i = 0; i < n_ctx; ++i) {
+        LPF_CHECK_CTX(ctxs[i]);
+        if (ctxs[i]->phase != 3) return fail(ctxs[i], LPF_ESTATE, "infer needs extract_flux first");
+    }
+    lpf_ctx* c0 = ctxs[0];
+    const int slot = (int)(m->next_ticket % kInflight);
+    if (m->slot_ticket[slot] >= 0) return fail(c0, LPF_EFULL, "too many inference tickets outstanding");
+    hipStream_t s = m->istream;
+    CnnWork& w = m->work;
+    // the contexts' streams hand over (flux and rings of this step are final)
+    for (int i = 0; i < n_ctx; ++i) {
+        lpf_ctx* c = ctxs[i];
+        if (!c->ev_ready) LPF_HIP(c, hipEventCreateWithFlags(&c->ev_ready, hipEventDisableTiming), "event");
+        LPF_HIP(c, hipEventRecord(c->ev_ready, c->stream), "event record");
+        LPF_HIP(c0, hipStreamWaitEvent(s, c->ev_ready, 0), "event wait");
+    }
+    LPF_HIP(c0, launch_gather_begin(w.hdr, s), "gather");
+    for (int i = 0; i < n_ctx; ++i)
+        LPF_HIP(ctxs[i], launch_gather_ended(ctxs[i], i, w.hdr, w.windows, w.rows, m->max_batch, s), "gather");
+    // the contexts may go on as soon as their rings have been read
+    LPF_HIP(c0, hipEventRecord(m->ev_gathered, s), "event record");
+    for (int i = 0; i < n_ctx; ++i) LPF_HIP(ctxs[i], hipStreamWaitEvent(ctxs[i]->stream, m->ev_gathered, 0), "event wait");
+    {
+        StageTimer tm(c0, 6, s);
+        LPF_HIP(c0, cnn_forward(m, w.windows, w.hdr, m->max_batch, w.mu, w.L, s), "cnn");
+    }
+    LPF_HIP(c0, hipMemcpyAsync(m->h_res[slot], w.hdr, w.out_bytes, hipMemcpyDeviceToHost, s), "result D2H");
+    LPF_HIP(c0, hipEventRecord(m->ev_done[slot], s), "event record");
+    m->slot_ticket[slot] = m->next_ticket;
+    *ticket = m->next_ticket++;
+    return LPF_OK;
+}
+
+int lpf_infer_collect(lpf_model* m, int64_t ticket, float* mu_out, float* L_out, int32_t* src_out, int32_t cap,
+                      int32_t* n_out) {
+    if (!m || !n_out || ticket < 0) return LPF_EINVAL;
+    const int slot = (int)(ticket % kInflight);
+    if (m->slot_ticket[slot] != ticket) return LPF_EINVAL;
+    if (hipEventSynchronize(m->ev_done[slot]) != hipSuccess) return LPF_EDEVICE;
+    const char* blk = m->h_res[slot];
+    const int32_t* hdr = reinterpret_cast<const int32_t*>(blk);
+    const int taken = hdr[0], seen = hdr[1];
+    const int maxb = m->max_batch;
+    const int32_t* rows = hdr + 4;
+    const float* hmu = reinterpret_cast<const float*>(rows + 2 * (size_t)maxb);
+    const float* hL = hmu + 4 * (size_t)maxb;
+    // rows in (context, id) order
+    std::vector<int> perm(taken);
+    for (int k = 0; k < taken; ++k) perm[k] = k;
+    std::sort(perm.begin(), perm.end(), [&](int x, int y) {
+        return rows[2 * x] != rows[2 * y] ? rows[2 * x] < rows[2 * y] : rows[2 * x + 1] < rows[2 * y + 1];
+    });
+    const int nw = std::min(taken, std::max(cap, 0));
+    for (int i = 0; i < nw; ++i) {
+        const int k = perm[i];
+        if (mu_out) std::memcpy(mu_out + (size_t)i * 4, hmu + (size_t)k * 4, 4 * sizeof(float));
+        if (L_out) std::memcpy(L_out + (size_t)i * 10, hL + (size_t)k * 10, 10 * sizeof(float));
+        if (src_out) { src_out[2 * i] = rows[2 * k]; src_out[2 * i + 1] = rows[2 * k + 1]; }
+    }
+    *n_out = nw;
+    m->slot_ticket[slot] = -1;
+    return seen > taken ? LPF_EFULL : LPF_OK;
 }
 
 int lpf_infer(lpf_ctx* const* ctxs, int32_t n_ctx, const lpf_model* m, const int32_t* ids, int32_t n_ids,
@@ -561,14 +647,25 @@ int lpf_infer(lpf_ctx* const* ctxs, int32_t n_ctx, const lpf_model* m, const int
         if (ctxs[i]->phase != 3) return fail(ctxs[i], LPF_ESTATE, "infer needs extract_flux first");
     }
     lpf_ctx* c0 = ctxs[0];
-    hipStream_t s = c0->stream;
+    lpf_model* mm = const_cast<lpf_model*>(m);   // result slots and tickets
+    if (!ids) {
+        // device-driven: counts stay on the device, one wait for the results
+        int64_t ticket = -1;
+        int rc = lpf_infer_async(ctxs, n_ctx, mm, &ticket);
+        if (rc != LPF_OK) return rc;
+        rc = lpf_infer_collect(mm, ticket, mu_out, L_out, src_out, cap, n_out);
+        if (rc != LPF_EFULL) return rc;
+        // more ended episodes than the model's batch: host-driven chunks below
+    }
+    hipStream_t s = m->istream;
     const int mb = model_max_batch(m);
     float* win = model_window_buffer(m);
     float* dmu = model_mu_buffer(m);
     float* dL = model_L_buffer(m);
     // Entries: per context a run of windows gathered on the device.  With
     // ids == NULL the ended list of each context (slot order) is used and the
-    // rows are reordered by id on the host afterwards.
+    // rows are reordered by id on the host afterwards; its count and ids come
+    // from the read-back of detect when that took place.
     struct Run { int ctx; int n; std::vector<int32_t> id; };
     std::vector<Run> runs;
     int N = 0;
@@ -576,18 +673,23 @@ int lpf_infer(lpf_ctx* const* ctxs, int32_t n_ctx, const lpf_model* m, const int
         lpf_ctx* c = ctxs[ci];
         Run r{ci, 0, {}};
         if (!ids) {
-            DevStatus st;
-            LPF_HIP(c, hipMemcpyAsync(&st, c->buf.status, sizeof(st), hipMemcpyDeviceToHost, c->stream), "status");
-            LPF_HIP(c, hipStreamSynchronize(c->stream), "infer sync");
-            r.n = st.n_ended;
+            if (c->host_n_ended < 0) {
+                DevStatus st;
+                LPF_HIP(c, hipMemcpyAsync(&st, c->buf.status, sizeof(st), hipMemcpyDeviceToHost, c->stream),
+                        "status");
+                LPF_HIP(c, hipStreamSynchronize(c->stream), "infer sync");
+                std::vector<lpf_source> ev(st.n_ended);
+                if (st.n_ended > 0)
+                    LPF_HIP(c, hipMemcpy(ev.data(), c->buf.events + st.n_new, st.n_ended * sizeof(lpf_source),
+                                         hipMemcpyDeviceToHost), "events");
+                c->host_ended_ids.resize(st.n_ended);
+                for (int k = 0; k < st.n_ended; ++k) c->host_ended_ids[k] = ev[k].id;
+                c->host_n_ended = st.n_ended;
+            }
+            r.n = c->host_n_ended;
             if (r.n == 0) continue;
-            std::vector<lpf_source> ev(r.n);
-            LPF_HIP(c, hipMemcpyAsync(ev.data(), c->buf.events + st.n_new, r.n * sizeof(lpf_source),
-                                      hipMemcpyDeviceToHost, c->stream), "events");
             LPF_HIP(c, launch_ended_ends(c, c->buf.infer_slots, c->buf.infer_tend), "ended list");
-            LPF_HIP(c, hipStreamSynchronize(c->stream), "infer sync");
-            r.id.resize(r.n);
-            for (int k = 0; k < r.n; ++k) r.id[k] = ev[k].id;
+            r.id = c->host_ended_ids;
         } else {
             const int S = c->cfg.max_sources;
             std::vector<int32_t> idv(S), state(S);
@@ -636,8 +738,16 @@ int lpf_infer(lpf_ctx* const* ctxs, int32_t n_ctx, const lpf_model* m, const int
     }
     *n_out = std::min(N, cap);
     if (N == 0) return LPF_OK;
-    std::vector<float> hmu((size_t)N * 4), hL((size_t)N * 10);
-    // process the gathered rows in chunks of the model's batch
+    float* hrow = model_host_rows(m, N);   // pinned: the copies below stay asynchronous
+    if (!hrow) return fail(c0, LPF_ENOMEM, "pinned result staging");
+    // the contexts' streams hand their lists and rings over to the model's stream
+    for (const auto& r : runs) {
+        lpf_ctx* c = ctxs[r.ctx];
+        if (!c->ev_ready) LPF_HIP(c, hipEventCreateWithFlags(&c->ev_ready, hipEventDisableTiming), "event");
+        LPF_HIP(c, hipEventRecord(c->ev_ready, c->stream), "event record");
+        LPF_HIP(c0, hipStreamWaitEvent(s, c->ev_ready, 0), "event wait");
+    }
+    // process the gathered rows in chunks of the model's batch; one wait at the end
     int g = 0;  // gathered index of the chunk start
     size_t run_i = 0;
     int run_off = 0;
@@ -648,27 +758,30 @@ int lpf_infer(lpf_ctx* const* ctxs, int32_t n_ctx, const lpf_model* m, const int
             const Run& r = runs[run_i];
             const int take = std::min(cnt - filled, r.n - run_off);
             lpf_ctx* c = ctxs[r.ctx];
-            LPF_HIP(c, launch_windows_gather(c, take, c->buf.infer_slots + run_off, c->buf.infer_tend + run_off,
-                                             win + (size_t)filled * kGridRows * kRing), "windows");
-            if (c->stream != s) LPF_HIP(c, hipStreamSynchronize(c->stream), "windows sync");
+            LPF_HIP(c0, launch_windows_gather(c, take, c->buf.infer_slots + run_off, c->buf.infer_tend + run_off,
+                                              win + (size_t)filled * kGridRows * kRing, s), "windows");
             filled += take;
             run_off += take;
             if (run_off == r.n) { ++run_i; run_off = 0; }
         }
         {
-            StageTimer tm(c0, 6);
-            LPF_HIP(c0, cnn_forward(m, win, cnt, dmu, dL, s), "cnn");
+            StageTimer tm(c0, 6, s);
+            LPF_HIP(c0, cnn_forward(m, win, nullptr, cnt, dmu, dL, s), "cnn");
         }
-        LPF_HIP(c0, hipMemcpyAsync(hmu.data() + (size_t)g * 4, dmu, cnt * 4 * sizeof(float), hipMemcpyDeviceToHost, s), "mu D2H");
-        LPF_HIP(c0, hipMemcpyAsync(hL.data() + (size_t)g * 10, dL, cnt * 10 * sizeof(float), hipMemcpyDeviceToHost, s), "L D2H");
-        LPF_HIP(c0, hipStreamSynchronize(s), "infer sync");
+        LPF_HIP(c0, hipMemcpyAsync(hrow + (size_t)g * 4, dmu, cnt * 4 * sizeof(float), hipMemcpyDeviceToHost, s),
+                "mu D2H");
+        LPF_HIP(c0, hipMemcpyAsync(hrow + (size_t)N * 4 + (size_t)g * 10, dL, cnt * 10 * sizeof(float),
+                                   hipMemcpyDeviceToHost, s), "L D2H");
         g += cnt;
     }
+    LPF_HIP(c0, hipStreamSynchronize(s), "infer sync");
+    const float* hmu = hrow;
+    const float* hL = hrow + (size_t)N * 4;
     const int nw = *n_out;
     for (int i = 0; i < nw; ++i) {
         const int k = row_src[i];
-        if (mu_out) std::memcpy(mu_out + (size_t)i * 4, hmu.data() + (size_t)k * 4, 4 * sizeof(float));
-        if (L_out) std::memcpy(L_out + (size_t)i * 10, hL.data() + (size_t)k * 10, 10 * sizeof(float));
+        if (mu_out) std::memcpy(mu_out + (size_t)i * 4, hmu + (size_t)k * 4, 4 * sizeof(float));
+        if (L_out) std::memcpy(L_out + (size_t)i * 10, hL + (size_t)k * 10, 10 * sizeof(float));
         if (src_out) { src_out[2 * i] = row_ctx[i]; src_out[2 * i + 1] = row_id[i]; }
     }
     return LPF_OK;

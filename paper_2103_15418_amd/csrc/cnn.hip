@@ -26,37 +26,6 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
-struct ModelLayout {
-    // float offsets inside the weight area
-    size_t w1, b1, w2, b2, w3, b3, w4, b4, f1, fb1, f2, fb2, total;
-};
-
-struct CnnWork {
-    float* act_a;     // [maxb][16][64][64] (float32 network)
-    float* act_b;
-    void* act16_a;    // [maxb][16][64][64] (16-bit network)
-    void* act16_b;
-    void* w16;        // 16-bit weights: conv2..4 [9][Cout][Cin], fc1 [128][65536]
-    float* part;      // [128][maxb_pad][128] fc1 split-K partials
-    float* hidden;    // [maxb][128]
-    float* windows;   // [maxb][16][64]
-    float* mu;        // [maxb][4]
-    float* L;         // [maxb][10]
-};
-
-}  // namespace lpf
-
-struct lpf_model {
-    int precision;
-    int max_batch;
-    float alpha;
-    float* wts;
-    lpf::ModelLayout lay;
-    lpf::CnnWork work;
-    hipStream_t stream;
-};
-
-namespace lpf {
 namespace {
 
 constexpr int kGH = 16, kGW = 64;
@@ -95,11 +64,19 @@ ModelLayout make_layout() {
 
 __device__ inline float act_fn(float v, float alpha) { return v >= 0.0f ? v : alpha * v; }
 
+// Number of windows of a launch: *n_dev (clamped to n_cap) when the count is
+// held on the device, else n_cap.  Grids are sized for n_cap and loop.
+__device__ inline int batch_n(const int* n_dev, int n_cap) {
+    if (!n_dev) return n_cap;
+    const int n = *n_dev;
+    return n < n_cap ? n : n_cap;
+}
+
 // conv1: x [n][16][64] -> out [n][16][64][32]
 __global__ __launch_bounds__(256) void k_conv1(const float* __restrict__ x, const float* __restrict__ w,
                                                const float* __restrict__ bias, float* __restrict__ out,
-                                               int n_total, float alpha) {
-    const int64_t total = (int64_t)n_total * kGH * kGW * 32;
+                                               const int* __restrict__ n_dev, int n_cap, float alpha) {
+    const int64_t total = (int64_t)batch_n(n_dev, n_cap) * kGH * kGW * 32;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int c = (int)(i % 32);
@@ -129,93 +106,103 @@ template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ in,
                                                    const float* __restrict__ w,  // [9*CIN][COUT]
                                                    const float* __restrict__ bias,
-                                                   float* __restrict__ out, float alpha) {
+                                                   float* __restrict__ out, const int* __restrict__ n_dev,
+                                                   int n_cap, float alpha) {
     constexpr int ROWS = 64 / COUT;
     constexpr int PADW = kGW + 2;  // 66
     __shared__ float s_in[(ROWS + 2) * CIN * PADW];
-    const int n = blockIdx.x / (kGH / ROWS);
-    const int h0 = (blockIdx.x % (kGH / ROWS)) * ROWS;
-    const float* src = in + (size_t)n * kGH * kGW * CIN;
-    // stage rows h0-1 .. h0+ROWS, channel-major with a zero column either side
-    for (int i = threadIdx.x; i < (ROWS + 2) * PADW * CIN; i += 256) {
-        const int cin = i % CIN;
-        const int col = (i / CIN) % PADW;
-        const int r = i / (CIN * PADW);
-        const int gr = h0 - 1 + r, gc = col - 1;
-        float v = 0.0f;
-        if (gr >= 0 && gr < kGH && gc >= 0 && gc < kGW) v = src[((size_t)gr * kGW + gc) * CIN + cin];
-        s_in[(r * CIN + cin) * PADW + col] = v;
-    }
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // block assignment: COUT = 64 -> (pixel half, cout half); COUT = 32 -> (row, pixel half)
-    int rloc, px0, co0;
-    if (COUT == 64) {
-        rloc = 0;
-        px0 = (wave & 1) * 32;
-        co0 = (wave >> 1) * 32;
-    } else {
-        rloc = wave >> 1;
-        px0 = (wave & 1) * 32;
-        co0 = 0;
-    }
-    const int m = lane & 31, kk = lane >> 5;
-    floatx16 acc = {};
+    const int nblk = batch_n(n_dev, n_cap) * (kGH / ROWS);
+    for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int n = blk / (kGH / ROWS);
+        const int h0 = (blk % (kGH / ROWS)) * ROWS;
+        const float* src = in + (size_t)n * kGH * kGW * CIN;
+        // stage rows h0-1 .. h0+ROWS, channel-major with a zero column either side
+        for (int i = threadIdx.x; i < (ROWS + 2) * PADW * CIN; i += 256) {
+            const int cin = i % CIN;
+            const int col = (i / CIN) % PADW;
+            const int r = i / (CIN * PADW);
+            const int gr = h0 - 1 + r, gc = col - 1;
+            float v = 0.0f;
+            if (gr >= 0 && gr < kGH && gc >= 0 && gc < kGW) v = src[((size_t)gr * kGW + gc) * CIN + cin];
+            s_in[(r * CIN + cin) * PADW + col] = v;
+        }
+        __syncthreads();
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        // block assignment: COUT = 64 -> (pixel half, cout half); COUT = 32 -> (row, pixel half)
+        int rloc, px0, co0;
+        if (COUT == 64) {
+            rloc = 0;
+            px0 = (wave & 1) * 32;
+            co0 = (wave >> 1) * 32;
+        } else {
+            rloc = wave >> 1;
+            px0 = (wave & 1) * 32;
+            co0 = 0;
+        }
+        const int m = lane & 31, kk = lane >> 5;
+        floatx16 acc = {};
 #pragma unroll 1
-    for (int kh = 0; kh < 3; ++kh) {
+        for (int kh = 0; kh < 3; ++kh) {
 #pragma unroll 1
-        for (int kw = 0; kw < 3; ++kw) {
-            const float* arow = s_in + ((rloc + kh) * CIN) * PADW + px0 + m + kw;
-            const float* wrow = w + (size_t)((kh * 3 + kw) * CIN) * COUT + co0 + m;
+            for (int kw = 0; kw < 3; ++kw) {
+                const float* arow = s_in + ((rloc + kh) * CIN) * PADW + px0 + m + kw;
+                const float* wrow = w + (size_t)((kh * 3 + kw) * CIN) * COUT + co0 + m;
 #pragma unroll 8
-            for (int c = 0; c < CIN; c += 2) {
-                const float av = arow[(c + kk) * PADW];
-                const float bv = wrow[(size_t)(c + kk) * COUT];
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+                for (int c = 0; c < CIN; c += 2) {
+                    const float av = arow[(c + kk) * PADW];
+                    const float bv = wrow[(size_t)(c + kk) * COUT];
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+                }
             }
         }
-    }
-    // D[i][j]: j = lane % 32 (output channel), i = 8 (v / 4) + 4 (lane / 32) + v % 4 (pixel)
-    const int row = h0 + rloc;
-    float* dst = out + ((size_t)n * kGH + row) * kGW * COUT;
-    const float bj = bias[co0 + m];
+        // D[i][j]: j = lane % 32 (output channel), i = 8 (v / 4) + 4 (lane / 32) + v % 4 (pixel)
+        const int row = h0 + rloc;
+        float* dst = out + ((size_t)n * kGH + row) * kGW * COUT;
+        const float bj = bias[co0 + m];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int px = px0 + 8 * (v / 4) + 4 * kk + (v % 4);
-        dst[(size_t)px * COUT + co0 + m] = act_fn(acc[v] + bj, alpha);
+        for (int v = 0; v < 16; ++v) {
+            const int px = px0 + 8 * (v / 4) + 4 * kk + (v % 4);
+            dst[(size_t)px * COUT + co0 + m] = act_fn(acc[v] + bj, alpha);
+        }
+        __syncthreads();   // s_in is restaged by the next iteration
     }
 }
 
 // fc1 split-K: part[ks][row][128] = A[rows][kchunk] * W1[kchunk][128]
 // grid (kNSplit, ceil(n / 32)); A = act (NHWC flatten, k = (h*64 + w)*64 + c).
 __global__ __launch_bounds__(256) void k_fc1_mfma(const float* __restrict__ a, const float* __restrict__ w,
-                                                  float* __restrict__ part, int n_total, int ld_part) {
+                                                  float* __restrict__ part, const int* __restrict__ n_dev,
+                                                  int n_cap, int ld_part) {
     constexpr int LDA = kSplitK + 1;
     __shared__ float s_a[32 * LDA];
-    const int ks = blockIdx.x, mb = blockIdx.y;
+    const int n_total = batch_n(n_dev, n_cap);
+    const int ks = blockIdx.x;
     const int k0 = ks * kSplitK;
-    for (int i = threadIdx.x; i < 32 * kSplitK; i += 256) {
-        const int r = i / kSplitK, k = i % kSplitK;
-        const int n = mb * 32 + r;
-        s_a[r * LDA + k] = n < n_total ? a[(size_t)n * kFlat + k0 + k] : 0.0f;
-    }
-    __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = lane & 31, kk = lane >> 5;
     const int co0 = wave * 32;
-    floatx16 acc = {};
-    const float* wp = w + (size_t)k0 * kHidden + co0 + m;
+    for (int mb = blockIdx.y; mb * 32 < n_total; mb += gridDim.y) {
+        for (int i = threadIdx.x; i < 32 * kSplitK; i += 256) {
+            const int r = i / kSplitK, k = i % kSplitK;
+            const int n = mb * 32 + r;
+            s_a[r * LDA + k] = n < n_total ? a[(size_t)n * kFlat + k0 + k] : 0.0f;
+        }
+        __syncthreads();
+        floatx16 acc = {};
+        const float* wp = w + (size_t)k0 * kHidden + co0 + m;
 #pragma unroll 8
-    for (int k = 0; k < kSplitK; k += 2) {
-        const float av = s_a[m * LDA + k + kk];
-        const float bv = wp[(size_t)(k + kk) * kHidden];
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
-    }
-    float* dst = part + (size_t)ks * ld_part * kHidden;
+        for (int k = 0; k < kSplitK; k += 2) {
+            const float av = s_a[m * LDA + k + kk];
+            const float bv = wp[(size_t)(k + kk) * kHidden];
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+        }
+        float* dst = part + (size_t)ks * ld_part * kHidden;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int r = mb * 32 + 8 * (v / 4) + 4 * kk + (v % 4);
-        dst[(size_t)r * kHidden + co0 + m] = acc[v];
+        for (int v = 0; v < 16; ++v) {
+            const int r = mb * 32 + 8 * (v / 4) + 4 * kk + (v % 4);
+            dst[(size_t)r * kHidden + co0 + m] = acc[v];
+        }
+        __syncthreads();   // s_a is restaged by the next row block
     }
 }
 
@@ -238,8 +225,8 @@ __device__ inline floatx16 mfma32<_Float16>(f16x8 a, f16x8 b, floatx16 c) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_conv1_16(const float* __restrict__ x, const float* __restrict__ w,
                                                   const float* __restrict__ bias, T* __restrict__ out,
-                                                  int n_total, float alpha) {
-    const int64_t total = (int64_t)n_total * kGH * kGW * 32;
+                                                  const int* __restrict__ n_dev, int n_cap, float alpha) {
+    const int64_t total = (int64_t)batch_n(n_dev, n_cap) * kGH * kGW * 32;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int c = (int)(i % 32);
@@ -268,11 +255,10 @@ __global__ __launch_bounds__(256) void k_conv1_16(const float* __restrict__ x, c
 template <typename T, int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_conv16(const T* __restrict__ in, const T* __restrict__ w,
                                                 const float* __restrict__ bias, T* __restrict__ out,
-                                                float alpha) {
+                                                const int* __restrict__ n_dev, int n_cap, float alpha) {
     typedef typename V8<T>::type vec;
     constexpr int ROWS = 64 / COUT;
-    const int n = blockIdx.x / (kGH / ROWS);
-    const int h0 = (blockIdx.x % (kGH / ROWS)) * ROWS;
+    const int nblk = batch_n(n_dev, n_cap) * (kGH / ROWS);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int rloc, px0, co0;
     if (COUT == 64) {
@@ -285,63 +271,71 @@ __global__ __launch_bounds__(256) void k_conv16(const T* __restrict__ in, const 
         co0 = 0;
     }
     const int m = lane & 31, kg = lane >> 5;
-    const int row = h0 + rloc;
-    floatx16 acc = {};
-    vec zero = {};
+    for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int n = blk / (kGH / ROWS);
+        const int h0 = (blk % (kGH / ROWS)) * ROWS;
+        const int row = h0 + rloc;
+        floatx16 acc = {};
+        vec zero = {};
 #pragma unroll 1
-    for (int kh = 0; kh < 3; ++kh) {
-        const int r = row + kh - 1;
-        const bool rv = r >= 0 && r < kGH;
+        for (int kh = 0; kh < 3; ++kh) {
+            const int r = row + kh - 1;
+            const bool rv = r >= 0 && r < kGH;
 #pragma unroll
-        for (int kw = 0; kw < 3; ++kw) {
-            const int col = px0 + m + kw - 1;
-            const bool valid = rv && col >= 0 && col < kGW;
-            const T* ap = in + (((size_t)n * kGH + (rv ? r : 0)) * kGW + (valid ? col : 0)) * CIN + kg * 8;
-            const T* bp = w + ((size_t)(kh * 3 + kw) * COUT + co0 + m) * CIN + kg * 8;
+            for (int kw = 0; kw < 3; ++kw) {
+                const int col = px0 + m + kw - 1;
+                const bool valid = rv && col >= 0 && col < kGW;
+                const T* ap = in + (((size_t)n * kGH + (rv ? r : 0)) * kGW + (valid ? col : 0)) * CIN + kg * 8;
+                const T* bp = w + ((size_t)(kh * 3 + kw) * COUT + co0 + m) * CIN + kg * 8;
 #pragma unroll
-            for (int c0 = 0; c0 < CIN; c0 += 16) {
-                const vec av = valid ? *reinterpret_cast<const vec*>(ap + c0) : zero;
-                const vec bv = *reinterpret_cast<const vec*>(bp + c0);
-                acc = mfma32<T>(av, bv, acc);
+                for (int c0 = 0; c0 < CIN; c0 += 16) {
+                    const vec av = valid ? *reinterpret_cast<const vec*>(ap + c0) : zero;
+                    const vec bv = *reinterpret_cast<const vec*>(bp + c0);
+                    acc = mfma32<T>(av, bv, acc);
+                }
             }
         }
-    }
-    T* dst = out + ((size_t)n * kGH + row) * kGW * COUT;
-    const float bj = bias[co0 + m];
+        T* dst = out + ((size_t)n * kGH + row) * kGW * COUT;
+        const float bj = bias[co0 + m];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int px = px0 + 8 * (v / 4) + 4 * kg + (v % 4);
-        dst[(size_t)px * COUT + co0 + m] = (T)act_fn(acc[v] + bj, alpha);
+        for (int v = 0; v < 16; ++v) {
+            const int px = px0 + 8 * (v / 4) + 4 * kg + (v % 4);
+            dst[(size_t)px * COUT + co0 + m] = (T)act_fn(acc[v] + bj, alpha);
+        }
     }
 }
 
 // fc1 split-K on 16-bit operands: A = act [n][65536] (NHWC flatten), B = W1 [128][65536].
 template <typename T>
 __global__ __launch_bounds__(256) void k_fc1_16(const T* __restrict__ a, const T* __restrict__ w,
-                                                float* __restrict__ part, int n_total, int ld_part) {
+                                                float* __restrict__ part, const int* __restrict__ n_dev,
+                                                int n_cap, int ld_part) {
     typedef typename V8<T>::type vec;
-    const int ks = blockIdx.x, mb = blockIdx.y;
+    const int n_total = batch_n(n_dev, n_cap);
+    const int ks = blockIdx.x;
     const int k0 = ks * kSplitK;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = lane & 31, kg = lane >> 5;
     const int co0 = wave * 32;
-    const int n = mb * 32 + m;
-    const bool valid = n < n_total;
-    const T* ap = a + (size_t)(valid ? n : 0) * kFlat + k0 + kg * 8;
     const T* bp = w + (size_t)(co0 + m) * kFlat + k0 + kg * 8;
-    floatx16 acc = {};
-    vec zero = {};
+    for (int mb = blockIdx.y; mb * 32 < n_total; mb += gridDim.y) {
+        const int n = mb * 32 + m;
+        const bool valid = n < n_total;
+        const T* ap = a + (size_t)(valid ? n : 0) * kFlat + k0 + kg * 8;
+        floatx16 acc = {};
+        vec zero = {};
 #pragma unroll 8
-    for (int k = 0; k < kSplitK; k += 16) {
-        const vec av = valid ? *reinterpret_cast<const vec*>(ap + k) : zero;
-        const vec bv = *reinterpret_cast<const vec*>(bp + k);
-        acc = mfma32<T>(av, bv, acc);
-    }
-    float* dst = part + (size_t)ks * ld_part * kHidden;
+        for (int k = 0; k < kSplitK; k += 16) {
+            const vec av = valid ? *reinterpret_cast<const vec*>(ap + k) : zero;
+            const vec bv = *reinterpret_cast<const vec*>(bp + k);
+            acc = mfma32<T>(av, bv, acc);
+        }
+        float* dst = part + (size_t)ks * ld_part * kHidden;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int r = mb * 32 + 8 * (v / 4) + 4 * kg + (v % 4);
-        dst[(size_t)r * kHidden + co0 + m] = acc[v];
+        for (int v = 0; v < 16; ++v) {
+            const int r = mb * 32 + 8 * (v / 4) + 4 * kg + (v % 4);
+            dst[(size_t)r * kHidden + co0 + m] = acc[v];
+        }
     }
 }
 
@@ -371,13 +365,15 @@ __global__ void k_to16(const float* __restrict__ W, T* __restrict__ w16, ModelLa
 
 // hidden[n][j] = phi(sum_ks part[ks][n][j] + b[j]) in a fixed order.
 __global__ void k_fc1_reduce(const float* __restrict__ part, const float* __restrict__ bias,
-                             float* __restrict__ hidden, int n_total, int ld_part, float alpha) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_total * kHidden) return;
-    const int n = i / kHidden, j = i % kHidden;
-    float acc = 0.0f;
-    for (int ks = 0; ks < kNSplit; ++ks) acc += part[((size_t)ks * ld_part + n) * kHidden + j];
-    hidden[i] = act_fn(acc + bias[j], alpha);
+                             float* __restrict__ hidden, const int* __restrict__ n_dev, int n_cap, int ld_part,
+                             float alpha) {
+    const int total = batch_n(n_dev, n_cap) * kHidden;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const int n = i / kHidden, j = i % kHidden;
+        float acc = 0.0f;
+        for (int ks = 0; ks < kNSplit; ++ks) acc += part[((size_t)ks * ld_part + n) * kHidden + j];
+        hidden[i] = act_fn(acc + bias[j], alpha);
+    }
 }
 
 __device__ inline float softplus(float z) { return fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))); }
@@ -385,20 +381,21 @@ __device__ inline float softplus(float z) { return fmaxf(z, 0.0f) + log1pf(expf(
 // fc2 + head: one lane per (sample, output).
 __global__ void k_fc2_head(const float* __restrict__ hidden, const float* __restrict__ w,  // [14][128]
                            const float* __restrict__ bias, float* __restrict__ mu, float* __restrict__ L,
-                           int n_total) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_total * kOut) return;
-    const int n = i / kOut, o = i % kOut;
-    const float* h = hidden + (size_t)n * kHidden;
-    const float* wr = w + (size_t)o * kHidden;
-    float acc = bias[o];
-    for (int j = 0; j < kHidden; ++j) acc = fmaf(wr[j], h[j], acc);
-    if (o < 4) {
-        mu[n * 4 + o] = acc;
-    } else {
-        const int p = o - 4;
-        const bool diag = p == 0 || p == 2 || p == 5 || p == 9;
-        L[n * 10 + p] = diag ? softplus(acc) : acc;
+                           const int* __restrict__ n_dev, int n_cap) {
+    const int total = batch_n(n_dev, n_cap) * kOut;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const int n = i / kOut, o = i % kOut;
+        const float* h = hidden + (size_t)n * kHidden;
+        const float* wr = w + (size_t)o * kHidden;
+        float acc = bias[o];
+        for (int j = 0; j < kHidden; ++j) acc = fmaf(wr[j], h[j], acc);
+        if (o < 4) {
+            mu[n * 4 + o] = acc;
+        } else {
+            const int p = o - 4;
+            const bool diag = p == 0 || p == 2 || p == 5 || p == 9;
+            L[n * 10 + p] = diag ? softplus(acc) : acc;
+        }
     }
 }
 
@@ -451,6 +448,9 @@ size_t blob_floats() {
 
 int pad32(int n) { return (n + 31) / 32 * 32; }
 
+// Result block: hdr[4] int32, rows[maxb][2] int32, mu[maxb][4], L[maxb][10] float32.
+size_t out_block_bytes(int maxb) { return (4 + (size_t)maxb * (2 + 4 + 10)) * 4; }
+
 size_t work_bytes(int precision, int maxb) {
     const size_t elt = precision == LPF_PREC_FP32 ? sizeof(float) : 2;
     const size_t act = (size_t)maxb * kGH * kGW * 64 * elt;
@@ -460,69 +460,68 @@ size_t work_bytes(int precision, int maxb) {
     b += align64((size_t)kNSplit * pad32(maxb) * kHidden * sizeof(float));
     b += align64((size_t)maxb * kHidden * sizeof(float));
     b += align64((size_t)maxb * kGH * kGW * sizeof(float));
-    b += align64((size_t)maxb * 4 * sizeof(float));
-    b += align64((size_t)maxb * 10 * sizeof(float));
+    b += align64(out_block_bytes(maxb));
     return b;
 }
 
 }  // namespace
 
+// Grid sizes for n_cap windows; with the count on the device the grids loop.
+inline int grid_cap(int64_t want, int cap) { return (int)(want < 1 ? 1 : (want > cap ? cap : want)); }
+
 template <typename T>
-hipError_t forward16(const lpf_model* m, const float* windows, int n, hipStream_t s) {
+hipError_t forward16(const lpf_model* m, const float* windows, const int* n_dev, int n_cap, hipStream_t s) {
     const ModelLayout& lay = m->lay;
     const float* W = m->wts;
     const CnnWork& w = m->work;
     const T* w16 = static_cast<const T*>(w.w16);
     T* a = static_cast<T*>(w.act16_a);
     T* b = static_cast<T*>(w.act16_b);
-    int blocks = (int)(((int64_t)n * kGH * kGW * 32 + 255) / 256);
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL((k_conv1_16<T>), dim3(blocks), dim3(256), 0, s, windows, W + lay.w1, W + lay.b1, a, n,
-                       m->alpha);
-    hipLaunchKernelGGL((k_conv16<T, 32, 32>), dim3(n * (kGH / 2)), dim3(256), 0, s, a, w16 + kW16o2,
-                       W + lay.b2, b, m->alpha);
-    hipLaunchKernelGGL((k_conv16<T, 32, 64>), dim3(n * kGH), dim3(256), 0, s, b, w16 + kW16o3, W + lay.b3, a,
-                       m->alpha);
-    hipLaunchKernelGGL((k_conv16<T, 64, 64>), dim3(n * kGH), dim3(256), 0, s, a, w16 + kW16o4, W + lay.b4, b,
-                       m->alpha);
-    hipLaunchKernelGGL((k_fc1_16<T>), dim3(kNSplit, (n + 31) / 32), dim3(256), 0, s, b, w16 + kW16of1, w.part,
-                       n, pad32(m->max_batch));
+    hipLaunchKernelGGL((k_conv1_16<T>), dim3(grid_cap(((int64_t)n_cap * kGH * kGW * 32 + 255) / 256, 4096)),
+                       dim3(256), 0, s, windows, W + lay.w1, W + lay.b1, a, n_dev, n_cap, m->alpha);
+    hipLaunchKernelGGL((k_conv16<T, 32, 32>), dim3(grid_cap((int64_t)n_cap * (kGH / 2), 2048)), dim3(256), 0, s,
+                       a, w16 + kW16o2, W + lay.b2, b, n_dev, n_cap, m->alpha);
+    hipLaunchKernelGGL((k_conv16<T, 32, 64>), dim3(grid_cap((int64_t)n_cap * kGH, 2048)), dim3(256), 0, s, b,
+                       w16 + kW16o3, W + lay.b3, a, n_dev, n_cap, m->alpha);
+    hipLaunchKernelGGL((k_conv16<T, 64, 64>), dim3(grid_cap((int64_t)n_cap * kGH, 2048)), dim3(256), 0, s, a,
+                       w16 + kW16o4, W + lay.b4, b, n_dev, n_cap, m->alpha);
+    hipLaunchKernelGGL((k_fc1_16<T>), dim3(kNSplit, grid_cap((n_cap + 31) / 32, 4)), dim3(256), 0, s, b,
+                       w16 + kW16of1, w.part, n_dev, n_cap, pad32(m->max_batch));
     return hipGetLastError();
 }
 
-// Runs the network on n device windows (n <= max_batch).
-hipError_t cnn_forward(const lpf_model* m, const float* windows, int n, float* mu, float* L,
-                       hipStream_t s) {
-    if (n <= 0) return hipSuccess;
+// Runs the network on the device windows [0, n) with n = *n_dev clamped to
+// n_cap when n_dev is given, else n = n_cap (n_cap <= max_batch).
+hipError_t cnn_forward(const lpf_model* m, const float* windows, const int* n_dev, int n_cap, float* mu,
+                       float* L, hipStream_t s) {
+    if (n_cap <= 0) return hipSuccess;
     const ModelLayout& lay = m->lay;
     const float* W = m->wts;
     const CnnWork& w = m->work;
     const int ldp = pad32(m->max_batch);
     hipError_t e = hipSuccess;
     if (m->precision == LPF_PREC_BF16) {
-        e = forward16<__bf16>(m, windows, n, s);
+        e = forward16<__bf16>(m, windows, n_dev, n_cap, s);
     } else if (m->precision == LPF_PREC_FP16) {
-        e = forward16<_Float16>(m, windows, n, s);
+        e = forward16<_Float16>(m, windows, n_dev, n_cap, s);
     } else {
-        int blocks = (int)(((int64_t)n * kGH * kGW * 32 + 255) / 256);
-        if (blocks > 4096) blocks = 4096;
-        hipLaunchKernelGGL(k_conv1, dim3(blocks), dim3(256), 0, s, windows, W + lay.w1, W + lay.b1, w.act_a, n,
-                           m->alpha);
-        hipLaunchKernelGGL((k_conv_mfma<32, 32>), dim3(n * (kGH / 2)), dim3(256), 0, s, w.act_a, W + lay.w2,
-                           W + lay.b2, w.act_b, m->alpha);
-        hipLaunchKernelGGL((k_conv_mfma<32, 64>), dim3(n * kGH), dim3(256), 0, s, w.act_b, W + lay.w3,
-                           W + lay.b3, w.act_a, m->alpha);
-        hipLaunchKernelGGL((k_conv_mfma<64, 64>), dim3(n * kGH), dim3(256), 0, s, w.act_a, W + lay.w4,
-                           W + lay.b4, w.act_b, m->alpha);
-        hipLaunchKernelGGL(k_fc1_mfma, dim3(kNSplit, (n + 31) / 32), dim3(256), 0, s, w.act_b, W + lay.f1,
-                           w.part, n, ldp);
+        hipLaunchKernelGGL(k_conv1, dim3(grid_cap(((int64_t)n_cap * kGH * kGW * 32 + 255) / 256, 4096)),
+                           dim3(256), 0, s, windows, W + lay.w1, W + lay.b1, w.act_a, n_dev, n_cap, m->alpha);
+        hipLaunchKernelGGL((k_conv_mfma<32, 32>), dim3(grid_cap((int64_t)n_cap * (kGH / 2), 2048)), dim3(256),
+                           0, s, w.act_a, W + lay.w2, W + lay.b2, w.act_b, n_dev, n_cap, m->alpha);
+        hipLaunchKernelGGL((k_conv_mfma<32, 64>), dim3(grid_cap((int64_t)n_cap * kGH, 2048)), dim3(256), 0, s,
+                           w.act_b, W + lay.w3, W + lay.b3, w.act_a, n_dev, n_cap, m->alpha);
+        hipLaunchKernelGGL((k_conv_mfma<64, 64>), dim3(grid_cap((int64_t)n_cap * kGH, 2048)), dim3(256), 0, s,
+                           w.act_a, W + lay.w4, W + lay.b4, w.act_b, n_dev, n_cap, m->alpha);
+        hipLaunchKernelGGL(k_fc1_mfma, dim3(kNSplit, grid_cap((n_cap + 31) / 32, 4)), dim3(256), 0, s, w.act_b,
+                           W + lay.f1, w.part, n_dev, n_cap, ldp);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fc1_reduce, dim3((n * kHidden + 255) / 256), dim3(256), 0, s, w.part, W + lay.fb1,
-                       w.hidden, n, ldp, m->alpha);
-    hipLaunchKernelGGL(k_fc2_head, dim3((n * kOut + 255) / 256), dim3(256), 0, s, w.hidden, W + lay.f2,
-                       W + lay.fb2, mu, L, n);
+    hipLaunchKernelGGL(k_fc1_reduce, dim3(grid_cap(((int64_t)n_cap * kHidden + 255) / 256, 1024)), dim3(256), 0,
+                       s, w.part, W + lay.fb1, w.hidden, n_dev, n_cap, ldp, m->alpha);
+    hipLaunchKernelGGL(k_fc2_head, dim3(grid_cap(((int64_t)n_cap * kOut + 255) / 256, 1024)), dim3(256), 0, s,
+                       w.hidden, W + lay.f2, W + lay.fb2, mu, L, n_dev, n_cap);
     return hipGetLastError();
 }
 
@@ -530,6 +529,22 @@ float* model_window_buffer(const lpf_model* m) { return m->work.windows; }
 float* model_mu_buffer(const lpf_model* m) { return m->work.mu; }
 float* model_L_buffer(const lpf_model* m) { return m->work.L; }
 int model_max_batch(const lpf_model* m) { return m->max_batch; }
+
+// Pinned host rows of 14 floats (mu then L) for n results; grows by doubling.
+float* model_host_rows(const lpf_model* m, size_t n) {
+    if (n > m->h_cap) {
+        size_t cap = m->h_cap ? m->h_cap : 256;
+        while (cap < n) cap *= 2;
+        float* p = nullptr;
+        if (hipHostMalloc(reinterpret_cast<void**>(&p), cap * 14 * sizeof(float), hipHostMallocDefault) !=
+            hipSuccess)
+            return nullptr;
+        if (m->h_out) (void)hipHostFree(m->h_out);
+        m->h_out = p;
+        m->h_cap = cap;
+    }
+    return m->h_out;
+}
 
 size_t model_blob_bytes() { return (blob_floats() + 1) * sizeof(float); }
 
@@ -541,6 +556,8 @@ int model_workspace_size(int precision, int maxb, size_t* bytes) {
              align64(blob_floats() * sizeof(float));
     return LPF_OK;
 }
+
+void model_destroy(lpf_model* m);
 
 int model_create(const void* weights, size_t bytes, int precision, int maxb, void* ws, size_t ws_bytes,
                  hipStream_t s, lpf_model** out) {
@@ -579,8 +596,12 @@ int model_create(const void* weights, size_t bytes, int precision, int maxb, voi
     p += align64((size_t)kNSplit * pad32(maxb) * kHidden * sizeof(float));
     m->work.hidden = reinterpret_cast<float*>(p); p += align64((size_t)maxb * kHidden * sizeof(float));
     m->work.windows = reinterpret_cast<float*>(p); p += align64((size_t)maxb * kGH * kGW * sizeof(float));
-    m->work.mu = reinterpret_cast<float*>(p); p += align64((size_t)maxb * 4 * sizeof(float));
-    m->work.L = reinterpret_cast<float*>(p); p += align64((size_t)maxb * 10 * sizeof(float));
+    m->work.hdr = reinterpret_cast<int32_t*>(p);
+    m->work.rows = m->work.hdr + 4;
+    m->work.mu = reinterpret_cast<float*>(m->work.rows + 2 * (size_t)maxb);
+    m->work.L = m->work.mu + 4 * (size_t)maxb;
+    m->work.out_bytes = out_block_bytes(maxb);
+    p += align64(m->work.out_bytes);
     float* staging = reinterpret_cast<float*>(p);
     hipError_t e = hipMemcpyAsync(staging, weights, blob_floats() * sizeof(float), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
@@ -597,14 +618,37 @@ int model_create(const void* weights, size_t bytes, int precision, int maxb, voi
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    // inference stream (default priority), events and pinned result blocks
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&m->istream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_gathered, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_out, hipEventDisableTiming);
+    for (int i = 0; i < kInflight && e == hipSuccess; ++i) {
+        e = hipEventCreateWithFlags(&m->ev_done[i], hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void**>(&m->h_res[i]), m->work.out_bytes, hipHostMallocDefault);
+    }
     if (e != hipSuccess) {
-        delete m;
+        model_destroy(m);
         return LPF_EDEVICE;
     }
     *out = m;
     return LPF_OK;
 }
 
-void model_destroy(lpf_model* m) { delete m; }
+void model_destroy(lpf_model* m) {
+    if (!m) return;
+    if (m->istream) (void)hipStreamSynchronize(m->istream);
+    for (int i = 0; i < kInflight; ++i) {
+        if (m->ev_done[i]) (void)hipEventDestroy(m->ev_done[i]);
+        if (m->h_res[i]) (void)hipHostFree(m->h_res[i]);
+    }
+    if (m->ev_gathered) (void)hipEventDestroy(m->ev_gathered);
+    if (m->ev_in) (void)hipEventDestroy(m->ev_in);
+    if (m->ev_out) (void)hipEventDestroy(m->ev_out);
+    if (m->istream) (void)hipStreamDestroy(m->istream);
+    if (m->h_out) (void)hipHostFree(m->h_out);
+    delete m;
+}
 
 }  // namespace lpf

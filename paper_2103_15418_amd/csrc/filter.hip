@@ -25,6 +25,7 @@
 //                S <- filter(W.(X-C)^2)/den, Y |= threshold;   then one peak pass.
 
 #include <cmath>
+#include <cstdlib>
 
 #include "lpf_internal.h"
 
@@ -50,14 +51,15 @@ __device__ inline floatx4 mfma16<_Float16>(f16x8 a, f16x8 b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
-enum InMode { IN_MX = 0, IN_ME = 1, IN_W = 2, IN_WX = 3, IN_WE = 4, IN_M = 5 };
+enum InMode { IN_MX = 0, IN_ME = 1, IN_W = 2, IN_WX = 3, IN_WE = 4, IN_M = 5, IN_E = 6 };
 enum OutMode {
     OUT_C_STATIC = 0,    // C = v * inv_den
     OUT_S_PEAKS = 1,     // S = v * inv_den; threshold; peaks; optional S/Y planes
     OUT_RAW = 2,         // plane = v (den)
     OUT_C_DYN = 3,       // C = v / den
     OUT_S_DYN = 4,       // S = v / den; Y |= threshold; changed flag
-    OUT_INV_DEN = 5      // inv_den = v > 0 ? 1 / v : 0
+    OUT_INV_DEN = 5,     // inv_den = v > 0 ? 1 / v : 0
+    OUT_C_E = 6          // C = v * inv_den and E = M (X - C)^2
 };
 
 struct FiltArgs {
@@ -70,6 +72,9 @@ struct FiltArgs {
     const uint32_t* mbits; // [H][mwords] sky mask, bit j of word w = column 32 w + j (null = all)
     int mwords;
     float* out;          // output plane(s)
+    const float* E;      // residual plane M (X - C)^2 (input of IN_E)
+    float* E_out;        // residual plane written by OUT_C_E
+    int strip_h;         // output rows per strip (strip kernels, multiple of 32)
     float* S_out;        // optional spread plane
     uint8_t* Y_out;      // optional clip plane
     uint8_t* Y_out2;     // optional second clip plane (iteration 1 of several)
@@ -250,17 +255,55 @@ __device__ inline void epilogue_col(const FiltArgs& a, int b, size_t bo, int gy0
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
             if (q < nvalid) a.out[bo + (size_t)(gy0 + q) * a.W + gx] = v[q] * id[q];
+    } else if (OUT == OUT_C_E) {
+        // loads from clamped rows (always inside the image), stores for q < nvalid only
+        float id[NQ], xv[NQ], mk[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int gy = gy0 + q < a.H ? gy0 + q : a.H - 1;
+            const size_t p = (size_t)gy * a.W + gx;
+            id[q] = a.inv_den[p];
+            xv[q] = a.X[bo + p];
+        }
+        if (a.M) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int gy = gy0 + q < a.H ? gy0 + q : a.H - 1;
+                mk[q] = (float)a.M[(size_t)gy * a.W + gx];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) mk[q] = 1.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            if (q >= nvalid) break;
+            const size_t p = bo + (size_t)(gy0 + q) * a.W + gx;
+            const float cv = v[q] * id[q];
+            const float r = xv[q] - cv;
+            a.out[p] = cv;
+            a.E_out[p] = mk[q] * r * r;
+        }
     } else if (OUT == OUT_S_PEAKS) {
         float id[NQ], cv[NQ], xv[NQ];
         bool mk[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            const size_t p = (size_t)(gy0 + q) * a.W + gx;
-            const bool in = q < nvalid;
-            id[q] = in ? a.inv_den[p] : 0.0f;
-            cv[q] = in ? a.C[bo + p] : 0.0f;
-            xv[q] = in ? a.X[bo + p] : 0.0f;
-            mk[q] = in && (a.M ? a.M[p] != 0 : true);
+            const int gy = gy0 + q < a.H ? gy0 + q : a.H - 1;
+            const size_t p = (size_t)gy * a.W + gx;
+            id[q] = a.inv_den[p];
+            cv[q] = a.C[bo + p];
+            xv[q] = a.X[bo + p];
+        }
+        if (a.M) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int gy = gy0 + q < a.H ? gy0 + q : a.H - 1;
+                mk[q] = q < nvalid && a.M[(size_t)gy * a.W + gx] != 0;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) mk[q] = q < nvalid;
         }
         bool y[NQ];
         float s[NQ];
@@ -623,6 +666,180 @@ __global__ __launch_bounds__(kThreads2) void k_filter_mfma(FiltArgs a, Taps tp) 
     }
 }
 
+// Strip kernel (float32 path; compile-time half-width K; W % 4 == 0).
+// One 256-thread workgroup walks down a 64-column strip of one band in
+// chunks of 32 output rows, so every input row is row-filtered once per strip
+// (plus 2K warm-up rows) instead of once per tile.  Per 32-row input batch:
+//   * coalesced float4 loads, issued one batch ahead into registers, masked
+//     and written to an LDS stage;
+//   * row pass on the matrix cores: a 16-column output block is the banded
+//     product In[16 rows][k] x T[k][16] with T[k][n] = g[k - n] on
+//     v_mfma_f32_16x16x4f32 (float32 operands and accumulation).  Lane group
+//     q of the instruction owns k = q S .. q S + S - 1, so each lane reads its
+//     operand as S / 4 aligned 16-byte LDS loads and keeps its taps in
+//     registers for the whole strip;
+//   * the 16 x 16 results go to a ring of NB batches of row results in LDS;
+//   * column pass on the vector ALUs: each lane owns one column and eight
+//     consecutive output rows, reading 8 + 2K ring rows through per-group
+//     base addresses (the ring wraps only at 8-row group boundaries), then
+//     the fused epilogue.
+// While one wave's matrix instructions run, the vector ALUs run another
+// wave's column pass.
+template <int K>
+struct StripGeo {
+    static constexpr int SHIFT = (4 - K % 4) % 4;                  // stage col 0 = x0 - K - SHIFT
+    static constexpr int S = (16 + 2 * K + SHIFT + 15) / 16 * 4;   // k per lane group (4 S >= 16 + 2K + SHIFT)
+    static constexpr int LW = 48 + 4 * S;                          // staged columns
+    static constexpr int SW = LW + 4;                              // stage row stride (floats)
+    static constexpr int NB = (32 + 2 * K + 31) / 32;              // ring depth (32-row batches)
+    static constexpr int RS = kTileW + 1;                          // ring row stride
+    static constexpr int NWIN = 8 + 2 * K;                         // ring rows per lane
+    static constexpr int NG = (NWIN + 7) / 8;                      // 8-row groups per lane
+    static constexpr int NF = 32 * LW / 4;                         // float4 per batch
+    static constexpr int NL = (NF + 255) / 256;                    // float4 per thread
+    static constexpr int LDS_FLOATS = 32 * SW + NB * 32 * RS;
+};
+constexpr int kStripThreads = 256;
+
+template <int K, int IN, int OUT>
+__global__ __launch_bounds__(kStripThreads) void k_filter_strip(FiltArgs a, Taps tp) {
+    typedef StripGeo<K> G;
+    __shared__ __attribute__((aligned(16))) float lds[G::LDS_FLOATS];
+    float* stage = lds;
+    float* ring = lds + 32 * G::SW;
+    const int strips_y = (a.H + a.strip_h - 1) / a.strip_h;
+    const int per_band = a.tiles_x * strips_y;
+    const int lin = xcd_remap(blockIdx.x, gridDim.x);
+    const int b = lin / per_band;
+    const int rem = lin % per_band;
+    if (a.rej && ((*a.rej >> b) & 1u)) return;
+    const int sy = rem / a.tiles_x, tx = rem % a.tiles_x;
+    const int x0 = tx * kTileW;
+    const int ys = sy * a.strip_h;
+    const int ye = ys + a.strip_h < a.H ? ys + a.strip_h : a.H;
+    const size_t bo = (size_t)b * a.H * a.W;
+    const int tid = threadIdx.x;
+    const int wv = tid >> 6, lane = tid & 63, li = lane & 15, lq = lane >> 4;
+    const float* src = IN == IN_E ? a.E : a.X;
+
+    // ---- batch loads (one batch ahead, in registers)
+    float4 pf[G::NL];
+    uint32_t pm[G::NL];
+    auto prefetch = [&](int bi) {
+        const int gy0 = ys - K + 32 * bi;
+#pragma unroll
+        for (int i = 0; i < G::NL; ++i) {
+            const int f = tid + kStripThreads * i;
+            pf[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            pm[i] = 0u;
+            if (f < G::NF) {
+                const int row = f / (G::LW / 4), c4 = f % (G::LW / 4);
+                const int gy = gy0 + row, gx = x0 - K - G::SHIFT + 4 * c4;
+                if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
+                    pf[i] = *reinterpret_cast<const float4*>(src + bo + (size_t)gy * a.W + gx);
+                    if (IN == IN_MX) pm[i] = a.mbits ? a.mbits[(size_t)gy * a.mwords + (gx >> 5)] : 0xffffffffu;
+                }
+            }
+        }
+    };
+    auto stage_write = [&]() {
+#pragma unroll
+        for (int i = 0; i < G::NL; ++i) {
+            const int f = tid + kStripThreads * i;
+            if (f < G::NF) {
+                const int row = f / (G::LW / 4), c4 = f % (G::LW / 4);
+                float4 v = pf[i];
+                if (IN == IN_MX) {
+                    const int gx = x0 - K - G::SHIFT + 4 * c4;
+                    const uint32_t bits = pm[i] >> (gx & 31);
+                    v.x = (float)(bits & 1u) * v.x;
+                    v.y = (float)((bits >> 1) & 1u) * v.y;
+                    v.z = (float)((bits >> 2) & 1u) * v.z;
+                    v.w = (float)((bits >> 3) & 1u) * v.w;
+                }
+                *reinterpret_cast<float4*>(stage + row * G::SW + 4 * c4) = v;
+            }
+        }
+    };
+
+    // ---- row pass (matrix cores): wave wv owns output columns 16 wv .. 16 wv + 15
+    float tap[G::S];
+#pragma unroll
+    for (int s = 0; s < G::S; ++s) {
+        const int u = lq * G::S + s - G::SHIFT - li;
+        tap[s] = (u >= 0 && u <= 2 * K) ? tp.g[u] : 0.0f;
+    }
+    auto row_pass = [&](int bi) {
+        const int slot = bi % G::NB;
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            const float* sp = stage + (rb * 16 + li) * G::SW + wv * 16 + lq * G::S;
+#pragma unroll
+            for (int p4 = 0; p4 < G::S / 4; ++p4) {
+                const float4 av = *reinterpret_cast<const float4*>(sp + 4 * p4);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, tap[4 * p4 + 0], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, tap[4 * p4 + 1], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, tap[4 * p4 + 2], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, tap[4 * p4 + 3], acc, 0, 0, 0);
+            }
+            // acc[v] = row result for row rb*16 + 4 lq + v, column 16 wv + li
+            float* dst = ring + (slot * 32 + rb * 16 + 4 * lq) * G::RS + wv * 16 + li;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dst[v * G::RS] = acc[v];
+        }
+    };
+
+    // ---- column pass (vector ALUs): lane = column, rows 8 wv .. 8 wv + 7 of chunk j
+    // Each ring value t is read once and scattered into the outputs q it
+    // reaches (tap u = t - q), so only the eight sums stay in registers; per
+    // output the taps still accumulate in ascending u.
+    auto col_pass = [&](int j) {
+        float acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = 0.0f;
+#pragma unroll
+        for (int m = 0; m < G::NG; ++m) {
+            const int grp = wv + m;
+            const int slot = (j + grp / 4) % G::NB;
+            const float* rp = ring + (slot * 32 + (grp % 4) * 8) * G::RS + lane;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int t = 8 * m + r;
+                if (t >= G::NWIN) break;
+                const float wt = rp[r * G::RS];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int u = t - q;
+                    if (u >= 0 && u <= 2 * K)
+                        acc[q] = fmaf(tp.g[u <= K ? u : 2 * K - u], wt, acc[q]);   // symmetric taps
+                }
+            }
+        }
+        const int gx = x0 + lane;
+        if (gx >= a.W) return;
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+            const int gy0 = ys + 32 * j + 8 * wv + 4 * hf;
+            const int nv = ye - gy0 < 4 ? (ye - gy0 > 0 ? ye - gy0 : 0) : 4;
+            if (nv > 0) epilogue_col<OUT, 4>(a, b, bo, gy0, gx, acc + 4 * hf, nv);
+        }
+    };
+
+    const int nch = (ye - ys + 31) / 32;
+    const int nbat = nch + G::NB - 1;
+    prefetch(0);
+    for (int bi = 0; bi < nbat; ++bi) {
+        stage_write();
+        __syncthreads();                  // stage complete; ring slot bi % NB no longer read
+        if (bi + 1 < nbat) prefetch(bi + 1);
+        row_pass(bi);
+        __syncthreads();                  // ring holds batches bi - NB + 1 .. bi; stage free
+        const int j = bi - (G::NB - 1);
+        if (j >= 0) col_pass(j);
+    }
+}
+
 // Peaks after several clip iterations: P = Q and Y from the planes.
 __global__ __launch_bounds__(256) void k_peaks_planes(FiltArgs a) {
     const int b = blockIdx.y;
@@ -696,6 +913,40 @@ hipError_t run_fast(lpf_ctx* c, FiltArgs a, int nbands) {
     return hipGetLastError();
 }
 
+// Strip height: a multiple of 32 rows chosen so that a launch has about 2048
+// workgroups (8 per CU), unless overridden for tuning by LPF_STRIP_H.
+int strip_height(int H, int tiles_x, int nbands) {
+    const char* env = std::getenv("LPF_STRIP_H");
+    const int forced = env ? std::atoi(env) : 0;
+    const int chunks = (H + 31) / 32;
+    if (forced > 0) return ((forced + 31) / 32) * 32;
+    const int cols = tiles_x * (nbands > 0 ? nbands : 1);
+    int sy = (2048 + cols - 1) / cols;
+    if (sy > chunks) sy = chunks;
+    if (sy < 1) sy = 1;
+    return 32 * ((chunks + sy - 1) / sy);
+}
+
+template <int K, int IN, int OUT>
+hipError_t run_strip(lpf_ctx* c, FiltArgs a, int nbands) {
+    a.tiles_x = (a.W + kTileW - 1) / kTileW;
+    a.strip_h = strip_height(a.H, a.tiles_x, nbands);
+    const int nblocks = a.tiles_x * ((a.H + a.strip_h - 1) / a.strip_h) * nbands;
+    hipLaunchKernelGGL((k_filter_strip<K, IN, OUT>), dim3(nblocks), dim3(kStripThreads), 0, c->stream, a,
+                       c->taps);
+    return hipGetLastError();
+}
+
+template <int IN, int OUT>
+hipError_t dispatch_strip(lpf_ctx* c, const FiltArgs& a, int nbands) {
+    switch (c->d.k) {
+        case 15: return run_strip<15, IN, OUT>(c, a, nbands);
+        case 24: return run_strip<24, IN, OUT>(c, a, nbands);
+        case 36: return run_strip<36, IN, OUT>(c, a, nbands);
+        default: return hipErrorInvalidValue;  // derive() enables strips for these only
+    }
+}
+
 template <typename T, int K, int IN, int OUT>
 hipError_t run_mfma(lpf_ctx* c, FiltArgs a, int nbands) {
     a.tiles_y = (a.H + kTH2 - 1) / kTH2;
@@ -740,6 +991,7 @@ FiltArgs base_args(lpf_ctx* c, int slot) {
     a.Y = c->buf.clip;
     a.den = c->buf.den;
     a.inv_den = c->buf.inv_den;
+    a.E = c->buf.resid;
     a.mbits = c->d.masked ? c->buf.mask_bits : nullptr;
     a.mwords = c->d.mwords;
     a.rej = c->buf.cache_rej + slot;
@@ -795,16 +1047,18 @@ hipError_t launch_filters(lpf_ctx* c, int slot) {
     hipError_t e;
     FiltArgs a = base_args(c, slot);
     a.out = c->buf.centre;
+    a.E_out = c->buf.resid;
     {
         StageTimer tm(c, 2);
-        if ((e = dispatch_k<IN_MX, OUT_C_STATIC>(c, a, B)) != hipSuccess) return e;
+        e = c->d.strip ? dispatch_strip<IN_MX, OUT_C_E>(c, a, B) : dispatch_k<IN_MX, OUT_C_STATIC>(c, a, B);
+        if (e != hipSuccess) return e;
     }
     StageTimer tm3(c, 3);
     a = base_args(c, slot);
     if (iters == 1) {
         a.S_out = c->d.dyn ? c->buf.spread : nullptr;
         a.Y_out = c->d.dyn ? clip1 : nullptr;
-        return dispatch_k<IN_ME, OUT_S_PEAKS>(c, a, B);
+        return c->d.strip ? dispatch_strip<IN_E, OUT_S_PEAKS>(c, a, B) : dispatch_k<IN_ME, OUT_S_PEAKS>(c, a, B);
     }
     // Several iterations: S and Y planes are materialised and peaks are
     // listed after the last iteration.
@@ -814,7 +1068,8 @@ hipError_t launch_filters(lpf_ctx* c, int slot) {
     a.changed = c->buf.changed + B;   // changed[1]
     a.peak_cap = 0;                   // no peak records from this pass
     a.kp = 0;
-    if ((e = dispatch_k<IN_ME, OUT_S_PEAKS>(c, a, B)) != hipSuccess) return e;
+    e = c->d.strip ? dispatch_strip<IN_E, OUT_S_PEAKS>(c, a, B) : dispatch_k<IN_ME, OUT_S_PEAKS>(c, a, B);
+    if (e != hipSuccess) return e;
     for (int it = 2; it <= iters; ++it) {
         uint8_t* yin = ((it - 1) & 1) ? clip1 : clip0;
         uint8_t* yout = (it & 1) ? clip1 : clip0;

@@ -143,7 +143,101 @@ __global__ void k_ended_ends(const int32_t* list, const int32_t* count, const in
     }
 }
 
+// Ended episodes of one context appended to a model batch held on the device:
+// rows base .. base + take - 1 with base = hdr[0], take = min(n_ended, cap - base).
+struct GatherArgs {
+    int B, cap, ci;
+    const int32_t* list;      // ended slots [n_ended]
+    const int32_t* n_ended;
+    const int64_t* src_tend;
+    const int32_t* src_id;
+    const float* ring;
+    const int64_t* ring_t;
+    const uint32_t* ring_v;
+    int32_t row_band[kGridRows];
+    const int32_t* hdr;
+    float* out;               // [cap][16][64]
+    int32_t* rows;            // [cap][2]: (context index, id)
+};
+
+__global__ __launch_bounds__(256) void k_gather_ended(GatherArgs a) {
+    const int base = a.hdr[0];
+    const int n_end = *a.n_ended;
+    const int room = a.cap - base;
+    const int take = n_end < room ? n_end : (room > 0 ? room : 0);
+    const int64_t total = (int64_t)take * kGridRows * kRing;
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total;
+         w += (int64_t)gridDim.x * blockDim.x) {
+        const int e = (int)(w / (kGridRows * kRing));
+        const int row = (int)((w / kRing) % kGridRows);
+        const int c = (int)(w % kRing);
+        const int s = a.list[e];
+        const int b = a.row_band[row];
+        float v = 0.0f;
+        if (b >= 0) {
+            const int64_t tau = a.src_tend[s] - (kRing - 1) + c;
+            const int ri = pmod(tau, kRing);
+            if (a.ring_t[(size_t)s * kRing + ri] == tau && ((a.ring_v[(size_t)s * kRing + ri] >> b) & 1u))
+                v = a.ring[((size_t)s * a.B + b) * kRing + ri];
+        }
+        a.out[(size_t)(base + e) * kGridRows * kRing + (size_t)row * kRing + c] = v;
+        if (row == 0 && c == 0) {
+            a.rows[2 * (base + e)] = a.ci;
+            a.rows[2 * (base + e) + 1] = a.src_id[s];
+        }
+    }
+}
+
+// hdr[0] += rows taken from this context, hdr[1] += its ended episodes.
+__global__ void k_gather_advance(int32_t* hdr, const int32_t* n_ended, int cap) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int base = hdr[0], n_end = *n_ended;
+    const int room = cap - base;
+    hdr[0] = base + (n_end < room ? n_end : (room > 0 ? room : 0));
+    hdr[1] += n_end;
+}
+
+__global__ void k_gather_begin(int32_t* hdr) {
+    if (threadIdx.x < 4 && blockIdx.x == 0) hdr[threadIdx.x] = 0;
+}
+
 }  // namespace
+
+hipError_t launch_gather_begin(int32_t* hdr, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_begin, dim3(1), dim3(64), 0, s, hdr);
+    return hipGetLastError();
+}
+
+// Appends context c's ended episodes (as context index ci) to the batch; grid
+// sized for up to min(max_sources, cap) windows, counts read on the device.
+hipError_t launch_gather_ended(lpf_ctx* c, int ci, int32_t* hdr, float* out, int32_t* rows, int cap,
+                               hipStream_t s) {
+    GatherArgs a;
+    a.B = c->cfg.B;
+    a.cap = cap;
+    a.ci = ci;
+    a.list = c->buf.list_ended;
+    a.n_ended = &c->buf.status->n_ended;
+    a.src_tend = c->buf.src_tend;
+    a.src_id = c->buf.src_id;
+    a.ring = c->buf.ring;
+    a.ring_t = c->buf.ring_t;
+    a.ring_v = c->buf.ring_v;
+    for (int r = 0; r < kGridRows; ++r) a.row_band[r] = -1;
+    for (int b = 0; b < c->cfg.B; ++b) a.row_band[c->grid_rows[b]] = b;
+    a.hdr = hdr;
+    a.out = out;
+    a.rows = rows;
+    const int most = c->cfg.max_sources < cap ? c->cfg.max_sources : cap;
+    int blocks = (int)((((int64_t)most * kGridRows * kRing) + 255) / 256);
+    if (blocks > 512) blocks = 512;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_gather_ended, dim3(blocks), dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gather_advance, dim3(1), dim3(64), 0, s, hdr, &c->buf.status->n_ended, cap);
+    return hipGetLastError();
+}
 
 hipError_t launch_flux(lpf_ctx* c, int slot, int64_t t) {
     (void)slot;
@@ -179,9 +273,9 @@ hipError_t launch_flux(lpf_ctx* c, int slot, int64_t t) {
     return e;
 }
 
-// Gathers windows for n entries: d_slots[n], d_tend[n] on the device.
+// Gathers windows for n entries: d_slots[n], d_tend[n] on the device, on stream s.
 hipError_t launch_windows_gather(lpf_ctx* c, int n, const int32_t* d_slots, const int64_t* d_tend,
-                                 float* d_out) {
+                                 float* d_out, hipStream_t s) {
     WinArgs a;
     a.n = n;
     a.B = c->cfg.B;
@@ -196,7 +290,7 @@ hipError_t launch_windows_gather(lpf_ctx* c, int n, const int32_t* d_slots, cons
     int blocks = (int)((((int64_t)n * kGridRows * kRing) + 255) / 256);
     if (blocks > 1024) blocks = 1024;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_windows, dim3(blocks), dim3(256), 0, c->stream, a);
+    hipLaunchKernelGGL(k_windows, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -79,6 +79,7 @@ struct DevBufs {
     uint32_t* mask_bits;   // [H][mwords] packed sky mask
     float* inv_den;        // [H][W] 1 / (G * M), 0 where G * M = 0
     float* centre;         // [B][H][W]
+    float* resid;          // [B][H][W] E = M (X - C)^2 (strip kernels)
     float* spread;         // [B][H][W] (debug or iterations > 1)
     uint8_t* clip;         // [B][H][W] (debug or iterations > 1)
     float* den;            // [B][H][W] (iterations > 1)
@@ -127,6 +128,7 @@ struct Derived {
     int mwords;    // 32-bit words per packed mask row
     bool masked;
     bool dyn;      // iterations > 1 or debug planes: materialise S / Y
+    bool strip;    // float32 strip kernels (W % 4 == 0, k in {15, 24, 36}): residual plane E
 };
 
 }  // namespace lpf
@@ -150,6 +152,57 @@ struct lpf_ctx {
     size_t prof_next = 0;
     struct ProfRec { int stage; hipEvent_t a, b; };
     std::vector<ProfRec> prof_recs;
+    // ended episodes of the last detect as read back by it (count -1: not read)
+    int32_t host_n_ended = -1;
+    std::vector<int32_t> host_ended_ids;   // list order (the order of the ended-slot list)
+    hipEvent_t ev_ready = nullptr;         // cross-stream hand-off in pooled inference
+};
+
+namespace lpf {
+
+struct ModelLayout {
+    // float offsets inside the weight area
+    size_t w1, b1, w2, b2, w3, b3, w4, b4, f1, fb1, f2, fb2, total;
+};
+
+struct CnnWork {
+    float* act_a;     // [maxb][16][64][64] (float32 network)
+    float* act_b;
+    void* act16_a;    // [maxb][16][64][64] (16-bit network)
+    void* act16_b;
+    void* w16;        // 16-bit weights: conv2..4 [9][Cout][Cin], fc1 [128][65536]
+    float* part;      // [128][maxb_pad][128] fc1 split-K partials
+    float* hidden;    // [maxb][128]
+    float* windows;   // [maxb][16][64]
+    // result block, one contiguous device range (copied to the host in one piece):
+    int32_t* hdr;     // [4]: windows taken, ended episodes seen
+    int32_t* rows;    // [maxb][2]: (context index, source id)
+    float* mu;        // [maxb][4]
+    float* L;         // [maxb][10]
+    size_t out_bytes; // bytes of the result block
+};
+
+constexpr int kInflight = 4;   // asynchronous inference tickets outstanding per model
+
+}  // namespace lpf
+
+struct lpf_model {
+    int precision;
+    int max_batch;
+    float alpha;
+    float* wts;
+    lpf::ModelLayout lay;
+    lpf::CnnWork work;
+    hipStream_t stream;            // the caller's stream (weight upload)
+    hipStream_t istream = nullptr; // inference stream owned by the model
+    hipEvent_t ev_gathered = nullptr, ev_in = nullptr, ev_out = nullptr;
+    hipEvent_t ev_done[lpf::kInflight] = {};
+    char* h_res[lpf::kInflight] = {};          // pinned result blocks
+    int64_t slot_ticket[lpf::kInflight] = {-1, -1, -1, -1};
+    int64_t next_ticket = 0;
+    // pinned host staging for host-driven inference (grown on demand)
+    mutable float* h_out = nullptr;
+    mutable size_t h_cap = 0;   // rows
 };
 
 namespace lpf {
@@ -163,16 +216,17 @@ inline int xcd_count() { return 8; }
 struct StageTimer {
     lpf_ctx* c;
     int stage;
+    hipStream_t s;
     hipEvent_t b = nullptr;
-    StageTimer(lpf_ctx* ctx, int st) : c(ctx), stage(st) {
+    StageTimer(lpf_ctx* ctx, int st, hipStream_t on = nullptr) : c(ctx), stage(st), s(on ? on : ctx->stream) {
         if (!c->prof_on || c->prof_next + 2 > c->prof_pool.size()) return;
         hipEvent_t a = c->prof_pool[c->prof_next++];
         b = c->prof_pool[c->prof_next++];
-        (void)hipEventRecord(a, c->stream);
+        (void)hipEventRecord(a, s);
         c->prof_recs.push_back({stage, a, b});
     }
     ~StageTimer() {
-        if (b) (void)hipEventRecord(b, c->stream);
+        if (b) (void)hipEventRecord(b, s);
     }
 };
 

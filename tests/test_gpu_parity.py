@@ -127,6 +127,29 @@ def test_planes_kernel_variants(kernel, s, k):
     run_steps(ctx, orc, [cube], [0], compare_planes=True, label=f"k{kernel}-{s}-{k}")
 
 
+@pytest.mark.parametrize("k,strip_h", [(24, None), (15, None), (36, None), (24, "64"), (15, "96")])
+def test_strip_filters_ragged(k, strip_h, monkeypatch):
+    """Float32 strip kernels (W % 4 == 0, k in {15, 24, 36}): dense C / S planes
+    and peaks on a ragged image (W not a multiple of 64, H not a multiple of
+    32) with a sky mask, at the default strip height and at forced heights
+    that give several 32-row chunks per strip."""
+    _torch_cuda()
+    if strip_h is not None:
+        monkeypatch.setenv("LPF_STRIP_H", strip_h)
+    rng = np.random.default_rng(7 + k)
+    B, H, W = 3, 150, 196
+    mask = synth.sky_mask(H, W)
+    ctx, orc = make_pair(B, H, W, sky_mask=mask, debug_planes=1, kappa=3.5, bg_halfwidth=k,
+                         bg_sigma=k / 3.0)
+    frames = []
+    for t in range(2):
+        cube = (rng.standard_normal((B, H, W)) + 0.3).astype(np.float32)
+        for _ in range(5):
+            cube[rng.integers(B), rng.integers(10, H - 10), rng.integers(10, W - 10)] += 10.0
+        frames.append(cube * mask)
+    run_steps(ctx, orc, frames, [0, 1], compare_planes=True, label=f"strip-k{k}-h{strip_h}")
+
+
 def test_tiny_stream_full_pipeline():
     """4 subbands x 16 steps of 256^2 (the tiny workload): QC, peaks, events,
     dynamic spectra every step, then the network on the ended episodes."""
@@ -264,3 +287,69 @@ def test_network_on_ended_episodes_matches_oracle():
             assert np.all(np.abs(L_d - L_o) <= 1e-5 * sc[:, 4:] + 1e-6)
             checked += len(ids_o)
     assert checked >= 2
+
+
+def test_async_inference_lagged_and_batch_overflow():
+    """lpf_infer_async / lpf_infer_collect: results collected one step late
+    equal the oracle's for that step; more ended episodes than the model's
+    batch are reported by collect (EFULL) while lpf_infer falls back to
+    host-driven chunks and returns them all; at most four tickets."""
+    _torch_cuda()
+    from paper_2103_15418_amd import LpfError, Model
+    rng = np.random.default_rng(11)
+    B, H, W = 4, 96, 96
+    ctx, orc = make_pair(B, H, W, kappa=6.0, bg_sigma=3.0, backfill_steps=6, monitor_steps=4)
+    wts = synth.cnn_weights(seed=4)
+    big = Model(wts, max_batch=16)
+    small = Model(wts, max_batch=8)
+    spots = [(12 + 24 * i, 12 + 24 * j) for i in range(4) for j in range(4)][:12]
+    pending = None
+    checked = overflow_steps = 0
+
+    def compare(res, ref, label):
+        mu_d, L_d, src = res
+        mu_o, L_o, ids_o, x = ref
+        assert [int(s[1]) for s in src] == list(ids_o), label
+        if ids_o:
+            sc = cnn_scale(x, wts)
+            assert np.all(np.abs(mu_d - mu_o) <= 1e-5 * sc[:, :4] + 1e-6), label
+            assert np.all(np.abs(L_d - L_o) <= 1e-5 * sc[:, 4:] + 1e-6), label
+
+    for t in range(12):
+        cube = rng.standard_normal((B, H, W)).astype(np.float32)
+        if t == 3:
+            for (r, c) in spots:
+                cube[:, r, c] += 25.0
+        orc.ingest(t, cube)
+        ctx.ingest(t, cube)
+        orc.detect()
+        ctx.detect()
+        orc.extract_flux()
+        ctx.extract_flux()
+        mu_o, L_o, ids_o = orc.infer(wts)
+        x = np.stack([orc.spectrum(s)[0] for s in ids_o]) if ids_o else None
+        ref = (mu_o, L_o, ids_o, x)
+        tk = big.infer_async([ctx])                    # collected at the next step
+        if len(ids_o) > small.max_batch:
+            overflow_steps += 1
+            t_small = small.infer_async([ctx])
+            with pytest.raises(LpfError) as err:
+                small.collect(t_small)
+            assert err.value.code == -3                # LPF_EFULL
+            compare(small.infer([ctx]), ref, f"fallback t={t}")
+        if pending is not None:
+            compare(big.collect(pending[0]), pending[1], f"lagged t={t - 1}")
+            checked += len(pending[1][2])
+        pending = (tk, ref)
+    compare(big.collect(pending[0]), pending[1], "last")
+    checked += len(pending[1][2])
+    assert checked >= 12 and overflow_steps >= 1
+    # ticket limit: four outstanding, the fifth is refused
+    tks = [big.infer_async([ctx]) for _ in range(4)]
+    with pytest.raises(LpfError) as err:
+        big.infer_async([ctx])
+    assert err.value.code == -3
+    for tk in reversed(tks):                           # any collection order
+        big.collect(tk)
+    with pytest.raises(LpfError):
+        big.collect(tks[0])                            # already collected
