@@ -669,35 +669,35 @@ __global__ __launch_bounds__(kThreads2) void k_filter_mfma(FiltArgs a, Taps tp) 
 // Strip kernel (float32 path; compile-time half-width K; W % 4 == 0).
 // One 256-thread workgroup walks down a 64-column strip of one band in
 // chunks of 32 output rows, so every input row is row-filtered once per strip
-// (plus 2K warm-up rows) instead of once per tile.  Per 32-row input batch:
+// (plus 2K warm-up rows) instead of once per tile.  Both passes of the
+// separable filter are banded (Toeplitz) products on v_mfma_f32_16x16x4f32,
+// float32 operands and accumulation:
+//   row pass    Out[16 rows][16 cols] = In[16][k] x T[k][16],   T[k][n] = g[k - n]
+//   column pass Out[16 rows][16 cols] = T'[16][k] x R[k][16],   T'[m][k] = g[k - m]
+// Lane group q of the instruction owns k = q S .. q S + S - 1, so every lane
+// reads its operand as S / 4 aligned 16-byte LDS loads and keeps its S taps in
+// registers for the whole strip.  Per 32-row input batch:
 //   * coalesced float4 loads, issued one batch ahead into registers, masked
 //     and written to an LDS stage;
-//   * row pass on the matrix cores: a 16-column output block is the banded
-//     product In[16 rows][k] x T[k][16] with T[k][n] = g[k - n] on
-//     v_mfma_f32_16x16x4f32 (float32 operands and accumulation).  Lane group
-//     q of the instruction owns k = q S .. q S + S - 1, so each lane reads its
-//     operand as S / 4 aligned 16-byte LDS loads and keeps its taps in
-//     registers for the whole strip;
-//   * the 16 x 16 results go to a ring of NB batches of row results in LDS;
-//   * column pass on the vector ALUs: each lane owns one column and eight
-//     consecutive output rows, reading 8 + 2K ring rows through per-group
-//     base addresses (the ring wraps only at 8-row group boundaries), then
-//     the fused epilogue.
-// While one wave's matrix instructions run, the vector ALUs run another
-// wave's column pass.
+//   * row pass from the stage into a column-major ring of NB batches of row
+//     results (each lane writes its four rows of one column as one 16-byte
+//     store; the column pass reads four rows of one column the same way);
+//   * column pass for the chunk whose rows are complete; each lane ends with
+//     four consecutive rows of one column for the fused epilogue.
+// The vector ALUs only stage, normalise, threshold and test peaks.
 template <int K>
 struct StripGeo {
     static constexpr int SHIFT = (4 - K % 4) % 4;                  // stage col 0 = x0 - K - SHIFT
-    static constexpr int S = (16 + 2 * K + SHIFT + 15) / 16 * 4;   // k per lane group (4 S >= 16 + 2K + SHIFT)
+    static constexpr int S = (16 + 2 * K + SHIFT + 15) / 16 * 4;   // row pass: k per lane group
+    static constexpr int SC = (16 + 2 * K + 15) / 16 * 4;          // column pass: k per lane group
     static constexpr int LW = 48 + 4 * S;                          // staged columns
     static constexpr int SW = LW + 4;                              // stage row stride (floats)
-    static constexpr int NB = (32 + 2 * K + 31) / 32;              // ring depth (32-row batches)
-    static constexpr int RS = kTileW + 1;                          // ring row stride
-    static constexpr int NWIN = 8 + 2 * K;                         // ring rows per lane
-    static constexpr int NG = (NWIN + 7) / 8;                      // 8-row groups per lane
+    static constexpr int NB = (16 + 4 * SC + 31) / 32;             // ring depth (32-row batches)
+    static constexpr int RING = NB * 32;                           // ring rows
+    static constexpr int RT = RING + 4;                            // ring column stride (floats)
     static constexpr int NF = 32 * LW / 4;                         // float4 per batch
     static constexpr int NL = (NF + 255) / 256;                    // float4 per thread
-    static constexpr int LDS_FLOATS = 32 * SW + NB * 32 * RS;
+    static constexpr int LDS_FLOATS = 32 * SW + kTileW * RT;
 };
 constexpr int kStripThreads = 256;
 
@@ -706,7 +706,7 @@ __global__ __launch_bounds__(kStripThreads) void k_filter_strip(FiltArgs a, Taps
     typedef StripGeo<K> G;
     __shared__ __attribute__((aligned(16))) float lds[G::LDS_FLOATS];
     float* stage = lds;
-    float* ring = lds + 32 * G::SW;
+    float* ring = lds + 32 * G::SW;   // [64 columns][RT]
     const int strips_y = (a.H + a.strip_h - 1) / a.strip_h;
     const int per_band = a.tiles_x * strips_y;
     const int lin = xcd_remap(blockIdx.x, gridDim.x);
@@ -762,13 +762,20 @@ __global__ __launch_bounds__(kStripThreads) void k_filter_strip(FiltArgs a, Taps
         }
     };
 
-    // ---- row pass (matrix cores): wave wv owns output columns 16 wv .. 16 wv + 15
-    float tap[G::S];
+    // taps in registers: B operand of the row pass, A operand of the column pass
+    float tap[G::S], tapc[G::SC];
 #pragma unroll
     for (int s = 0; s < G::S; ++s) {
         const int u = lq * G::S + s - G::SHIFT - li;
         tap[s] = (u >= 0 && u <= 2 * K) ? tp.g[u] : 0.0f;
     }
+#pragma unroll
+    for (int s = 0; s < G::SC; ++s) {
+        const int u = lq * G::SC + s - li;
+        tapc[s] = (u >= 0 && u <= 2 * K) ? tp.g[u] : 0.0f;
+    }
+
+    // ---- row pass: wave wv owns columns 16 wv .. 16 wv + 15 of both 16-row halves
     auto row_pass = [&](int bi) {
         const int slot = bi % G::NB;
 #pragma unroll
@@ -783,46 +790,39 @@ __global__ __launch_bounds__(kStripThreads) void k_filter_strip(FiltArgs a, Taps
                 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, tap[4 * p4 + 2], acc, 0, 0, 0);
                 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, tap[4 * p4 + 3], acc, 0, 0, 0);
             }
-            // acc[v] = row result for row rb*16 + 4 lq + v, column 16 wv + li
-            float* dst = ring + (slot * 32 + rb * 16 + 4 * lq) * G::RS + wv * 16 + li;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) dst[v * G::RS] = acc[v];
+            // acc[v] = row result of batch row rb*16 + 4 lq + v at column 16 wv + li
+            float* dst = ring + (wv * 16 + li) * G::RT + slot * 32 + rb * 16 + 4 * lq;
+            *reinterpret_cast<float4*>(dst) = make_float4(acc[0], acc[1], acc[2], acc[3]);
         }
     };
 
-    // ---- column pass (vector ALUs): lane = column, rows 8 wv .. 8 wv + 7 of chunk j
-    // Each ring value t is read once and scattered into the outputs q it
-    // reaches (tap u = t - q), so only the eight sums stay in registers; per
-    // output the taps still accumulate in ascending u.
+    // ---- column pass for chunk j: wave wv owns columns 16 wv .. +15, both 16-row halves
     auto col_pass = [&](int j) {
-        float acc[8];
+        const int gx = x0 + wv * 16 + li;
+        floatx4 acc[2];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] = 0.0f;
+        for (int ob = 0; ob < 2; ++ob) {
+            acc[ob] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            const float* cp = ring + (wv * 16 + li) * G::RT;
+            const int r0 = 32 * j + ob * 16 + lq * G::SC;     // relative ring row of this lane's k range
 #pragma unroll
-        for (int m = 0; m < G::NG; ++m) {
-            const int grp = wv + m;
-            const int slot = (j + grp / 4) % G::NB;
-            const float* rp = ring + (slot * 32 + (grp % 4) * 8) * G::RS + lane;
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const int t = 8 * m + r;
-                if (t >= G::NWIN) break;
-                const float wt = rp[r * G::RS];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int u = t - q;
-                    if (u >= 0 && u <= 2 * K)
-                        acc[q] = fmaf(tp.g[u <= K ? u : 2 * K - u], wt, acc[q]);   // symmetric taps
-                }
+            for (int p4 = 0; p4 < G::SC / 4; ++p4) {
+                const int rr = (r0 + 4 * p4) % G::RING;
+                const float4 bv = *reinterpret_cast<const float4*>(cp + rr);
+                acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(tapc[4 * p4 + 0], bv.x, acc[ob], 0, 0, 0);
+                acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(tapc[4 * p4 + 1], bv.y, acc[ob], 0, 0, 0);
+                acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(tapc[4 * p4 + 2], bv.z, acc[ob], 0, 0, 0);
+                acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(tapc[4 * p4 + 3], bv.w, acc[ob], 0, 0, 0);
             }
         }
-        const int gx = x0 + lane;
+        // acc[ob][v] = output row ys + 32 j + 16 ob + 4 lq + v, column gx
         if (gx >= a.W) return;
 #pragma unroll
-        for (int hf = 0; hf < 2; ++hf) {
-            const int gy0 = ys + 32 * j + 8 * wv + 4 * hf;
+        for (int ob = 0; ob < 2; ++ob) {
+            const int gy0 = ys + 32 * j + 16 * ob + 4 * lq;
             const int nv = ye - gy0 < 4 ? (ye - gy0 > 0 ? ye - gy0 : 0) : 4;
-            if (nv > 0) epilogue_col<OUT, 4>(a, b, bo, gy0, gx, acc + 4 * hf, nv);
+            float v4[4] = {acc[ob][0], acc[ob][1], acc[ob][2], acc[ob][3]};
+            if (nv > 0) epilogue_col<OUT, 4>(a, b, bo, gy0, gx, v4, nv);
         }
     };
 
@@ -831,7 +831,7 @@ __global__ __launch_bounds__(kStripThreads) void k_filter_strip(FiltArgs a, Taps
     prefetch(0);
     for (int bi = 0; bi < nbat; ++bi) {
         stage_write();
-        __syncthreads();                  // stage complete; ring slot bi % NB no longer read
+        __syncthreads();                  // stage complete; ring batch bi % NB no longer read
         if (bi + 1 < nbat) prefetch(bi + 1);
         row_pass(bi);
         __syncthreads();                  // ring holds batches bi - NB + 1 .. bi; stage free
