@@ -274,8 +274,10 @@ def main():
     for i, f in enumerate(frames):
         pool[i].copy_(torch.from_numpy(f))
     del frames
-    def run(precision, steps, warmup):
-        """Times `steps` steps after `warmup`; returns (elapsed s, latencies, stage profile, windows)."""
+    def run(precision, steps, warmup, frames=None):
+        """Times `steps` steps after `warmup`; returns (elapsed s, latencies, stage profile, windows).
+        frames: the cubes to cycle through (default: the device-resident pool)."""
+        frames = pool if frames is None else frames
         ctx = Context(B, H, W, sky_mask=st.mask, filter_precision=precision)
         model = Model(synth.cnn_weights(), precision=precision, max_batch=1024)
         torch.cuda.synchronize()
@@ -285,7 +287,7 @@ def main():
         def step(t):
             # the network's results of step t are collected during step t + 1,
             # so the host enqueues the next frame while the device finishes
-            ctx.ingest(t, pool[t % n_pool])
+            ctx.ingest(t, frames[t % len(frames)])
             ctx.detect(want=False)
             ctx.extract_flux()
             pending.append(model.infer_async([ctx]))
@@ -387,6 +389,13 @@ def main():
     }
     out["network_batch1024"] = {name: network_batch(Model, synth.cnn_weights(), code)
                                 for code, name in ((0, "fp32"), (1, "bf16"), (2, "fp16"))}
+    # cubes handed over from pinned host memory: the rate including the PCIe copy (not `value`)
+    host_pool = [f.cpu().pin_memory() for f in pool[:2]]
+    el_h, _, _, _, _ = run(0, min(args.steps, 20), 2, frames=host_pool)
+    out["pcie_inclusive"] = {"value": min(args.steps, 20) * px_step / el_h, "unit": "subband-px/s",
+                             "ms_per_step": el_h / min(args.steps, 20) * 1e3,
+                             "note": "cubes copied host->device each step from pinned memory"}
+    del host_pool
     # precision forms: bf16 / fp16 operands on MFMA (filters and network), float32 accumulation
     if not args.no_precision_forms:
         forms = {}

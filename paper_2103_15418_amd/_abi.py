@@ -201,9 +201,10 @@ class Context:
     def ingest(self, t: int, cube, want_rejected: bool = False) -> Optional[int]:
         torch = _torch()
         if isinstance(cube, torch.Tensor):
-            assert cube.is_cuda and cube.dtype == torch.float32 and cube.is_contiguous()
+            # device tensor, or host tensor (pinned memory keeps the copy asynchronous)
+            assert cube.dtype == torch.float32 and cube.is_contiguous()
             assert tuple(cube.shape) == (self.B, self.H, self.W)
-            ptr, on_dev = cube.data_ptr(), 1
+            ptr, on_dev = cube.data_ptr(), (1 if cube.is_cuda else 0)
             keep = cube
         else:
             keep = np.ascontiguousarray(cube, dtype=np.float32)
