@@ -129,6 +129,8 @@ size_t carve(const lpf_config* c, const Derived& d, char* base, DevBufs* b) {
     b->bandstats = cv.take<double>(6 * kMaxB);
     b->changed = cv.take<int32_t>((kMaxIters + 1) * kMaxB);
     b->peak_cnt = cv.take<int32_t>(kMaxB);
+    b->cand = d.strip ? cv.take<int2>(d.plane) : nullptr;
+    b->cand_cnt = cv.take<int32_t>(kMaxB);
     b->peak_raw = cv.take<PeakRec>((size_t)c->B * c->peak_cap);
     b->peak_sorted = cv.take<PeakRec>((size_t)c->B * c->peak_cap);
     b->cat_dec = cv.take<int32_t>(kCatMaxPeaks);

@@ -82,6 +82,8 @@ struct FiltArgs {
     const int32_t* active;  // per-band active flags (null = all)
     int32_t* changed;    // per-band changed flags (OUT_S_DYN / OUT_S_PEAKS with Y plane)
     int32_t* peak_cnt;   // [B]
+    int2* cand;          // [B][H*W] above-threshold pixels (pixel index, S bits) for the deferred peak test
+    int32_t* cand_cnt;   // [B]
     PeakRec* peak_raw;   // [B][cap]
     int peak_cap;
     int kp;              // max-filter half-width
@@ -171,8 +173,37 @@ __device__ inline void corr16_col(const float* src, int stride, const Taps& tp, 
     }
 }
 
+// Local-maximum test (Sec. 2.1.2) with a compile-time half-width: the loads
+// of one window row (from clamped, always valid addresses) are issued before
+// its comparisons, so a lane pays one memory latency per row rather than per
+// pixel, with few registers held (the test runs inside the filter epilogue).
+template <int KP>
+__device__ inline bool is_peak_k(const FiltArgs& a, size_t bo, int y, int x, float xv) {
+    constexpr int N = 2 * KP + 1;
+    bool peak = true;
+#pragma unroll 1
+    for (int dy = 0; dy < N; ++dy) {
+        const int yy = y + dy - KP;
+        if (yy < 0 || yy >= a.H) continue;
+        float v[N];
+        bool in[N];
+#pragma unroll
+        for (int dx = 0; dx < N; ++dx) {
+            const int xx = x + dx - KP;
+            const int xc = xx < 0 ? 0 : (xx >= a.W ? a.W - 1 : xx);
+            const size_t p = (size_t)yy * a.W + xc;
+            v[dx] = a.X[bo + p];
+            in[dx] = xx >= 0 && xx < a.W && (a.M ? a.M[p] != 0 : true);
+        }
+#pragma unroll
+        for (int dx = 0; dx < N; ++dx) peak = peak && !(in[dx] && v[dx] > xv);
+    }
+    return peak;
+}
+
 __device__ inline bool is_peak(const FiltArgs& a, size_t bo, int y, int x, float xv) {
     const int kp = a.kp;
+    if (kp == 3) return is_peak_k<3>(a, bo, y, x, xv);   // the paper's 7 x 7 window
     for (int dy = -kp; dy <= kp; ++dy) {
         const int yy = y + dy;
         if (yy < 0 || yy >= a.H) continue;
@@ -185,6 +216,24 @@ __device__ inline bool is_peak(const FiltArgs& a, size_t bo, int y, int x, float
         }
     }
     return true;
+}
+
+// Peak test and record append for one above-threshold pixel.
+__device__ inline void record_if_peak(const FiltArgs& a, int b, size_t bo, int gy, int gx,
+                                                         float xv, float cv, float s) {
+    if (!is_peak(a, bo, gy, gx, xv)) return;
+    const int idx = atomicAdd(&a.peak_cnt[b], 1);
+    if (idx < a.peak_cap) {
+        PeakRec rec;
+        rec.band = b;
+        rec.row = gy;
+        rec.col = gx;
+        rec.x = xv;
+        rec.c = cv;
+        rec.s = s;
+        rec.sig = (xv - cv) / sqrtf(s);
+        a.peak_raw[(size_t)b * a.peak_cap + idx] = rec;
+    }
 }
 
 // Per-output epilogue: normalisation, threshold, peak test, stores.
@@ -325,24 +374,8 @@ __device__ inline void epilogue_col(const FiltArgs& a, int b, size_t bo, int gy0
             }
         }
         if (any) {
-            for (int q = 0; q < NQ; ++q) {
-                if (!y[q]) continue;
-                const int gy = gy0 + q;
-                if (is_peak(a, bo, gy, gx, xv[q])) {
-                    const int idx = atomicAdd(&a.peak_cnt[b], 1);
-                    if (idx < a.peak_cap) {
-                        PeakRec rec;
-                        rec.band = b;
-                        rec.row = gy;
-                        rec.col = gx;
-                        rec.x = xv[q];
-                        rec.c = cv[q];
-                        rec.s = s[q];
-                        rec.sig = (xv[q] - cv[q]) / sqrtf(s[q]);
-                        a.peak_raw[(size_t)b * a.peak_cap + idx] = rec;
-                    }
-                }
-            }
+            for (int q = 0; q < NQ; ++q)
+                if (y[q]) record_if_peak(a, b, bo, gy0 + q, gx, xv[q], cv[q], s[q]);
             if (a.changed) a.changed[b] = 1;
         }
     } else {
@@ -666,6 +699,69 @@ __global__ __launch_bounds__(kThreads2) void k_filter_mfma(FiltArgs a, Taps tp) 
     }
 }
 
+// Spread epilogue of the strip kernels (four vertically consecutive outputs):
+// S, threshold and the optional S / Y planes as everywhere, but the 7 x 7
+// local-maximum test of the (few) above-threshold pixels is deferred to
+// k_peak_cands through a per-band list that can hold every pixel, so the
+// filter kernel neither waits on the window loads nor holds their registers.
+__device__ inline void strip_spread_epilogue(const FiltArgs& a, int b, size_t bo, int gy0, int gx, const float* v,
+                                             int nvalid) {
+    float id[4], cv[4], xv[4];
+    bool mk[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int gy = gy0 + q < a.H ? gy0 + q : a.H - 1;
+        const size_t p = (size_t)gy * a.W + gx;
+        id[q] = a.inv_den[p];
+        cv[q] = a.C[bo + p];
+        xv[q] = a.X[bo + p];
+        mk[q] = q < nvalid && (a.M ? a.M[p] != 0 : true);
+    }
+    bool y[4];
+    float s[4];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        s[q] = v[q] * id[q];
+        y[q] = mk[q] && id[q] > 0.0f && xv[q] > cv[q] + a.kappa * sqrtf(s[q]);
+        any |= y[q];
+    }
+    if (a.S_out || a.Y_out || a.Y_out2) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q >= nvalid) continue;
+            const size_t p = bo + (size_t)(gy0 + q) * a.W + gx;
+            if (a.S_out) a.S_out[p] = s[q];
+            if (a.Y_out) a.Y_out[p] = y[q] ? 1 : 0;
+            if (a.Y_out2) a.Y_out2[p] = y[q] ? 1 : 0;
+        }
+    }
+    if (!any) return;
+    if (a.peak_cap > 0) {
+        for (int q = 0; q < 4; ++q) {
+            if (!y[q]) continue;
+            const int idx = atomicAdd(&a.cand_cnt[b], 1);   // < H * W: each pixel is listed once
+            a.cand[(size_t)b * a.H * a.W + idx] = make_int2((gy0 + q) * a.W + gx, __float_as_int(s[q]));
+        }
+    }
+    if (a.changed) a.changed[b] = 1;
+}
+
+// Deferred peak test: one lane per listed above-threshold pixel.
+__global__ __launch_bounds__(256) void k_peak_cands(FiltArgs a) {
+    const int b = blockIdx.y;
+    if (a.rej && ((*a.rej >> b) & 1u)) return;
+    const int n = a.cand_cnt[b];
+    const size_t bo = (size_t)b * a.H * a.W;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int2 e = a.cand[bo + i];
+        const int gy = e.x / a.W, gx = e.x % a.W;
+        const float s = __int_as_float(e.y);
+        const float xv = a.X[bo + e.x], cv = a.C[bo + e.x];
+        record_if_peak(a, b, bo, gy, gx, xv, cv, s);
+    }
+}
+
 // Strip kernel (float32 path; compile-time half-width K; W % 4 == 0).
 // One 256-thread workgroup walks down a 64-column strip of one band in
 // chunks of 32 output rows, so every input row is row-filtered once per strip
@@ -822,7 +918,9 @@ __global__ __launch_bounds__(kStripThreads) void k_filter_strip(FiltArgs a, Taps
             const int gy0 = ys + 32 * j + 16 * ob + 4 * lq;
             const int nv = ye - gy0 < 4 ? (ye - gy0 > 0 ? ye - gy0 : 0) : 4;
             float v4[4] = {acc[ob][0], acc[ob][1], acc[ob][2], acc[ob][3]};
-            if (nv > 0) epilogue_col<OUT, 4>(a, b, bo, gy0, gx, v4, nv);
+            if (nv <= 0) continue;
+            if (OUT == OUT_S_PEAKS) strip_spread_epilogue(a, b, bo, gy0, gx, v4, nv);
+            else epilogue_col<OUT, 4>(a, b, bo, gy0, gx, v4, nv);
         }
     };
 
@@ -883,9 +981,10 @@ __global__ void k_pack_mask(const uint8_t* __restrict__ m, uint32_t* __restrict_
     }
 }
 
-__global__ void k_detect_init(int32_t* peak_cnt, int32_t* changed, int n_changed, int B) {
+__global__ void k_detect_init(int32_t* peak_cnt, int32_t* cand_cnt, int32_t* changed, int n_changed, int B) {
     const int i = threadIdx.x + blockIdx.x * blockDim.x;
     if (i < B) peak_cnt[i] = 0;
+    if (cand_cnt && i < B) cand_cnt[i] = 0;
     if (i < n_changed) changed[i] = 0;
 }
 
@@ -999,6 +1098,8 @@ FiltArgs base_args(lpf_ctx* c, int slot) {
     a.mwords = c->d.mwords;
     a.rej = c->buf.cache_rej + slot;
     a.peak_cnt = c->buf.peak_cnt;
+    a.cand = c->buf.cand;
+    a.cand_cnt = c->buf.cand_cnt;
     a.peak_raw = c->buf.peak_raw;
     a.peak_cap = c->cfg.peak_cap;
     a.kp = c->cfg.peak_halfwidth;
@@ -1033,7 +1134,7 @@ hipError_t launch_inv_den(lpf_ctx* c) {
 hipError_t launch_detect_init(lpf_ctx* c) {
     const int nch = (kMaxIters + 1) * c->cfg.B;
     hipLaunchKernelGGL(k_detect_init, dim3((nch + 255) / 256), dim3(256), 0, c->stream,
-                       c->buf.peak_cnt, c->buf.changed, nch, c->cfg.B);
+                       c->buf.peak_cnt, c->buf.cand_cnt, c->buf.changed, nch, c->cfg.B);
     return hipGetLastError();
 }
 
@@ -1061,7 +1162,10 @@ hipError_t launch_filters(lpf_ctx* c, int slot) {
     if (iters == 1) {
         a.S_out = c->d.dyn ? c->buf.spread : nullptr;
         a.Y_out = c->d.dyn ? clip1 : nullptr;
-        return c->d.strip ? dispatch_strip<IN_E, OUT_S_PEAKS>(c, a, B) : dispatch_k<IN_ME, OUT_S_PEAKS>(c, a, B);
+        if (!c->d.strip) return dispatch_k<IN_ME, OUT_S_PEAKS>(c, a, B);
+        if ((e = dispatch_strip<IN_E, OUT_S_PEAKS>(c, a, B)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_peak_cands, dim3(16, B), dim3(256), 0, c->stream, a);
+        return hipGetLastError();
     }
     // Several iterations: S and Y planes are materialised and peaks are
     // listed after the last iteration.
@@ -1093,7 +1197,7 @@ hipError_t launch_filters(lpf_ctx* c, int slot) {
         if ((e = dispatch_k<IN_WE, OUT_S_DYN>(c, ss, B)) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_detect_init, dim3(1), dim3(64), 0, c->stream, c->buf.peak_cnt,
-                       (int32_t*)nullptr, 0, B);
+                       (int32_t*)nullptr, (int32_t*)nullptr, 0, B);
     FiltArgs p = base_args(c, slot);
     p.Y = (iters & 1) ? clip1 : clip0;
     p.den = c->buf.spread;  // k_peaks_planes reads S through the den slot

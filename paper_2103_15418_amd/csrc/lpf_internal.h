@@ -87,6 +87,8 @@ struct DevBufs {
     double* bandstats;     // [B][6]
     int32_t* changed;      // [kMaxIters + 1][B]
     int32_t* peak_cnt;     // [B]
+    int2* cand;            // [B][H*W] above-threshold pixels awaiting the peak test (strip kernels)
+    int32_t* cand_cnt;     // [B]
     PeakRec* peak_raw;     // [B][peak_cap]
     PeakRec* peak_sorted;  // [B * peak_cap]
     // catalogue scratch
