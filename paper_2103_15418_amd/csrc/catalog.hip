@@ -135,6 +135,35 @@ __device__ int block_scan(int v, int* s_tmp, int* total) {
     return res;
 }
 
+// Eight consecutive table entries s0 .. s0 + 7 of one thread (fill past S):
+// 16-byte loads when the group is whole, so a wave touches each cache line
+// once per instruction pair instead of once per entry.
+__device__ inline void load8(const int32_t* p, int s0, int S, int fill, int* out) {
+    if (s0 + 8 <= S) {
+        const int4 a = *reinterpret_cast<const int4*>(p + s0);
+        const int4 b = *reinterpret_cast<const int4*>(p + s0 + 4);
+        out[0] = a.x; out[1] = a.y; out[2] = a.z; out[3] = a.w;
+        out[4] = b.x; out[5] = b.y; out[6] = b.z; out[7] = b.w;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) out[i] = s0 + i < S ? p[s0 + i] : fill;
+    }
+}
+
+__device__ inline void load8(const int64_t* p, int s0, int S, int64_t fill, int64_t* out) {
+    if (s0 + 8 <= S) {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const longlong2 v = *reinterpret_cast<const longlong2*>(p + s0 + 2 * h);
+            out[2 * h] = v.x;
+            out[2 * h + 1] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) out[i] = s0 + i < S ? p[s0 + i] : fill;
+    }
+}
+
 __device__ inline int pack_pos(int i, int j) { return (i << 16) | j; }
 __device__ inline int pos_i(int p) { return p >> 16; }
 __device__ inline int pos_j(int p) { return p & 0xffff; }
@@ -148,6 +177,7 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
     __shared__ int32_t s_pos[kCatMaxPeaks];          // 32 KB: positions in visiting order
     __shared__ uint8_t s_flag[kCatMaxPeaks];         //  8 KB: kept flags
     __shared__ uint32_t s_taken[kMaxSources / 32];   //  8 KB: taken bitmap
+    __shared__ uint32_t s_seen[kMaxSources / 32];    //  8 KB: slots named by some candidate list
     __shared__ int32_t s_cand[kLdsKept * (kCand + 1)];  // 18 KB: candidate lists
     __shared__ int32_t s_dec[kLdsKept];              //  2 KB: association decisions
     __shared__ uint64_t s_wkey[(kCatThreads / 64) * kCand];  // per-wave candidate keys
@@ -186,7 +216,10 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
             a.src_new[s] = 0;
         }
     }
-    for (int w = tid; w < (S + 31) / 32; w += kCatThreads) s_taken[w] = 0u;
+    for (int w = tid; w < (S + 31) / 32; w += kCatThreads) {
+        s_taken[w] = 0u;
+        s_seen[w] = 0u;
+    }
     if (tid == 0) {
         int off = 0;
         uint32_t ovf = 0;
@@ -209,33 +242,28 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
     while (Ppad < P) Ppad <<= 1;
     for (int n = tid; n < Ppad; n += kCatThreads) s_keys[n] = ~0ull;
     __syncthreads();
-    for (int b = 0; b < a.B; ++b) {
-        if ((s_overflow >> b) & 1u) continue;
-        const int n0 = s_off[b], cnt = s_off[b + 1] - n0;
-        for (int q = tid; q < cnt; q += kCatThreads) {
-            const PeakRec& r = a.peak_raw[(size_t)b * a.peak_cap + q];
-            const uint32_t key = ((uint32_t)r.band << 24) | ((uint32_t)r.row << 12) | (uint32_t)r.col;
-            s_keys[n0 + q] = ((uint64_t)key << 32) | (uint32_t)(b * a.peak_cap + q);
-        }
+    // one pass over all listed peaks (overflowed bands have empty ranges)
+    for (int n = tid; n < P; n += kCatThreads) {
+        int b = 0;
+        while (n >= s_off[b + 1]) ++b;
+        const int q = n - s_off[b];
+        const PeakRec& r = a.peak_raw[(size_t)b * a.peak_cap + q];
+        const uint32_t key = ((uint32_t)r.band << 24) | ((uint32_t)r.row << 12) | (uint32_t)r.col;
+        s_keys[n] = ((uint64_t)key << 32) | (uint32_t)(b * a.peak_cap + q);
     }
     __syncthreads();
     if (P > 1) sort_keys(s_keys, Ppad);
+    // copy in (band, row, col) order; the same lane writes the visiting-order
+    // key of position n (x descending, then rank n); padding keys stay ~0
     for (int n = tid; n < P; n += kCatThreads) {
         const uint32_t ref = (uint32_t)(s_keys[n] & 0xffffffffu);
-        a.peak_sorted[n] = a.peak_raw[ref];
-    }
-    __syncthreads();  // peak_sorted is read back below (global, same block)
-
-    // ---- 2. visiting order: x descending, then (band, row, col) = rank
-    for (int n = tid; n < Ppad; n += kCatThreads) {
-        if (n < P) {
-            const uint32_t ox = ~ordered(a.peak_sorted[n].x);
-            s_keys[n] = ((uint64_t)ox << 32) | (uint32_t)n;
-        } else {
-            s_keys[n] = ~0ull;
-        }
+        const PeakRec rec = a.peak_raw[ref];
+        a.peak_sorted[n] = rec;
+        s_keys[n] = ((uint64_t)(~ordered(rec.x)) << 32) | (uint32_t)n;
     }
     __syncthreads();
+
+    // ---- 2. visiting order: x descending, then (band, row, col) = rank
     if (P > 1) sort_keys(s_keys, Ppad);
     for (int q = tid; q < P; q += kCatThreads) {
         const int n = (int)(s_keys[q] & 0xffffffffu);
@@ -261,18 +289,26 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
         nb[0] = cnt;
     }
     __syncthreads();
+    // A peak without an earlier neighbour is kept whatever the others do: mark
+    // those in parallel; the greedy pass visits only peaks with neighbours.
+    for (int q = tid; q < P; q += kCatThreads) s_flag[q] = nbr[(size_t)q * (kNbr + 1)] == 0 ? 1 : 2;
+    __syncthreads();
     if (tid == 0) {
         int K = 0;
         for (int q = 0; q < P; ++q) {
+            if (s_flag[q] == 1) {
+                ++K;
+                continue;
+            }
             const int32_t* nb = nbr + (size_t)q * (kNbr + 1);
             const int cnt = nb[0];
             bool keep = true;
             if (cnt > kNbr) {  // long list: test every earlier peak that was kept
                 for (int r = 0; r < q && keep; ++r)
-                    if (s_flag[r] && dist2(s_pos[q], s_pos[r]) <= a.r_dup2) keep = false;
+                    if (s_flag[r] == 1 && dist2(s_pos[q], s_pos[r]) <= a.r_dup2) keep = false;
             } else {
                 for (int r = 0; r < cnt && keep; ++r)
-                    if (s_flag[nb[1 + r]]) keep = false;
+                    if (s_flag[nb[1 + r]] == 1) keep = false;
             }
             s_flag[q] = keep ? 1 : 0;
             K += keep;
@@ -303,8 +339,7 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
         for (int base = 0; base < S; base += 8 * kCatThreads) {
             const int s0 = base + tid * 8;
             int st[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) st[i] = s0 + i < S ? a.src_state[s0 + i] : -1;
+            load8(a.src_state, s0, S, -1, st);
             int nl = 0, nf = 0, nh = 0;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
@@ -404,10 +439,50 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
     }
     __syncthreads();
 
-    // ---- 4c. greedy resolution in visiting order (one lane, LDS data only):
-    // dec[kq] = matched slot (>= 0), -1 - r for the r-th new source, or
-    // INT32_MIN for a peak dropped at capacity.
-    if (tid == 0) {
+    // ---- 4c. resolution in visiting order: dec[kq] = matched slot (>= 0),
+    // -1 - r for the r-th new source, or INT32_MIN for a peak dropped at
+    // capacity.  When every candidate list is complete and no slot appears in
+    // two lists, no peak can take another's candidate: each takes its first
+    // one and new sources are numbered by a prefix count (parallel).
+    // Otherwise one lane resolves greedily on LDS data.
+    int conflict = 0;
+    for (int kq = tid; kq < K; kq += kCatThreads) {
+        const int32_t* cl = cand + (size_t)kq * (kCand + 1);
+        if (cl[0] < 0) {
+            conflict = 1;
+            continue;
+        }
+        for (int m = 0; m < cl[0]; ++m) {
+            const int sl = cl[1 + m];
+            const uint32_t bit = 1u << (sl & 31);
+            if (atomicOr(&s_seen[sl >> 5], bit) & bit) conflict = 1;
+        }
+    }
+    conflict = __syncthreads_or(conflict);
+    if (!conflict) {
+        const int per = (K + kCatThreads - 1) / kCatThreads;
+        const int q0 = tid * per, q1 = min(K, q0 + per);
+        int nw = 0;
+        for (int kq = q0; kq < q1; ++kq) nw += cand[(size_t)kq * (kCand + 1)] == 0;
+        const int room = min(S - s_held, s_nfree);   // read before the scan's barriers (tid 0 updates s_held)
+        int tot;
+        int r = block_scan(nw, s_tmp, &tot);
+        for (int kq = q0; kq < q1; ++kq) {
+            const int32_t* cl = cand + (size_t)kq * (kCand + 1);
+            if (cl[0] > 0) {
+                dec[kq] = cl[1];
+            } else {
+                dec[kq] = r < room ? -1 - r : INT32_MIN;
+                ++r;
+            }
+        }
+        if (tid == 0) {
+            const int made = min(tot, max(room, 0));
+            s_nnew = made;
+            s_drop = tot - made;
+            s_held = s_held + made;
+        }
+    } else if (tid == 0) {
         int held = s_held, nnew = 0, drop = 0;
         for (int kq = 0; kq < K; ++kq) {
             const int32_t* cl = cand + (size_t)kq * (kCand + 1);
@@ -486,32 +561,26 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
             const int s0 = base + tid * 8;
             int st[8], nw[8];
             int64_t tl[8], te8[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const bool in = s0 + i < S;
-                st[i] = in ? a.src_state[s0 + i] : -1;
-                nw[i] = in ? a.src_new[s0 + i] : 0;
-                tl[i] = in ? a.src_tlast[s0 + i] : 0;
-                te8[i] = in ? a.src_tend[s0 + i] : 0;
-            }
+            load8(a.src_state, s0, S, -1, st);
+            load8(a.src_new, s0, S, 0, nw);
+            load8(a.src_tlast, s0, S, (int64_t)0, tl);
+            load8(a.src_tend, s0, S, (int64_t)0, te8);
             int nm = 0, nn = 0, ne = 0;
+            uint32_t now_end = 0u;   // bit i: monitoring ends at this step
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                const int sl = s0 + i;
                 if (st[i] == kSrcLive) {
                     ++nm;
                     nn += nw[i] != 0;
                     if (t - tl[i] == a.n_mon) {
                         st[i] = kSrcEnded;
                         te8[i] = t;
-                        a.src_state[sl] = kSrcEnded;
-                        a.src_tend[sl] = t;
+                        now_end |= 1u << i;
                     }
                 }
                 ne += st[i] == kSrcEnded;
-                if (nw[i])
-                    for (int r = 0; r < kRing; ++r) a.ring_t[(size_t)sl * kRing + r] = INT64_MIN;
             }
+            // scans first: their barriers then wait on no outstanding stores
             int tm, tn, te;
             int om = base_m + block_scan(nm, s_tmp, &tm);
             int on = base_n + block_scan(nn, s_tmp, &tn);
@@ -520,6 +589,14 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
             for (int i = 0; i < 8; ++i) {
                 const int sl = s0 + i;
                 if (st[i] < 0) continue;
+                if ((now_end >> i) & 1u) {
+                    a.src_state[sl] = kSrcEnded;
+                    a.src_tend[sl] = t;
+                }
+                if (nw[i]) {
+                    longlong2* rt = reinterpret_cast<longlong2*>(a.ring_t + (size_t)sl * kRing);
+                    for (int r = 0; r < kRing / 2; ++r) rt[r] = make_longlong2(INT64_MIN, INT64_MIN);
+                }
                 const bool measured = st[i] == kSrcLive || (st[i] == kSrcEnded && te8[i] == t);
                 if (measured) a.list_measured[om++] = sl;
                 if (nw[i] || st[i] == kSrcEnded) {

@@ -236,6 +236,32 @@ def test_gap_in_time_and_backfill():
     assert res["exact_steps"] == len(ts) and res["events"] >= 2
 
 
+def test_association_conflicts_and_duplicates():
+    """Catalogue cases that take the sequential resolutions: two kept peaks
+    (farther apart than dup_radius) both within assoc_radius of one live
+    source, a duplicate pair across bands, and a peak with two sources in
+    reach; events and lists must match the oracle at every step."""
+    _torch_cuda()
+    rng = np.random.default_rng(21)
+    B, H, W = 2, 96, 96
+    ctx, orc = make_pair(B, H, W, kappa=6.0, bg_sigma=3.0, backfill_steps=4, monitor_steps=3)
+    frames, ts = [], list(range(6))
+    for t in ts:
+        cube = rng.standard_normal((B, H, W)).astype(np.float32)
+        if t == 0:
+            cube[0, 50, 50] += 30.0            # source A
+            cube[1, 20, 20] += 30.0            # source B
+            cube[0, 20, 25] += 28.0            # source C (5 px from B)
+        if t == 1:
+            cube[0, 50, 47] += 35.0            # both 3 px from A, 6 px apart:
+            cube[1, 50, 53] += 32.0            #   the brighter takes A, the other opens
+            cube[0, 20, 22] += 33.0            # within reach of B (2 px) and C (3 px)
+            cube[1, 21, 22] += 31.0            # duplicate of the previous one (1.4 px)
+        frames.append(cube)
+    res = run_steps(ctx, orc, frames, ts, label="conflicts")
+    assert res["exact_steps"] == len(ts) and res["events"] >= 5
+
+
 def test_network_fp32_parity_ragged_batch():
     """infer_windows on 37 seeded windows (a ragged multiple of 32) against the
     FP64 oracle network, per output within 1e-5 of the condition scale."""
