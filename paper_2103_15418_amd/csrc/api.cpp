@@ -99,7 +99,7 @@ Derived derive(const lpf_config* c) {
     d.masked = c->sky_mask != nullptr;
     d.dyn = c->clip_iters > 1 || c->debug_planes != 0;
     d.mwords = (c->W + 31) / 32;
-    d.strip = c->filter_precision == LPF_PREC_FP32 && c->W % 4 == 0 && (d.k == 15 || d.k == 24 || d.k == 36);
+    d.strip = c->W % 4 == 0 && (d.k == 15 || d.k == 24 || d.k == 36);
     size_t nb = (d.HW + 8191) / 8192;  // ~8K pixels per ingest block
     if (nb < 1) nb = 1;
     d.nblk = (int)nb;

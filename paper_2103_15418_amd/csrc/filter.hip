@@ -938,6 +938,171 @@ __global__ __launch_bounds__(kStripThreads) void k_filter_strip(FiltArgs a, Taps
     }
 }
 
+// 16-bit precision form of the strip kernels (bf16 / fp16 operands, float32
+// accumulation): the same walk, stage and column-major ring, with 16-bit
+// elements and v_mfma_f32_16x16x32 (each lane supplies eight consecutive k,
+// one 16-byte LDS read).  Row results are rounded to 16 bits in the ring, as
+// in the tile kernel of this form; the epilogue is the float32 one.  fp16
+// squared residuals are scaled by 2^-8 on the way in and back after the sum.
+template <int K>
+struct Strip16Geo {
+    static constexpr int SHIFT = (4 - K % 4) % 4;
+    static constexpr int KS = (16 + 2 * K + SHIFT + 31) / 32;   // row pass: 32-wide k steps
+    static constexpr int KC = (16 + 2 * K + 31) / 32;           // column pass: 32-wide k steps
+    static constexpr int LW = 48 + 32 * KS;                     // staged columns
+    static constexpr int SW = LW + 8;                           // stage row stride (elements)
+    static constexpr int NB = (16 + 32 * KC + 31) / 32;         // ring depth (32-row batches)
+    static constexpr int RING = NB * 32;
+    static constexpr int RT = RING + 8;                         // ring column stride (elements)
+    static constexpr int NF = 32 * LW / 4;                      // float4 loads per batch
+    static constexpr int NL = (NF + 255) / 256;
+};
+
+template <typename T, int K, int IN, int OUT>
+__global__ __launch_bounds__(kStripThreads) void k_filter_strip16(FiltArgs a, Taps tp) {
+    typedef Strip16Geo<K> G;
+    typedef typename V8<T>::type vec;
+    constexpr bool SCALE = !__is_same(T, __bf16) && IN == IN_E;
+    __shared__ __attribute__((aligned(16))) T stage[32 * G::SW];
+    __shared__ __attribute__((aligned(16))) T ring[kTileW * G::RT];
+    const int strips_y = (a.H + a.strip_h - 1) / a.strip_h;
+    const int per_band = a.tiles_x * strips_y;
+    const int lin = xcd_remap(blockIdx.x, gridDim.x);
+    const int b = lin / per_band;
+    const int rem = lin % per_band;
+    if (a.rej && ((*a.rej >> b) & 1u)) return;
+    const int sy = rem / a.tiles_x, tx = rem % a.tiles_x;
+    const int x0 = tx * kTileW;
+    const int ys = sy * a.strip_h;
+    const int ye = ys + a.strip_h < a.H ? ys + a.strip_h : a.H;
+    const size_t bo = (size_t)b * a.H * a.W;
+    const int tid = threadIdx.x;
+    const int wv = tid >> 6, lane = tid & 63, li = lane & 15, lq = lane >> 4;
+    const float* src = IN == IN_E ? a.E : a.X;
+
+    float4 pf[G::NL];
+    uint32_t pm[G::NL];
+    auto prefetch = [&](int bi) {
+        const int gy0 = ys - K + 32 * bi;
+#pragma unroll
+        for (int i = 0; i < G::NL; ++i) {
+            const int f = tid + kStripThreads * i;
+            pf[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            pm[i] = 0u;
+            if (f < G::NF) {
+                const int row = f / (G::LW / 4), c4 = f % (G::LW / 4);
+                const int gy = gy0 + row, gx = x0 - K - G::SHIFT + 4 * c4;
+                if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
+                    pf[i] = *reinterpret_cast<const float4*>(src + bo + (size_t)gy * a.W + gx);
+                    if (IN == IN_MX) pm[i] = a.mbits ? a.mbits[(size_t)gy * a.mwords + (gx >> 5)] : 0xffffffffu;
+                }
+            }
+        }
+    };
+    auto stage_write = [&]() {
+#pragma unroll
+        for (int i = 0; i < G::NL; ++i) {
+            const int f = tid + kStripThreads * i;
+            if (f < G::NF) {
+                const int row = f / (G::LW / 4), c4 = f % (G::LW / 4);
+                float4 v = pf[i];
+                if (IN == IN_MX) {
+                    const int gx = x0 - K - G::SHIFT + 4 * c4;
+                    const uint32_t bits = pm[i] >> (gx & 31);
+                    v.x = (float)(bits & 1u) * v.x;
+                    v.y = (float)((bits >> 1) & 1u) * v.y;
+                    v.z = (float)((bits >> 2) & 1u) * v.z;
+                    v.w = (float)((bits >> 3) & 1u) * v.w;
+                }
+                const float sc = SCALE ? 1.0f / 256.0f : 1.0f;
+                T* d = stage + row * G::SW + 4 * c4;
+                d[0] = (T)(v.x * sc);
+                d[1] = (T)(v.y * sc);
+                d[2] = (T)(v.z * sc);
+                d[3] = (T)(v.w * sc);
+            }
+        }
+    };
+
+    // taps: B operand of the row pass, A operand of the column pass (8 k per lane and step)
+    vec tap[G::KS], tapc[G::KC];
+#pragma unroll
+    for (int st = 0; st < G::KS; ++st)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int u = 32 * st + 8 * lq + e - G::SHIFT - li;
+            tap[st][e] = (T)((u >= 0 && u <= 2 * K) ? tp.g[u] : 0.0f);
+        }
+#pragma unroll
+    for (int st = 0; st < G::KC; ++st)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int u = 32 * st + 8 * lq + e - li;
+            tapc[st][e] = (T)((u >= 0 && u <= 2 * K) ? tp.g[u] : 0.0f);
+        }
+
+    auto row_pass = [&](int bi) {
+        const int slot = bi % G::NB;
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            const T* sp = stage + (rb * 16 + li) * G::SW + wv * 16 + 8 * lq;
+#pragma unroll
+            for (int st = 0; st < G::KS; ++st) {
+                const vec av = *reinterpret_cast<const vec*>(sp + 32 * st);
+                acc = mfma16<T>(av, tap[st], acc);
+            }
+            // acc[v] = row result of batch row rb*16 + 4 lq + v at column 16 wv + li
+            T* dst = ring + (wv * 16 + li) * G::RT + slot * 32 + rb * 16 + 4 * lq;
+            dst[0] = (T)acc[0];
+            dst[1] = (T)acc[1];
+            dst[2] = (T)acc[2];
+            dst[3] = (T)acc[3];
+        }
+    };
+
+    auto col_pass = [&](int j) {
+        const int gx = x0 + wv * 16 + li;
+        floatx4 acc[2];
+#pragma unroll
+        for (int ob = 0; ob < 2; ++ob) {
+            acc[ob] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            const T* cp = ring + (wv * 16 + li) * G::RT;
+#pragma unroll
+            for (int st = 0; st < G::KC; ++st) {
+                const int rr = (32 * j + ob * 16 + 32 * st + 8 * lq) % G::RING;
+                const vec bv = *reinterpret_cast<const vec*>(cp + rr);
+                acc[ob] = mfma16<T>(tapc[st], bv, acc[ob]);
+            }
+        }
+        if (gx >= a.W) return;
+#pragma unroll
+        for (int ob = 0; ob < 2; ++ob) {
+            const int gy0 = ys + 32 * j + 16 * ob + 4 * lq;
+            const int nv = ye - gy0 < 4 ? (ye - gy0 > 0 ? ye - gy0 : 0) : 4;
+            if (nv <= 0) continue;
+            float v4[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) v4[v] = SCALE ? acc[ob][v] * 256.0f : acc[ob][v];
+            if (OUT == OUT_S_PEAKS) strip_spread_epilogue(a, b, bo, gy0, gx, v4, nv);
+            else epilogue_col<OUT, 4>(a, b, bo, gy0, gx, v4, nv);
+        }
+    };
+
+    const int nch = (ye - ys + 31) / 32;
+    const int nbat = nch + G::NB - 1;
+    prefetch(0);
+    for (int bi = 0; bi < nbat; ++bi) {
+        stage_write();
+        __syncthreads();
+        if (bi + 1 < nbat) prefetch(bi + 1);
+        row_pass(bi);
+        __syncthreads();
+        const int j = bi - (G::NB - 1);
+        if (j >= 0) col_pass(j);
+    }
+}
+
 // Peaks after several clip iterations: P = Q and Y from the planes.
 __global__ __launch_bounds__(256) void k_peaks_planes(FiltArgs a) {
     const int b = blockIdx.y;
@@ -1039,8 +1204,30 @@ hipError_t run_strip(lpf_ctx* c, FiltArgs a, int nbands) {
     return hipGetLastError();
 }
 
+template <typename T, int K, int IN, int OUT>
+hipError_t run_strip16(lpf_ctx* c, FiltArgs a, int nbands) {
+    a.tiles_x = (a.W + kTileW - 1) / kTileW;
+    a.strip_h = strip_height(a.H, a.tiles_x, nbands, OUT == OUT_C_E ? 1024 : 2048);
+    const int nblocks = a.tiles_x * ((a.H + a.strip_h - 1) / a.strip_h) * nbands;
+    hipLaunchKernelGGL((k_filter_strip16<T, K, IN, OUT>), dim3(nblocks), dim3(kStripThreads), 0, c->stream, a,
+                       c->taps);
+    return hipGetLastError();
+}
+
+template <typename T, int IN, int OUT>
+hipError_t dispatch_strip16(lpf_ctx* c, const FiltArgs& a, int nbands) {
+    switch (c->d.k) {
+        case 15: return run_strip16<T, 15, IN, OUT>(c, a, nbands);
+        case 24: return run_strip16<T, 24, IN, OUT>(c, a, nbands);
+        case 36: return run_strip16<T, 36, IN, OUT>(c, a, nbands);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int IN, int OUT>
 hipError_t dispatch_strip(lpf_ctx* c, const FiltArgs& a, int nbands) {
+    if (c->cfg.filter_precision == LPF_PREC_BF16) return dispatch_strip16<__bf16, IN, OUT>(c, a, nbands);
+    if (c->cfg.filter_precision == LPF_PREC_FP16) return dispatch_strip16<_Float16, IN, OUT>(c, a, nbands);
     switch (c->d.k) {
         case 15: return run_strip<15, IN, OUT>(c, a, nbands);
         case 24: return run_strip<24, IN, OUT>(c, a, nbands);

@@ -130,7 +130,7 @@ struct Derived {
     int mwords;    // 32-bit words per packed mask row
     bool masked;
     bool dyn;      // iterations > 1 or debug planes: materialise S / Y
-    bool strip;    // float32 strip kernels (W % 4 == 0, k in {15, 24, 36}): residual plane E
+    bool strip;    // strip kernels (W % 4 == 0, k in {15, 24, 36}): residual plane E
 };
 
 }  // namespace lpf
