@@ -469,6 +469,15 @@ size_t work_bytes(int precision, int maxb) {
 // Grid sizes for n_cap windows; with the count on the device the grids loop.
 inline int grid_cap(int64_t want, int cap) { return (int)(want < 1 ? 1 : (want > cap ? cap : want)); }
 
+// Grid caps: with the count held on the device most of an n_cap-sized grid
+// would exit at once (and hold LDS while being dispatched), so those launches
+// use about two workgroups per CU and loop.
+struct GridCaps {
+    int conv1, conv, fc1_rows, small;
+    explicit GridCaps(const int* n_dev)
+        : conv1(n_dev ? 1024 : 4096), conv(n_dev ? 512 : 2048), fc1_rows(n_dev ? 2 : 4), small(n_dev ? 128 : 1024) {}
+};
+
 template <typename T>
 hipError_t forward16(const lpf_model* m, const float* windows, const int* n_dev, int n_cap, hipStream_t s) {
     const ModelLayout& lay = m->lay;
@@ -477,15 +486,16 @@ hipError_t forward16(const lpf_model* m, const float* windows, const int* n_dev,
     const T* w16 = static_cast<const T*>(w.w16);
     T* a = static_cast<T*>(w.act16_a);
     T* b = static_cast<T*>(w.act16_b);
-    hipLaunchKernelGGL((k_conv1_16<T>), dim3(grid_cap(((int64_t)n_cap * kGH * kGW * 32 + 255) / 256, 4096)),
+    const GridCaps gc(n_dev);
+    hipLaunchKernelGGL((k_conv1_16<T>), dim3(grid_cap(((int64_t)n_cap * kGH * kGW * 32 + 255) / 256, gc.conv1)),
                        dim3(256), 0, s, windows, W + lay.w1, W + lay.b1, a, n_dev, n_cap, m->alpha);
-    hipLaunchKernelGGL((k_conv16<T, 32, 32>), dim3(grid_cap((int64_t)n_cap * (kGH / 2), 2048)), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_conv16<T, 32, 32>), dim3(grid_cap((int64_t)n_cap * (kGH / 2), gc.conv)), dim3(256), 0, s,
                        a, w16 + kW16o2, W + lay.b2, b, n_dev, n_cap, m->alpha);
-    hipLaunchKernelGGL((k_conv16<T, 32, 64>), dim3(grid_cap((int64_t)n_cap * kGH, 2048)), dim3(256), 0, s, b,
+    hipLaunchKernelGGL((k_conv16<T, 32, 64>), dim3(grid_cap((int64_t)n_cap * kGH, gc.conv)), dim3(256), 0, s, b,
                        w16 + kW16o3, W + lay.b3, a, n_dev, n_cap, m->alpha);
-    hipLaunchKernelGGL((k_conv16<T, 64, 64>), dim3(grid_cap((int64_t)n_cap * kGH, 2048)), dim3(256), 0, s, a,
+    hipLaunchKernelGGL((k_conv16<T, 64, 64>), dim3(grid_cap((int64_t)n_cap * kGH, gc.conv)), dim3(256), 0, s, a,
                        w16 + kW16o4, W + lay.b4, b, n_dev, n_cap, m->alpha);
-    hipLaunchKernelGGL((k_fc1_16<T>), dim3(kNSplit, grid_cap((n_cap + 31) / 32, 4)), dim3(256), 0, s, b,
+    hipLaunchKernelGGL((k_fc1_16<T>), dim3(kNSplit, grid_cap((n_cap + 31) / 32, gc.fc1_rows)), dim3(256), 0, s, b,
                        w16 + kW16of1, w.part, n_dev, n_cap, pad32(m->max_batch));
     return hipGetLastError();
 }
@@ -499,28 +509,29 @@ hipError_t cnn_forward(const lpf_model* m, const float* windows, const int* n_de
     const float* W = m->wts;
     const CnnWork& w = m->work;
     const int ldp = pad32(m->max_batch);
+    const GridCaps gc(n_dev);
     hipError_t e = hipSuccess;
     if (m->precision == LPF_PREC_BF16) {
         e = forward16<__bf16>(m, windows, n_dev, n_cap, s);
     } else if (m->precision == LPF_PREC_FP16) {
         e = forward16<_Float16>(m, windows, n_dev, n_cap, s);
     } else {
-        hipLaunchKernelGGL(k_conv1, dim3(grid_cap(((int64_t)n_cap * kGH * kGW * 32 + 255) / 256, 4096)),
+        hipLaunchKernelGGL(k_conv1, dim3(grid_cap(((int64_t)n_cap * kGH * kGW * 32 + 255) / 256, gc.conv1)),
                            dim3(256), 0, s, windows, W + lay.w1, W + lay.b1, w.act_a, n_dev, n_cap, m->alpha);
-        hipLaunchKernelGGL((k_conv_mfma<32, 32>), dim3(grid_cap((int64_t)n_cap * (kGH / 2), 2048)), dim3(256),
+        hipLaunchKernelGGL((k_conv_mfma<32, 32>), dim3(grid_cap((int64_t)n_cap * (kGH / 2), gc.conv)), dim3(256),
                            0, s, w.act_a, W + lay.w2, W + lay.b2, w.act_b, n_dev, n_cap, m->alpha);
-        hipLaunchKernelGGL((k_conv_mfma<32, 64>), dim3(grid_cap((int64_t)n_cap * kGH, 2048)), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_conv_mfma<32, 64>), dim3(grid_cap((int64_t)n_cap * kGH, gc.conv)), dim3(256), 0, s,
                            w.act_b, W + lay.w3, W + lay.b3, w.act_a, n_dev, n_cap, m->alpha);
-        hipLaunchKernelGGL((k_conv_mfma<64, 64>), dim3(grid_cap((int64_t)n_cap * kGH, 2048)), dim3(256), 0, s,
+        hipLaunchKernelGGL((k_conv_mfma<64, 64>), dim3(grid_cap((int64_t)n_cap * kGH, gc.conv)), dim3(256), 0, s,
                            w.act_a, W + lay.w4, W + lay.b4, w.act_b, n_dev, n_cap, m->alpha);
-        hipLaunchKernelGGL(k_fc1_mfma, dim3(kNSplit, grid_cap((n_cap + 31) / 32, 4)), dim3(256), 0, s, w.act_b,
+        hipLaunchKernelGGL(k_fc1_mfma, dim3(kNSplit, grid_cap((n_cap + 31) / 32, gc.fc1_rows)), dim3(256), 0, s, w.act_b,
                            W + lay.f1, w.part, n_dev, n_cap, ldp);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fc1_reduce, dim3(grid_cap(((int64_t)n_cap * kHidden + 255) / 256, 1024)), dim3(256), 0,
+    hipLaunchKernelGGL(k_fc1_reduce, dim3(grid_cap(((int64_t)n_cap * kHidden + 255) / 256, gc.small)), dim3(256), 0,
                        s, w.part, W + lay.fb1, w.hidden, n_dev, n_cap, ldp, m->alpha);
-    hipLaunchKernelGGL(k_fc2_head, dim3(grid_cap(((int64_t)n_cap * kOut + 255) / 256, 1024)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_fc2_head, dim3(grid_cap(((int64_t)n_cap * kOut + 255) / 256, gc.small)), dim3(256), 0, s,
                        w.hidden, W + lay.f2, W + lay.fb2, mu, L, n_dev, n_cap);
     return hipGetLastError();
 }

@@ -176,7 +176,7 @@ __device__ inline void corr16_col(const float* src, int stride, const Taps& tp, 
 // Local-maximum test (Sec. 2.1.2) with a compile-time half-width: the loads
 // of one window row (from clamped, always valid addresses) are issued before
 // its comparisons, so a lane pays one memory latency per row rather than per
-// pixel, with few registers held (the test runs inside the filter epilogue).
+// pixel, with few registers held (the test runs inside filter epilogues).
 template <int KP>
 __device__ inline bool is_peak_k(const FiltArgs& a, size_t bo, int y, int x, float xv) {
     constexpr int N = 2 * KP + 1;
@@ -198,6 +198,32 @@ __device__ inline bool is_peak_k(const FiltArgs& a, size_t bo, int y, int x, flo
 #pragma unroll
         for (int dx = 0; dx < N; ++dx) peak = peak && !(in[dx] && v[dx] > xv);
     }
+    return peak;
+}
+
+// The same test with the whole window's loads in flight at once.
+template <int KP>
+__device__ inline bool is_peak_all(const FiltArgs& a, size_t bo, int y, int x, float xv) {
+    constexpr int N = 2 * KP + 1;
+    float v[N * N];
+    bool in[N * N];
+#pragma unroll
+    for (int dy = 0; dy < N; ++dy) {
+        const int yy = y + dy - KP;
+        const bool rok = yy >= 0 && yy < a.H;
+        const int yc = yy < 0 ? 0 : (yy >= a.H ? a.H - 1 : yy);
+#pragma unroll
+        for (int dx = 0; dx < N; ++dx) {
+            const int xx = x + dx - KP;
+            const int xc = xx < 0 ? 0 : (xx >= a.W ? a.W - 1 : xx);
+            const size_t p = (size_t)yc * a.W + xc;
+            v[dy * N + dx] = a.X[bo + p];
+            in[dy * N + dx] = rok && xx >= 0 && xx < a.W && (a.M ? a.M[p] != 0 : true);
+        }
+    }
+    bool peak = true;
+#pragma unroll
+    for (int i = 0; i < N * N; ++i) peak = peak && !(in[i] && v[i] > xv);
     return peak;
 }
 
@@ -758,7 +784,21 @@ __global__ __launch_bounds__(256) void k_peak_cands(FiltArgs a) {
         const int gy = e.x / a.W, gx = e.x % a.W;
         const float s = __int_as_float(e.y);
         const float xv = a.X[bo + e.x], cv = a.C[bo + e.x];
-        record_if_peak(a, b, bo, gy, gx, xv, cv, s);
+        // all window rows in flight at once (registers are plentiful here)
+        const bool pk = a.kp == 3 ? is_peak_all<3>(a, bo, gy, gx, xv) : is_peak(a, bo, gy, gx, xv);
+        if (!pk) continue;
+        const int idx = atomicAdd(&a.peak_cnt[b], 1);
+        if (idx < a.peak_cap) {
+            PeakRec rec;
+            rec.band = b;
+            rec.row = gy;
+            rec.col = gx;
+            rec.x = xv;
+            rec.c = cv;
+            rec.s = s;
+            rec.sig = (xv - cv) / sqrtf(s);
+            a.peak_raw[(size_t)b * a.peak_cap + idx] = rec;
+        }
     }
 }
 

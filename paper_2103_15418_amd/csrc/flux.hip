@@ -24,8 +24,11 @@ struct FluxArgs {
     int Tc, B, H, W, kf, T_bf;
     int64_t t, t_start;
     size_t plane;
-    const int32_t* list;      // measured or new slots
-    const int32_t* count;     // device count
+    const int32_t* list;      // measured slots
+    const int32_t* count;     // their device count
+    const int32_t* list_new;  // slots opened at this step (backward fill)
+    const int32_t* count_new;
+    int flux_blocks;          // blocks [0, flux_blocks) measure, the rest fill backwards
     const int32_t* src_row;
     const int32_t* src_col;
     float* ring;
@@ -47,22 +50,64 @@ __device__ inline float box_max(const float* img, int H, int W, int i, int j, in
     return m;
 }
 
-// Current step: every measured source, every band.
+// Box maximum with the half-width fixed at compile time: every load of the
+// window (clamped addresses, always valid) is issued before the maxima, which
+// are taken over the pixels inside the image in the same row-major order.
+template <int KF>
+__device__ inline float box_max_k(const float* img, int H, int W, int i, int j) {
+    constexpr int N = 2 * KF + 1;
+    float v[N * N];
+    bool ok[N * N];
+#pragma unroll
+    for (int dr = 0; dr < N; ++dr) {
+        const int r = i + dr - KF;
+        const int rc = r < 0 ? 0 : (r >= H ? H - 1 : r);
+#pragma unroll
+        for (int dc = 0; dc < N; ++dc) {
+            const int c = j + dc - KF;
+            const int cc = c < 0 ? 0 : (c >= W ? W - 1 : c);
+            v[dr * N + dc] = img[(size_t)rc * W + cc];
+            ok[dr * N + dc] = r >= 0 && r < H && c >= 0 && c < W;
+        }
+    }
+    float m = -INFINITY;
+#pragma unroll
+    for (int q = 0; q < N * N; ++q)
+        if (ok[q]) m = fmaxf(m, v[q]);
+    return m;
+}
+
+__device__ inline float box_max_any(const float* img, int H, int W, int i, int j, int k) {
+    return k == 2 ? box_max_k<2>(img, H, W, i, j) : box_max(img, H, W, i, j, k);
+}
+
+// Current step: every measured source, every band (blocks [0, flux_blocks)),
+// and the backward fill of the sources opened at this step (the other
+// blocks; their steps precede t by less than the ring length, so the two
+// parts write different ring entries).
+__device__ void flux_part(const FluxArgs& a, int blk, int nblk);
+__device__ void backfill_part(const FluxArgs& a, int blk, int nblk);
+
 __global__ __launch_bounds__(256) void k_flux(FluxArgs a) {
+    if ((int)blockIdx.x < a.flux_blocks) flux_part(a, blockIdx.x, a.flux_blocks);
+    else backfill_part(a, blockIdx.x - a.flux_blocks, gridDim.x - a.flux_blocks);
+}
+
+__device__ void flux_part(const FluxArgs& a, int blk, int nblk) {
     const int n = *a.count;
     const int cs = pmod(a.t, a.Tc);
     const uint32_t rej = a.cache_rej[cs];
     const float* frame = a.cache + (size_t)cs * a.plane;
     const int ri = pmod(a.t, kRing);
     const uint32_t allb = (a.B == 32) ? 0xffffffffu : ((1u << a.B) - 1u);
-    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < (int64_t)n * a.B;
-         w += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t w = (int64_t)blk * blockDim.x + threadIdx.x; w < (int64_t)n * a.B;
+         w += (int64_t)nblk * blockDim.x) {
         const int s = a.list[w / a.B];
         const int b = (int)(w % a.B);
         const float f = ((rej >> b) & 1u)
                             ? 0.0f
-                            : box_max(frame + (size_t)b * a.H * a.W, a.H, a.W, a.src_row[s],
-                                      a.src_col[s], a.kf);
+                            : box_max_any(frame + (size_t)b * a.H * a.W, a.H, a.W, a.src_row[s],
+                                          a.src_col[s], a.kf);
         a.ring[((size_t)s * a.B + b) * kRing + ri] = f;
         if (b == 0) {
             a.ring_t[(size_t)s * kRing + ri] = a.t;
@@ -72,16 +117,20 @@ __global__ __launch_bounds__(256) void k_flux(FluxArgs a) {
 }
 
 // Backward fill of the sources opened at this step.
-__global__ __launch_bounds__(256) void k_backfill(FluxArgs a) {
-    const int n = *a.count;
-    const int64_t per_src = (int64_t)a.T_bf * a.B;
+__device__ void backfill_part(const FluxArgs& a, int blk, int nblk) {
+    // steps older than t - (ring length - 1) can lie in no window ending at or
+    // after t, and would alias step t in the ring: the fill stops there
+    const int T_eff = a.T_bf < kRing - 1 ? a.T_bf : kRing - 1;
+    if (T_eff <= 0) return;
+    const int n = *a.count_new;
+    const int64_t per_src = (int64_t)T_eff * a.B;
     const uint32_t allb = (a.B == 32) ? 0xffffffffu : ((1u << a.B) - 1u);
-    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < (int64_t)n * per_src;
-         w += (int64_t)gridDim.x * blockDim.x) {
-        const int s = a.list[w / per_src];
+    for (int64_t w = (int64_t)blk * blockDim.x + threadIdx.x; w < (int64_t)n * per_src;
+         w += (int64_t)nblk * blockDim.x) {
+        const int s = a.list_new[w / per_src];
         const int rem = (int)(w % per_src);
         const int d = rem / a.B, b = rem % a.B;
-        const int64_t tau = a.t - a.T_bf + d;
+        const int64_t tau = a.t - T_eff + d;
         if (tau < a.t_start) continue;
         const int cs = pmod(tau, a.Tc);
         if (a.cache_t[cs] != tau) continue;  // step never ingested (gap)
@@ -89,8 +138,8 @@ __global__ __launch_bounds__(256) void k_backfill(FluxArgs a) {
         const float* frame = a.cache + (size_t)cs * a.plane;
         const float f = ((rej >> b) & 1u)
                             ? 0.0f
-                            : box_max(frame + (size_t)b * a.H * a.W, a.H, a.W, a.src_row[s],
-                                      a.src_col[s], a.kf);
+                            : box_max_any(frame + (size_t)b * a.H * a.W, a.H, a.W, a.src_row[s],
+                                          a.src_col[s], a.kf);
         const int ri = pmod(tau, kRing);
         a.ring[((size_t)s * a.B + b) * kRing + ri] = f;
         if (b == 0) {
@@ -261,16 +310,11 @@ hipError_t launch_flux(lpf_ctx* c, int slot, int64_t t) {
     a.ring_v = c->buf.ring_v;
     a.list = c->buf.list_measured;
     a.count = &c->buf.status->n_measured;
-    hipLaunchKernelGGL(k_flux, dim3(128), dim3(256), 0, c->stream, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (a.T_bf > 0) {
-        a.list = c->buf.list_new;
-        a.count = &c->buf.status->n_new;
-        hipLaunchKernelGGL(k_backfill, dim3(256), dim3(256), 0, c->stream, a);
-        e = hipGetLastError();
-    }
-    return e;
+    a.list_new = c->buf.list_new;
+    a.count_new = &c->buf.status->n_new;
+    a.flux_blocks = 128;
+    hipLaunchKernelGGL(k_flux, dim3(a.T_bf > 0 ? 384 : 128), dim3(256), 0, c->stream, a);
+    return hipGetLastError();
 }
 
 // Gathers windows for n entries: d_slots[n], d_tend[n] on the device, on stream s.
