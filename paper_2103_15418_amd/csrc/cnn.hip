@@ -147,12 +147,14 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ in,
             for (int kw = 0; kw < 3; ++kw) {
                 const float* arow = s_in + ((rloc + kh) * CIN) * PADW + px0 + m + kw;
                 const float* wrow = w + (size_t)((kh * 3 + kw) * CIN) * COUT + co0 + m;
-#pragma unroll 8
-                for (int c = 0; c < CIN; c += 2) {
-                    const float av = arow[(c + kk) * PADW];
-                    const float bv = wrow[(size_t)(c + kk) * COUT];
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
-                }
+                // all CIN / 2 weight loads of this tap in flight before the products
+                float bvs[CIN / 2];
+#pragma unroll
+                for (int c = 0; c < CIN; c += 2) bvs[c / 2] = wrow[(size_t)(c + kk) * COUT];
+                __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the products
+#pragma unroll
+                for (int c = 0; c < CIN; c += 2)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[(c + kk) * PADW], bvs[c / 2], acc, 0, 0, 0);
             }
         }
         // D[i][j]: j = lane % 32 (output channel), i = 8 (v / 4) + 4 (lane / 32) + v % 4 (pixel)
@@ -190,11 +192,15 @@ __global__ __launch_bounds__(256) void k_fc1_mfma(const float* __restrict__ a, c
         __syncthreads();
         floatx16 acc = {};
         const float* wp = w + (size_t)k0 * kHidden + co0 + m;
-#pragma unroll 8
-        for (int k = 0; k < kSplitK; k += 2) {
-            const float av = s_a[m * LDA + k + kk];
-            const float bv = wp[(size_t)(k + kk) * kHidden];
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+#pragma unroll 1
+        for (int kb = 0; kb < kSplitK; kb += 64) {   // 32 weight loads in flight per group
+            float bvs[32];
+#pragma unroll
+            for (int q = 0; q < 32; ++q) bvs[q] = wp[(size_t)(kb + 2 * q + kk) * kHidden];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < 32; ++q)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(s_a[m * LDA + kb + 2 * q + kk], bvs[q], acc, 0, 0, 0);
         }
         float* dst = part + (size_t)ks * ld_part * kHidden;
 #pragma unroll
@@ -281,6 +287,9 @@ __global__ __launch_bounds__(256) void k_conv16(const T* __restrict__ in, const 
         for (int kh = 0; kh < 3; ++kh) {
             const int r = row + kh - 1;
             const bool rv = r >= 0 && r < kGH;
+            // the kernel row's 3 x CIN / 16 operand pairs are loaded before the products
+            constexpr int NC = CIN / 16;
+            vec avs[3 * NC], bvs[3 * NC];
 #pragma unroll
             for (int kw = 0; kw < 3; ++kw) {
                 const int col = px0 + m + kw - 1;
@@ -288,12 +297,14 @@ __global__ __launch_bounds__(256) void k_conv16(const T* __restrict__ in, const 
                 const T* ap = in + (((size_t)n * kGH + (rv ? r : 0)) * kGW + (valid ? col : 0)) * CIN + kg * 8;
                 const T* bp = w + ((size_t)(kh * 3 + kw) * COUT + co0 + m) * CIN + kg * 8;
 #pragma unroll
-                for (int c0 = 0; c0 < CIN; c0 += 16) {
-                    const vec av = valid ? *reinterpret_cast<const vec*>(ap + c0) : zero;
-                    const vec bv = *reinterpret_cast<const vec*>(bp + c0);
-                    acc = mfma32<T>(av, bv, acc);
+                for (int q = 0; q < NC; ++q) {
+                    avs[kw * NC + q] = valid ? *reinterpret_cast<const vec*>(ap + 16 * q) : zero;
+                    bvs[kw * NC + q] = *reinterpret_cast<const vec*>(bp + 16 * q);
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < 3 * NC; ++q) acc = mfma32<T>(avs[q], bvs[q], acc);
         }
         T* dst = out + ((size_t)n * kGH + row) * kGW * COUT;
         const float bj = bias[co0 + m];
@@ -324,11 +335,17 @@ __global__ __launch_bounds__(256) void k_fc1_16(const T* __restrict__ a, const T
         const T* ap = a + (size_t)(valid ? n : 0) * kFlat + k0 + kg * 8;
         floatx16 acc = {};
         vec zero = {};
-#pragma unroll 8
-        for (int k = 0; k < kSplitK; k += 16) {
-            const vec av = valid ? *reinterpret_cast<const vec*>(ap + k) : zero;
-            const vec bv = *reinterpret_cast<const vec*>(bp + k);
-            acc = mfma32<T>(av, bv, acc);
+#pragma unroll 1
+        for (int k0 = 0; k0 < kSplitK; k0 += 8 * 16) {   // eight operand pairs in flight per group
+            vec avs[8], bvs[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                avs[q] = valid ? *reinterpret_cast<const vec*>(ap + k0 + 16 * q) : zero;
+                bvs[q] = *reinterpret_cast<const vec*>(bp + k0 + 16 * q);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc = mfma32<T>(avs[q], bvs[q], acc);
         }
         float* dst = part + (size_t)ks * ld_part * kHidden;
 #pragma unroll
