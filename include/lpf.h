@@ -254,13 +254,15 @@ enum {
  * Rows of rejected bands in the centre/spread planes are unspecified. */
 int lpf_debug_read(lpf_ctx* ctx, int32_t what, void* host_out, size_t bytes);
 
-/* Stage timing with HIP events recorded on the context's stream around each
- * stage's kernels (diagnostics; adds a few microseconds per step).
+/* Stage timing with HIP events recorded around each selected stage's kernels
+ * on the stream they run on (diagnostics: every event pair costs the stream a
+ * few microseconds, so time only the stages of interest in a timed run).
  * Stages: 0 ingest pass, 1 QC decision, 2 centre filter, 3 spread filter +
  * threshold + peaks (and further clip iterations), 4 association,
- * 5 flux + backfill, 6 network (recorded by lpf_infer on ctxs[0]). */
-enum { LPF_STAGE_COUNT = 7 };
-int lpf_profile_enable(lpf_ctx* ctx, int32_t on);
+ * 5 flux + backfill, 6 network (recorded on the model's stream for ctxs[0]).
+ * stages: bit i selects stage i (LPF_PROFILE_ALL for every stage, 0 = off). */
+enum { LPF_STAGE_COUNT = 7, LPF_PROFILE_ALL = (1 << 7) - 1 };
+int lpf_profile_enable(lpf_ctx* ctx, int32_t stages);
 /* Sums the recorded stage times (ms) and counts since the last read and
  * clears them; synchronises.  ms / counts: host arrays of LPF_STAGE_COUNT. */
 int lpf_profile_read(lpf_ctx* ctx, double* ms, int64_t* counts);

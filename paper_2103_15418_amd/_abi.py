@@ -264,8 +264,13 @@ class Context:
 
     STAGES = ("ingest", "qc_decide", "centre", "spread_peaks", "catalog", "flux", "network")
 
-    def profile(self, on: bool = True):
-        self._check(lib().lpf_profile_enable(self.h, 1 if on else 0), "profile_enable")
+    def profile(self, on: bool = True, stages: Optional[Sequence[str]] = None):
+        """Time every stage (on=True), the named stages only, or none (on=False)."""
+        mask = 0
+        if on:
+            mask = (1 << len(self.STAGES)) - 1 if stages is None else \
+                sum(1 << self.STAGES.index(k) for k in stages)
+        self._check(lib().lpf_profile_enable(self.h, mask), "profile_enable")
 
     def profile_read(self):
         """{stage: (total ms, launches)} since the last read."""

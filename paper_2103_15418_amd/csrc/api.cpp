@@ -505,13 +505,14 @@ int lpf_debug_read(lpf_ctx* c, int32_t what, void* host, size_t bytes) {
     return LPF_OK;
 }
 
-int lpf_profile_enable(lpf_ctx* c, int32_t on) {
+int lpf_profile_enable(lpf_ctx* c, int32_t stages) {
     LPF_CHECK_CTX(c);
-    if (on && c->prof_pool.empty()) {
+    if (stages < 0 || stages > LPF_PROFILE_ALL) return fail(c, LPF_EINVAL, "stage mask");
+    if (stages && c->prof_pool.empty()) {
         c->prof_pool.resize(1 << 14);
         for (auto& e : c->prof_pool) LPF_HIP(c, hipEventCreate(&e), "event create");
     }
-    c->prof_on = on != 0;
+    c->prof_mask = (uint32_t)stages;
     return LPF_OK;
 }
 

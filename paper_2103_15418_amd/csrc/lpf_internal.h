@@ -149,7 +149,7 @@ struct lpf_ctx {
     bool poisoned;
     std::string err;
     // stage timing (lpf_profile_enable)
-    bool prof_on = false;
+    uint32_t prof_mask = 0;   // stages timed (bit i = stage i)
     std::vector<hipEvent_t> prof_pool;
     size_t prof_next = 0;
     struct ProfRec { int stage; hipEvent_t a, b; };
@@ -221,7 +221,7 @@ struct StageTimer {
     hipStream_t s;
     hipEvent_t b = nullptr;
     StageTimer(lpf_ctx* ctx, int st, hipStream_t on = nullptr) : c(ctx), stage(st), s(on ? on : ctx->stream) {
-        if (!c->prof_on || c->prof_next + 2 > c->prof_pool.size()) return;
+        if (!((c->prof_mask >> stage) & 1u) || c->prof_next + 2 > c->prof_pool.size()) return;
         hipEvent_t a = c->prof_pool[c->prof_next++];
         b = c->prof_pool[c->prof_next++];
         (void)hipEventRecord(a, s);
