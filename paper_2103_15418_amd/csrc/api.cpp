@@ -358,7 +358,7 @@ int lpf_detect(lpf_ctx* c, lpf_peak* peaks, int32_t cap, int32_t* n_peaks, lpf_s
     LPF_CHECK_CTX(c);
     if (c->phase != 1) return fail(c, LPF_ESTATE, "detect needs a fresh ingest");
     const int slot = pmod(c->t_last, c->d.Tc);
-    LPF_HIP(c, launch_detect_init(c), "detect init");
+    // (the per-step detection counters were cleared by the QC kernel of this ingest)
     LPF_HIP(c, launch_filters(c, slot), "filters");
     {
         StageTimer tm(c, 4);

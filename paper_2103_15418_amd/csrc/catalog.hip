@@ -1,6 +1,8 @@
 // Source association and monitoring (Sec. 2.2), one workgroup per step.
 //
 // Input: the per-band peak lists written by the detection pass.  Steps:
+// -1. (strip filters) the local-maximum test of the above-threshold pixels
+//     the filter listed, appending peaks to the band lists;
 //  0. release records reported as ended at the previous step; end episodes
 //     a gap in t carried past their last measured step;
 //  1. order all peaks by (band, row, col) -> the step's peak list;
@@ -31,7 +33,14 @@ struct CatArgs {
     float r_dup2, r_assoc2;
     int64_t t;
     const int32_t* peak_cnt;
-    const PeakRec* peak_raw;
+    PeakRec* peak_raw;
+    // deferred local-maximum test (strip filters): above-threshold pixels per band
+    const int2* pk_cand;         // [B][H*W] (pixel index, S bits), null if peaks are already listed
+    const int32_t* pk_cand_cnt;  // [B]
+    const float* X;           // this step's cube [B][H][W]
+    const float* C;           // centre plane [B][H][W]
+    const uint8_t* M;         // sky mask [H][W] or null
+    int H, W, kp;
     PeakRec* peak_sorted;
     int32_t* order;     // [kCatMaxPeaks] bij-rank by visiting position
     int32_t* nbr;       // [kCatMaxPeaks][kNbr + 1]
@@ -183,6 +192,7 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
     __shared__ uint64_t s_wkey[(kCatThreads / 64) * kCand];  // per-wave candidate keys
     __shared__ int32_t s_wslot[(kCatThreads / 64) * kCand];
     __shared__ int s_off[kMaxB + 1];
+    __shared__ int s_cnt[kMaxB];
     __shared__ int s_tmp[kCatThreads / 64 + 1];
     __shared__ int s_P, s_K, s_nlive, s_held, s_nfree, s_nnew, s_drop, s_next;
     __shared__ uint32_t s_overflow;
@@ -190,6 +200,91 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
     const int tid = threadIdx.x;
     const int S = a.max_sources;
     const int64_t t = a.t;
+
+    // per-band peak counts, read in parallel (one dependent read per band
+    // would serialise as many memory latencies)
+    if (tid < a.B) {
+        s_cnt[tid] = a.peak_cnt[tid];
+        if (a.pk_cand) s_off[tid + 1] = a.pk_cand_cnt[tid];
+    }
+    __syncthreads();
+
+    // ---- -1. deferred local-maximum test (Sec. 2.1.2) of the above-threshold
+    // pixels the strip filters listed; peaks are appended to the band lists
+    // (counts in LDS).  For the 7 x 7 window eight lanes share a pixel, one
+    // window row each, so a wave tests eight pixels with seven loads a lane.
+    if (a.pk_cand) {
+        if (tid == 0) {
+            s_off[0] = 0;
+            for (int b = 1; b <= a.B; ++b) s_off[b] += s_off[b - 1];
+        }
+        __syncthreads();
+        const int ncand = s_off[a.B];
+        const size_t HW = (size_t)a.H * a.W;
+        auto append = [&](int b, int gy, int gx, float xv, float cv, float sv) {
+            const int idx = atomicAdd(&s_cnt[b], 1);
+            if (idx >= a.peak_cap) return;
+            PeakRec rec;
+            rec.band = b;
+            rec.row = gy;
+            rec.col = gx;
+            rec.x = xv;
+            rec.c = cv;
+            rec.s = sv;
+            rec.sig = (xv - cv) / sqrtf(sv);
+            a.peak_raw[(size_t)b * a.peak_cap + idx] = rec;
+        };
+        if (a.kp == 3) {
+            const int g = tid >> 3, r = tid & 7;
+            for (int base = 0; base < ncand; base += kCatThreads / 8) {   // uniform trip count
+                const int n = base + g;
+                const bool valid = n < ncand;
+                bool fail = false;
+                int b = 0, gy = 0, gx = 0;
+                float xv = 0.0f, cv = 0.0f, sv = 1.0f;
+                if (valid) {
+                    while (n >= s_off[b + 1]) ++b;
+                    const int2 e = a.pk_cand[(size_t)b * HW + (n - s_off[b])];
+                    const float* Xb = a.X + (size_t)b * HW;
+                    gy = e.x / a.W;
+                    gx = e.x % a.W;
+                    sv = __int_as_float(e.y);
+                    xv = Xb[e.x];
+                    if (r == 0) cv = a.C[(size_t)b * HW + e.x];
+                    const int yy = gy + r - 3;
+                    if (r < 7 && yy >= 0 && yy < a.H) {
+                        float v[7];
+                        bool in[7];
+#pragma unroll
+                        for (int dx = 0; dx < 7; ++dx) {
+                            const int xx = gx + dx - 3;
+                            const int xc = xx < 0 ? 0 : (xx >= a.W ? a.W - 1 : xx);
+                            const size_t p = (size_t)yy * a.W + xc;
+                            v[dx] = Xb[p];
+                            in[dx] = xx >= 0 && xx < a.W && (a.M ? a.M[p] != 0 : true);
+                        }
+#pragma unroll
+                        for (int dx = 0; dx < 7; ++dx) fail = fail || (in[dx] && v[dx] > xv);
+                    }
+                }
+                const uint64_t bal = __ballot(fail);
+                const bool peak = valid && ((bal >> (tid & 56)) & 0xffull) == 0ull;
+                if (peak && r == 0) append(b, gy, gx, xv, cv, sv);
+            }
+        } else {
+            for (int n = tid; n < ncand; n += kCatThreads) {
+                int b = 0;
+                while (n >= s_off[b + 1]) ++b;
+                const int2 e = a.pk_cand[(size_t)b * HW + (n - s_off[b])];
+                const size_t bo = (size_t)b * HW;
+                const int gy = e.x / a.W, gx = e.x % a.W;
+                const float xv = a.X[bo + e.x];
+                if (window_max(a.X + bo, a.M, a.H, a.W, a.kp, gy, gx, xv))
+                    append(b, gy, gx, xv, a.C[bo + e.x], __int_as_float(e.y));
+            }
+        }
+        __syncthreads();   // the appended records and counts are read below
+    }
 
     // ---- 0. release previous ended records; end episodes left over by a gap
     for (int s0 = tid; s0 < S; s0 += 8 * kCatThreads) {
@@ -224,7 +319,7 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
         int off = 0;
         uint32_t ovf = 0;
         for (int b = 0; b < a.B; ++b) {
-            const int n = a.peak_cnt[b];
+            const int n = s_cnt[b];
             s_off[b] = off;
             if (n > a.peak_cap) ovf |= 1u << b;
             else off += n;
@@ -657,6 +752,11 @@ __global__ void k_table_init(int32_t* src_state, int S, int64_t* cache_t, uint32
 
 }  // namespace
 
+inline int pmod_host(int64_t a, int m) {
+    const int64_t r = a % m;
+    return (int)(r < 0 ? r + m : r);
+}
+
 hipError_t launch_catalog(lpf_ctx* c, int64_t t) {
     CatArgs a;
     a.B = c->cfg.B;
@@ -669,6 +769,16 @@ hipError_t launch_catalog(lpf_ctx* c, int64_t t) {
     a.peak_cnt = c->buf.peak_cnt;
     a.peak_raw = c->buf.peak_raw;
     a.peak_sorted = c->buf.peak_sorted;
+    // the strip filters of one clip iteration leave the peak test to this kernel
+    const bool deferred = c->d.strip && c->cfg.clip_iters == 1;
+    a.pk_cand = deferred ? c->buf.cand : nullptr;
+    a.pk_cand_cnt = c->buf.cand_cnt;
+    a.X = c->buf.cache + (size_t)pmod_host(t, c->d.Tc) * c->d.plane;
+    a.C = c->buf.centre;
+    a.M = c->d.masked ? c->buf.mask : nullptr;
+    a.H = c->cfg.H;
+    a.W = c->cfg.W;
+    a.kp = c->cfg.peak_halfwidth;
     a.order = c->buf.cat_order;
     a.nbr = c->buf.cat_nbr;
     a.cand = c->buf.cat_cand;

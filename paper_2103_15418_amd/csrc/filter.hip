@@ -201,32 +201,6 @@ __device__ inline bool is_peak_k(const FiltArgs& a, size_t bo, int y, int x, flo
     return peak;
 }
 
-// The same test with the whole window's loads in flight at once.
-template <int KP>
-__device__ inline bool is_peak_all(const FiltArgs& a, size_t bo, int y, int x, float xv) {
-    constexpr int N = 2 * KP + 1;
-    float v[N * N];
-    bool in[N * N];
-#pragma unroll
-    for (int dy = 0; dy < N; ++dy) {
-        const int yy = y + dy - KP;
-        const bool rok = yy >= 0 && yy < a.H;
-        const int yc = yy < 0 ? 0 : (yy >= a.H ? a.H - 1 : yy);
-#pragma unroll
-        for (int dx = 0; dx < N; ++dx) {
-            const int xx = x + dx - KP;
-            const int xc = xx < 0 ? 0 : (xx >= a.W ? a.W - 1 : xx);
-            const size_t p = (size_t)yc * a.W + xc;
-            v[dy * N + dx] = a.X[bo + p];
-            in[dy * N + dx] = rok && xx >= 0 && xx < a.W && (a.M ? a.M[p] != 0 : true);
-        }
-    }
-    bool peak = true;
-#pragma unroll
-    for (int i = 0; i < N * N; ++i) peak = peak && !(in[i] && v[i] > xv);
-    return peak;
-}
-
 __device__ inline bool is_peak(const FiltArgs& a, size_t bo, int y, int x, float xv) {
     const int kp = a.kp;
     if (kp == 3) return is_peak_k<3>(a, bo, y, x, xv);   // the paper's 7 x 7 window
@@ -727,8 +701,8 @@ __global__ __launch_bounds__(kThreads2) void k_filter_mfma(FiltArgs a, Taps tp) 
 
 // Spread epilogue of the strip kernels (four vertically consecutive outputs):
 // S, threshold and the optional S / Y planes as everywhere, but the 7 x 7
-// local-maximum test of the (few) above-threshold pixels is deferred to
-// k_peak_cands through a per-band list that can hold every pixel, so the
+// local-maximum test of the (few) above-threshold pixels is deferred to the
+// catalogue kernel through a per-band list that can hold every pixel, so the
 // filter kernel neither waits on the window loads nor holds their registers.
 __device__ inline void strip_spread_epilogue(const FiltArgs& a, int b, size_t bo, int gy0, int gx, const float* v,
                                              int nvalid) {
@@ -771,35 +745,6 @@ __device__ inline void strip_spread_epilogue(const FiltArgs& a, int b, size_t bo
         }
     }
     if (a.changed) a.changed[b] = 1;
-}
-
-// Deferred peak test: one lane per listed above-threshold pixel.
-__global__ __launch_bounds__(256) void k_peak_cands(FiltArgs a) {
-    const int b = blockIdx.y;
-    if (a.rej && ((*a.rej >> b) & 1u)) return;
-    const int n = a.cand_cnt[b];
-    const size_t bo = (size_t)b * a.H * a.W;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const int2 e = a.cand[bo + i];
-        const int gy = e.x / a.W, gx = e.x % a.W;
-        const float s = __int_as_float(e.y);
-        const float xv = a.X[bo + e.x], cv = a.C[bo + e.x];
-        // all window rows in flight at once (registers are plentiful here)
-        const bool pk = a.kp == 3 ? is_peak_all<3>(a, bo, gy, gx, xv) : is_peak(a, bo, gy, gx, xv);
-        if (!pk) continue;
-        const int idx = atomicAdd(&a.peak_cnt[b], 1);
-        if (idx < a.peak_cap) {
-            PeakRec rec;
-            rec.band = b;
-            rec.row = gy;
-            rec.col = gx;
-            rec.x = xv;
-            rec.c = cv;
-            rec.s = s;
-            rec.sig = (xv - cv) / sqrtf(s);
-            a.peak_raw[(size_t)b * a.peak_cap + idx] = rec;
-        }
-    }
 }
 
 // Strip kernel (float32 path; compile-time half-width K; W % 4 == 0).
@@ -1358,13 +1303,6 @@ hipError_t launch_inv_den(lpf_ctx* c) {
     return dispatch_k<IN_M, OUT_INV_DEN>(c, a, 1);
 }
 
-hipError_t launch_detect_init(lpf_ctx* c) {
-    const int nch = (kMaxIters + 1) * c->cfg.B;
-    hipLaunchKernelGGL(k_detect_init, dim3((nch + 255) / 256), dim3(256), 0, c->stream,
-                       c->buf.peak_cnt, c->buf.cand_cnt, c->buf.changed, nch, c->cfg.B);
-    return hipGetLastError();
-}
-
 // Clip planes: clip[j] = buf.clip + j * plane, j = 0, 1.  Iteration 1 writes
 // Y_1 into both; iteration i reads clip[(i-1)&1] and writes clip[i&1] whole.
 // A band that stops changing therefore holds equal planes, so the final
@@ -1390,9 +1328,7 @@ hipError_t launch_filters(lpf_ctx* c, int slot) {
         a.S_out = c->d.dyn ? c->buf.spread : nullptr;
         a.Y_out = c->d.dyn ? clip1 : nullptr;
         if (!c->d.strip) return dispatch_k<IN_ME, OUT_S_PEAKS>(c, a, B);
-        if ((e = dispatch_strip<IN_E, OUT_S_PEAKS>(c, a, B)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_peak_cands, dim3(16, B), dim3(256), 0, c->stream, a);
-        return hipGetLastError();
+        return dispatch_strip<IN_E, OUT_S_PEAKS>(c, a, B);   // peak test of the candidates: k_catalog
     }
     // Several iterations: S and Y planes are materialised and peaks are
     // listed after the last iteration.

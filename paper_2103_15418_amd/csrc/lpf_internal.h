@@ -214,6 +214,52 @@ constexpr int kCand = 8;   // stored association candidates per kept peak
 
 inline int xcd_count() { return 8; }
 
+// Local-maximum test of Sec. 2.1.2 at (y, x) of one band plane X: no pixel
+// of the (2 KP + 1)^2 window inside the image and the sky mask M (null = all)
+// exceeds xv, so ties are peaks.  Every window load is issued (from clamped,
+// always valid addresses) before the comparisons.
+template <int KP>
+__device__ inline bool window_max_all(const float* X, const uint8_t* M, int H, int W, int y, int x, float xv) {
+    constexpr int N = 2 * KP + 1;
+    float v[N * N];
+    bool in[N * N];
+#pragma unroll
+    for (int dy = 0; dy < N; ++dy) {
+        const int yy = y + dy - KP;
+        const bool rok = yy >= 0 && yy < H;
+        const int yc = yy < 0 ? 0 : (yy >= H ? H - 1 : yy);
+#pragma unroll
+        for (int dx = 0; dx < N; ++dx) {
+            const int xx = x + dx - KP;
+            const int xc = xx < 0 ? 0 : (xx >= W ? W - 1 : xx);
+            const size_t p = (size_t)yc * W + xc;
+            v[dy * N + dx] = X[p];
+            in[dy * N + dx] = rok && xx >= 0 && xx < W && (M ? M[p] != 0 : true);
+        }
+    }
+    bool peak = true;
+#pragma unroll
+    for (int i = 0; i < N * N; ++i) peak = peak && !(in[i] && v[i] > xv);
+    return peak;
+}
+
+// The same test for a run-time half-width kp.
+__device__ inline bool window_max(const float* X, const uint8_t* M, int H, int W, int kp, int y, int x, float xv) {
+    if (kp == 3) return window_max_all<3>(X, M, H, W, y, x, xv);
+    for (int dy = -kp; dy <= kp; ++dy) {
+        const int yy = y + dy;
+        if (yy < 0 || yy >= H) continue;
+        for (int dx = -kp; dx <= kp; ++dx) {
+            const int xx = x + dx;
+            if (xx < 0 || xx >= W) continue;
+            const size_t p = (size_t)yy * W + xx;
+            if (M && !M[p]) continue;
+            if (X[p] > xv) return false;
+        }
+    }
+    return true;
+}
+
 // Stage timer: records an event pair around the enclosed launches.
 struct StageTimer {
     lpf_ctx* c;
@@ -235,7 +281,6 @@ struct StageTimer {
 // Launchers (defined in the .hip files); return hipError_t of the launch.
 hipError_t launch_ingest(lpf_ctx* c, const float* src, bool copy, int slot);
 hipError_t launch_qc_decide(lpf_ctx* c, int slot, int64_t t);
-hipError_t launch_detect_init(lpf_ctx* c);
 hipError_t launch_filters(lpf_ctx* c, int slot);
 hipError_t launch_inv_den(lpf_ctx* c);
 hipError_t launch_pack_mask(lpf_ctx* c);
