@@ -221,10 +221,12 @@ int lpf_infer_windows(const lpf_model* model, const float* windows, int32_t n, f
 
 /* Asynchronous form of lpf_infer over the episodes that ended at the last
  * detect of each context (Sec. 2.2 episode end -> Sec. 2.3 inference): the
- * counts stay on the device, the windows are gathered there, the network
- * runs on the model's stream and the results are copied into a pinned host
- * slot; nothing waits.  Each context's later work is ordered after the
- * gather, so the caller may ingest the next frame at once.  *ticket
+ * counts stay on the device, the windows are gathered there (into buffers of
+ * the ticket: on the context's own stream when n_ctx is 1, else on the
+ * model's stream), the network runs on the model's stream and the results
+ * are copied into a pinned host slot; nothing waits.  Each context's later
+ * work is ordered after the gather, so the caller may ingest the next frame
+ * at once.  *ticket
  * identifies the results for lpf_infer_collect.  At most 4 tickets may be
  * outstanding per model (LPF_EFULL otherwise).  Episodes beyond the model's
  * max_batch are not inferred; lpf_infer_collect reports them. */

@@ -17,9 +17,8 @@ hipError_t launch_windows_gather(lpf_ctx* c, int n, const int32_t* d_slots, cons
 hipError_t launch_ended_ends(lpf_ctx* c, int32_t* slots_out, int64_t* tend_out);
 hipError_t cnn_forward(const lpf_model* m, const float* windows, const int* n_dev, int n_cap, float* mu,
                        float* L, hipStream_t s);
-hipError_t launch_gather_begin(int32_t* hdr, hipStream_t s);
 hipError_t launch_gather_ended(lpf_ctx* c, int ci, int32_t* hdr, float* out, int32_t* rows, int cap,
-                               hipStream_t s);
+                               hipStream_t s, bool first);
 float* model_window_buffer(const lpf_model* m);
 float* model_mu_buffer(const lpf_model* m);
 float* model_L_buffer(const lpf_model* m);
@@ -585,25 +584,40 @@ int lpf_infer_async(lpf_ctx* const* ctxs, int32_t n_ctx, lpf_model* m, int64_t* 
     const int slot = (int)(m->next_ticket % kInflight);
     if (m->slot_ticket[slot] >= 0) return fail(c0, LPF_EFULL, "too many inference tickets outstanding");
     hipStream_t s = m->istream;
-    CnnWork& w = m->work;
-    // the contexts' streams hand over (flux and rings of this step are final)
-    for (int i = 0; i < n_ctx; ++i) {
-        lpf_ctx* c = ctxs[i];
-        if (!c->ev_ready) LPF_HIP(c, hipEventCreateWithFlags(&c->ev_ready, hipEventDisableTiming), "event");
-        LPF_HIP(c, hipEventRecord(c->ev_ready, c->stream), "event record");
-        LPF_HIP(c0, hipStreamWaitEvent(s, c->ev_ready, 0), "event wait");
+    const CnnWork& w = m->work;
+    int32_t* hdr = w.sblk[slot];
+    int32_t* rows = hdr + 4;
+    float* mu = reinterpret_cast<float*>(rows + 2 * (size_t)m->max_batch);
+    float* L = mu + 4 * (size_t)m->max_batch;
+    float* win = w.swin[slot];
+    if (n_ctx == 1) {
+        // one context: its stream gathers into this ticket's buffers and goes
+        // on; only the network waits (on the model's stream)
+        lpf_ctx* c = c0;
+        LPF_HIP(c, launch_gather_ended(c, 0, hdr, win, rows, m->max_batch, c->stream, true), "gather");
+        LPF_HIP(c, hipEventRecord(m->ev_gathered, c->stream), "event record");
+        LPF_HIP(c, hipStreamWaitEvent(s, m->ev_gathered, 0), "event wait");
+    } else {
+        // several contexts: their streams hand over to the model's stream
+        // (flux and rings of this step are final), which gathers them in
+        // order; each may go on as soon as its rings have been read
+        for (int i = 0; i < n_ctx; ++i) {
+            lpf_ctx* c = ctxs[i];
+            if (!c->ev_ready) LPF_HIP(c, hipEventCreateWithFlags(&c->ev_ready, hipEventDisableTiming), "event");
+            LPF_HIP(c, hipEventRecord(c->ev_ready, c->stream), "event record");
+            LPF_HIP(c0, hipStreamWaitEvent(s, c->ev_ready, 0), "event wait");
+        }
+        for (int i = 0; i < n_ctx; ++i)
+            LPF_HIP(ctxs[i], launch_gather_ended(ctxs[i], i, hdr, win, rows, m->max_batch, s, i == 0), "gather");
+        LPF_HIP(c0, hipEventRecord(m->ev_gathered, s), "event record");
+        for (int i = 0; i < n_ctx; ++i)
+            LPF_HIP(ctxs[i], hipStreamWaitEvent(ctxs[i]->stream, m->ev_gathered, 0), "event wait");
     }
-    LPF_HIP(c0, launch_gather_begin(w.hdr, s), "gather");
-    for (int i = 0; i < n_ctx; ++i)
-        LPF_HIP(ctxs[i], launch_gather_ended(ctxs[i], i, w.hdr, w.windows, w.rows, m->max_batch, s), "gather");
-    // the contexts may go on as soon as their rings have been read
-    LPF_HIP(c0, hipEventRecord(m->ev_gathered, s), "event record");
-    for (int i = 0; i < n_ctx; ++i) LPF_HIP(ctxs[i], hipStreamWaitEvent(ctxs[i]->stream, m->ev_gathered, 0), "event wait");
     {
         StageTimer tm(c0, 6, s);
-        LPF_HIP(c0, cnn_forward(m, w.windows, w.hdr, m->max_batch, w.mu, w.L, s), "cnn");
+        LPF_HIP(c0, cnn_forward(m, win, hdr, m->max_batch, mu, L, s), "cnn");
     }
-    LPF_HIP(c0, hipMemcpyAsync(m->h_res[slot], w.hdr, w.out_bytes, hipMemcpyDeviceToHost, s), "result D2H");
+    LPF_HIP(c0, hipMemcpyAsync(m->h_res[slot], hdr, w.out_bytes, hipMemcpyDeviceToHost, s), "result D2H");
     LPF_HIP(c0, hipEventRecord(m->ev_done[slot], s), "event record");
     m->slot_ticket[slot] = m->next_ticket;
     *ticket = m->next_ticket++;

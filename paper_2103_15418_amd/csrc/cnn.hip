@@ -476,8 +476,8 @@ size_t work_bytes(int precision, int maxb) {
     if (precision != LPF_PREC_FP32) b += align64(kW16total * 2);
     b += align64((size_t)kNSplit * pad32(maxb) * kHidden * sizeof(float));
     b += align64((size_t)maxb * kHidden * sizeof(float));
-    b += align64((size_t)maxb * kGH * kGW * sizeof(float));
-    b += align64(out_block_bytes(maxb));
+    b += (1 + kInflight) * align64((size_t)maxb * kGH * kGW * sizeof(float));
+    b += (1 + kInflight) * align64(out_block_bytes(maxb));
     return b;
 }
 
@@ -630,6 +630,10 @@ int model_create(const void* weights, size_t bytes, int precision, int maxb, voi
     m->work.L = m->work.mu + 4 * (size_t)maxb;
     m->work.out_bytes = out_block_bytes(maxb);
     p += align64(m->work.out_bytes);
+    for (int i = 0; i < kInflight; ++i) {
+        m->work.swin[i] = reinterpret_cast<float*>(p); p += align64((size_t)maxb * kGH * kGW * sizeof(float));
+        m->work.sblk[i] = reinterpret_cast<int32_t*>(p); p += align64(m->work.out_bytes);
+    }
     float* staging = reinterpret_cast<float*>(p);
     hipError_t e = hipMemcpyAsync(staging, weights, blob_floats() * sizeof(float), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {

@@ -204,16 +204,19 @@ struct GatherArgs {
     const int64_t* ring_t;
     const uint32_t* ring_v;
     int32_t row_band[kGridRows];
-    const int32_t* hdr;
+    int32_t* hdr;
+    int first;                // 1: first context of the batch (base 0; block 0 writes the header)
     float* out;               // [cap][16][64]
     int32_t* rows;            // [cap][2]: (context index, id)
 };
 
 __global__ __launch_bounds__(256) void k_gather_ended(GatherArgs a) {
-    const int base = a.hdr[0];
+    const int base = a.first ? 0 : a.hdr[0];
     const int n_end = *a.n_ended;
     const int room = a.cap - base;
     const int take = n_end < room ? n_end : (room > 0 ? room : 0);
+    if (a.first && blockIdx.x == 0 && threadIdx.x < 4)   // no block reads the header in this case
+        a.hdr[threadIdx.x] = threadIdx.x == 0 ? take : (threadIdx.x == 1 ? n_end : 0);
     const int64_t total = (int64_t)take * kGridRows * kRing;
     for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total;
          w += (int64_t)gridDim.x * blockDim.x) {
@@ -246,21 +249,14 @@ __global__ void k_gather_advance(int32_t* hdr, const int32_t* n_ended, int cap) 
     hdr[1] += n_end;
 }
 
-__global__ void k_gather_begin(int32_t* hdr) {
-    if (threadIdx.x < 4 && blockIdx.x == 0) hdr[threadIdx.x] = 0;
-}
-
 }  // namespace
-
-hipError_t launch_gather_begin(int32_t* hdr, hipStream_t s) {
-    hipLaunchKernelGGL(k_gather_begin, dim3(1), dim3(64), 0, s, hdr);
-    return hipGetLastError();
-}
 
 // Appends context c's ended episodes (as context index ci) to the batch; grid
 // sized for up to min(max_sources, cap) windows, counts read on the device.
+// The first context of a batch starts the header (one launch); later ones
+// read it and advance it in a second launch.
 hipError_t launch_gather_ended(lpf_ctx* c, int ci, int32_t* hdr, float* out, int32_t* rows, int cap,
-                               hipStream_t s) {
+                               hipStream_t s, bool first) {
     GatherArgs a;
     a.B = c->cfg.B;
     a.cap = cap;
@@ -275,6 +271,7 @@ hipError_t launch_gather_ended(lpf_ctx* c, int ci, int32_t* hdr, float* out, int
     for (int r = 0; r < kGridRows; ++r) a.row_band[r] = -1;
     for (int b = 0; b < c->cfg.B; ++b) a.row_band[c->grid_rows[b]] = b;
     a.hdr = hdr;
+    a.first = first ? 1 : 0;
     a.out = out;
     a.rows = rows;
     const int most = c->cfg.max_sources < cap ? c->cfg.max_sources : cap;
@@ -283,7 +280,7 @@ hipError_t launch_gather_ended(lpf_ctx* c, int ci, int32_t* hdr, float* out, int
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_gather_ended, dim3(blocks), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || first) return e;
     hipLaunchKernelGGL(k_gather_advance, dim3(1), dim3(64), 0, s, hdr, &c->buf.status->n_ended, cap);
     return hipGetLastError();
 }

@@ -167,6 +167,8 @@ struct ModelLayout {
     size_t w1, b1, w2, b2, w3, b3, w4, b4, f1, fb1, f2, fb2, total;
 };
 
+constexpr int kInflight = 4;   // asynchronous inference tickets outstanding per model
+
 struct CnnWork {
     float* act_a;     // [maxb][16][64][64] (float32 network)
     float* act_b;
@@ -182,9 +184,12 @@ struct CnnWork {
     float* mu;        // [maxb][4]
     float* L;         // [maxb][10]
     size_t out_bytes; // bytes of the result block
+    // per-ticket gather windows and result blocks (same layout as above) of
+    // the asynchronous calls, so a batch can be gathered while the network
+    // still reads the previous one
+    float* swin[kInflight];
+    int32_t* sblk[kInflight];
 };
-
-constexpr int kInflight = 4;   // asynchronous inference tickets outstanding per model
 
 }  // namespace lpf
 
