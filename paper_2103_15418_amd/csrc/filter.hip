@@ -331,7 +331,7 @@ __device__ inline void epilogue_col(const FiltArgs& a, int b, size_t bo, int gy0
             const float cv = v[q] * id[q];
             const float r = xv[q] - cv;
             a.out[p] = cv;
-            a.E_out[p] = mk[q] * r * r;
+            a.E_out[p] = mk[q] * r * fabsf(r);   // signed: |E| is the squared residual
         }
     } else if (OUT == OUT_S_PEAKS) {
         float id[NQ], cv[NQ], xv[NQ];
@@ -699,31 +699,32 @@ __global__ __launch_bounds__(kThreads2) void k_filter_mfma(FiltArgs a, Taps tp) 
     }
 }
 
-// Spread epilogue of the strip kernels (four vertically consecutive outputs):
-// S, threshold and the optional S / Y planes as everywhere, but the 7 x 7
+// Spread epilogue of the strip kernels (four vertically consecutive outputs).
+// The residual plane holds E = M r |r| with r = x - C, so the threshold
+// x > C + kappa sqrt(S) (kappa >= 0) is E > 0 and E > kappa^2 S, read from
+// E at the output pixel: this workgroup loaded it as filter input moments
+// ago, so it comes from cache, where X and C would come from HBM.  The 7 x 7
 // local-maximum test of the (few) above-threshold pixels is deferred to the
 // catalogue kernel through a per-band list that can hold every pixel, so the
 // filter kernel neither waits on the window loads nor holds their registers.
 __device__ inline void strip_spread_epilogue(const FiltArgs& a, int b, size_t bo, int gy0, int gx, const float* v,
                                              int nvalid) {
-    float id[4], cv[4], xv[4];
-    bool mk[4];
+    float id[4], ev[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int gy = gy0 + q < a.H ? gy0 + q : a.H - 1;
         const size_t p = (size_t)gy * a.W + gx;
         id[q] = a.inv_den[p];
-        cv[q] = a.C[bo + p];
-        xv[q] = a.X[bo + p];
-        mk[q] = q < nvalid && (a.M ? a.M[p] != 0 : true);
+        ev[q] = a.E[bo + p];   // 0 outside the sky mask
     }
+    const float k2 = a.kappa * a.kappa;
     bool y[4];
     float s[4];
     bool any = false;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         s[q] = v[q] * id[q];
-        y[q] = mk[q] && id[q] > 0.0f && xv[q] > cv[q] + a.kappa * sqrtf(s[q]);
+        y[q] = q < nvalid && id[q] > 0.0f && ev[q] > 0.0f && ev[q] > k2 * s[q];
         any |= y[q];
     }
     if (a.S_out || a.Y_out || a.Y_out2) {
@@ -837,6 +838,12 @@ __global__ __launch_bounds__(kStripThreads) void k_filter_strip(FiltArgs a, Taps
                     v.y = (float)((bits >> 1) & 1u) * v.y;
                     v.z = (float)((bits >> 2) & 1u) * v.z;
                     v.w = (float)((bits >> 3) & 1u) * v.w;
+                }
+                if (IN == IN_E) {   // the residual plane is signed
+                    v.x = fabsf(v.x);
+                    v.y = fabsf(v.y);
+                    v.z = fabsf(v.z);
+                    v.w = fabsf(v.w);
                 }
                 *reinterpret_cast<float4*>(stage + row * G::SW + 4 * c4) = v;
             }
@@ -998,6 +1005,12 @@ __global__ __launch_bounds__(kStripThreads) void k_filter_strip16(FiltArgs a, Ta
                     v.y = (float)((bits >> 1) & 1u) * v.y;
                     v.z = (float)((bits >> 2) & 1u) * v.z;
                     v.w = (float)((bits >> 3) & 1u) * v.w;
+                }
+                if (IN == IN_E) {   // the residual plane is signed
+                    v.x = fabsf(v.x);
+                    v.y = fabsf(v.y);
+                    v.z = fabsf(v.z);
+                    v.w = fabsf(v.w);
                 }
                 const float sc = SCALE ? 1.0f / 256.0f : 1.0f;
                 T* d = stage + row * G::SW + 4 * c4;

@@ -79,7 +79,7 @@ struct DevBufs {
     uint32_t* mask_bits;   // [H][mwords] packed sky mask
     float* inv_den;        // [H][W] 1 / (G * M), 0 where G * M = 0
     float* centre;         // [B][H][W]
-    float* resid;          // [B][H][W] E = M (X - C)^2 (strip kernels)
+    float* resid;          // [B][H][W] E = M r |r|, r = X - C: signed squared residual (strip kernels)
     float* spread;         // [B][H][W] (debug or iterations > 1)
     uint8_t* clip;         // [B][H][W] (debug or iterations > 1)
     float* den;            // [B][H][W] (iterations > 1)
