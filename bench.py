@@ -313,7 +313,7 @@ def main():
         prof_all = ctx.profile_read()
         dom = max((k for k in prof_all if k != "network" and prof_all[k][1] > 0),
                   key=lambda k: prof_all[k][0] / prof_all[k][1])
-        # timed run: events around the dominant kernel of every 4th step only (each
+        # timed run: events around the dominant kernel of every 8th step only (each
         # event pair costs the stream several microseconds)
         t_base = warmup + n_prof
         n_inf[0] = 0
@@ -322,9 +322,9 @@ def main():
         t0 = time.perf_counter()
         for i in range(steps):
             f0 = time.perf_counter()
-            if i % 4 == 0:
+            if i % 8 == 0:
                 ctx.profile(True, stages=[dom])
-            elif i % 4 == 1:
+            elif i % 8 == 1:
                 ctx.profile(False)
             step(t_base + i)
             lat.append(time.perf_counter() - f0)
@@ -403,7 +403,7 @@ def main():
         "roofline": roof,
         "stages": stages,
         "stages_note": "per-stage event timings from an untimed pass (events around every stage); "
-                       "the timed steps record events around the dominant kernel of every 4th step",
+                       "the timed steps record events around the dominant kernel of every 8th step",
     }
     out["network_batch1024"] = {name: network_batch(Model, synth.cnn_weights(), code)
                                 for code, name in ((0, "fp32"), (1, "bf16"), (2, "fp16"))}

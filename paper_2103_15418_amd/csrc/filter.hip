@@ -1193,9 +1193,9 @@ int strip_height(int H, int tiles_x, int nbands, int target) {
 template <int K, int IN, int OUT>
 hipError_t run_strip(lpf_ctx* c, FiltArgs a, int nbands) {
     a.tiles_x = (a.W + kTileW - 1) / kTileW;
-    // measured on 16 x 1024^2: the centre pass is fastest at ~4, the spread
-    // pass at ~8 workgroups per CU
-    a.strip_h = strip_height(a.H, a.tiles_x, nbands, OUT == OUT_C_E ? 1024 : 2048);
+    // measured on 16 x 1024^2: both passes are fastest at ~4 workgroups per CU
+    // (256-row strips)
+    a.strip_h = strip_height(a.H, a.tiles_x, nbands, 1024);
     const int nblocks = a.tiles_x * ((a.H + a.strip_h - 1) / a.strip_h) * nbands;
     hipLaunchKernelGGL((k_filter_strip<K, IN, OUT>), dim3(nblocks), dim3(kStripThreads), 0, c->stream, a,
                        c->taps);
@@ -1205,7 +1205,7 @@ hipError_t run_strip(lpf_ctx* c, FiltArgs a, int nbands) {
 template <typename T, int K, int IN, int OUT>
 hipError_t run_strip16(lpf_ctx* c, FiltArgs a, int nbands) {
     a.tiles_x = (a.W + kTileW - 1) / kTileW;
-    a.strip_h = strip_height(a.H, a.tiles_x, nbands, OUT == OUT_C_E ? 1024 : 2048);
+    a.strip_h = strip_height(a.H, a.tiles_x, nbands, 1024);
     const int nblocks = a.tiles_x * ((a.H + a.strip_h - 1) / a.strip_h) * nbands;
     hipLaunchKernelGGL((k_filter_strip16<T, K, IN, OUT>), dim3(nblocks), dim3(kStripThreads), 0, c->stream, a,
                        c->taps);

@@ -150,39 +150,39 @@ __global__ __launch_bounds__(kIngThreads) void k_ingest(
     }
 }
 
-// Median of the entries of v flagged in use, computed by lanes 0..B-1 of one
-// wave: each lane ranks its value (ties by index) and scatters it to its
-// rank, so no lane runs a serial sort.  tmp: LDS scratch of kMaxB doubles.
-__device__ double wave_median(double v, bool use, int B, double* tmp) {
+__device__ inline double readlane_d(double v, int j) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), j);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), j);
+    return __hiloint2double(hi, lo);
+}
+
+// Median of the entries of v flagged in use, over lanes 0..B-1 of one fully
+// active wave: each lane ranks its value (ties by index) against the others
+// read lane by lane from registers, and the median is read from the lanes
+// that hold the middle ranks.  Every lane returns it.
+__device__ double wave_median(double v, bool use, int B) {
     const int lane = threadIdx.x & 63;
-    __shared__ double s_v[kMaxB];
-    __shared__ int s_use[kMaxB];
-    if (lane < B) {
-        s_v[lane] = v;
-        s_use[lane] = use;
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    int m = 0, rank = 0;
+    const bool u = use && lane < B;
+    const uint64_t um = __ballot(u);
+    const int m = __popcll(um);
+    if (m == 0) return 0.0;
+    int rank = 0;
     for (int j = 0; j < B; ++j) {
-        if (!s_use[j]) continue;
-        ++m;
-        if (lane < B && use && (s_v[j] < v || (s_v[j] == v && j < lane))) ++rank;
+        if (!((um >> j) & 1ull)) continue;   // uniform
+        const double vj = readlane_d(v, j);
+        rank += (vj < v || (vj == v && j < lane)) ? 1 : 0;
     }
-    if (lane < B && use) tmp[rank] = v;
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    double med = 0.0;
-    if (m > 0) med = (m & 1) ? tmp[m / 2] : 0.5 * (tmp[m / 2 - 1] + tmp[m / 2]);
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    return med;
+    const uint64_t hi = __ballot(u && rank == m / 2);
+    const double vh = readlane_d(v, __ffsll((unsigned long long)hi) - 1);
+    if (m & 1) return vh;
+    const uint64_t lo = __ballot(u && rank == m / 2 - 1);
+    return 0.5 * (readlane_d(v, __ffsll((unsigned long long)lo) - 1) + vh);
 }
 
 // Robust z of lane b's value: (v - med) / max(MAD, floor |med|), 0 if unused.
-__device__ double wave_robust_z(double v, bool use, int B, double floor_rel, double* tmp) {
-    const double med = wave_median(v, use, B, tmp);
-    double mad = wave_median(fabs(v - med), use, B, tmp);
+__device__ double wave_robust_z(double v, bool use, int B, double floor_rel) {
+    const double med = wave_median(v, use, B);
+    double mad = wave_median(fabs(v - med), use, B);
     const double fl = floor_rel * fabs(med);
     if (fl > mad) mad = fl;
     if (!use) return 0.0;
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(1024) void k_qc_decide(QcParams q, const BandPartia
                                                      int32_t* wf_n, int32_t* wf_cur, double* bandstats,
                                                      int64_t* cache_t, uint32_t* cache_rej, int slot,
                                                      int64_t t, DevStatus* status) {
-    __shared__ double s_mean[kMaxB], s_rms[kMaxB], s_tmp[kMaxB];
+    __shared__ double s_mean[kMaxB], s_rms[kMaxB];
     __shared__ int s_nf[kMaxB];
     __shared__ float s_z[kMaxB];
     for (int i = threadIdx.x; i < q.n_changed; i += blockDim.x) q.changed[i] = 0;
@@ -246,8 +246,8 @@ __global__ __launch_bounds__(1024) void k_qc_decide(QcParams q, const BandPartia
     const int i = threadIdx.x;
     const bool in = i < q.B;
     const bool ok = in && s_nf[i] == 0;
-    const double zm = wave_robust_z(in ? s_mean[i] : 0.0, ok, q.B, 0.0, s_tmp);
-    const double zr = q.rms_z > 0.0 ? wave_robust_z(in ? s_rms[i] : 0.0, ok, q.B, q.rms_floor, s_tmp) : 0.0;
+    const double zm = wave_robust_z(in ? s_mean[i] : 0.0, ok, q.B, 0.0);
+    const double zr = q.rms_z > 0.0 ? wave_robust_z(in ? s_rms[i] : 0.0, ok, q.B, q.rms_floor) : 0.0;
     bool bad = false;
     if (in) {
         const int n = wf_n[i];
