@@ -355,15 +355,17 @@ def main():
             ent.update(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS)
         elif name in ("centre", "spread_peaks"):
             # algorithmic work: two 1-D passes of 2k+1 taps (FMA = 2 FLOP) per pixel; both passes
-            # run as banded products on the float32 matrix cores.  Algorithmic bytes: x (and c)
-            # read, c written = 8 B per pixel.
+            # run as banded products on the float32 matrix cores.  Algorithmic bytes: the centre
+            # pass reads x and writes c and the signed residual plane (12 B per pixel), the
+            # spread pass reads the residual plane (4 B per pixel; S is not stored).
             k = ctx.cfg.bg_halfwidth if ctx.cfg.bg_halfwidth > 0 else int(np.ceil(3 * ctx.cfg.bg_sigma))
             flops = 2.0 * 2 * (2 * k + 1) * px_step
             ach = flops / (avg * 1e-3) / 1e12
+            bpp = 12.0 if name == "centre" else 4.0
             ent.update(bound="mfma", achieved=ach, peak=FP32_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
                        frac=ach / FP32_MFMA_PEAK_TFLOPS,
-                       hbm_view={"bytes_per_px": 8, "achieved_gbs": 8.0 * px_step / (avg * 1e-3) / 1e9,
-                                 "frac": 8.0 * px_step / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS})
+                       hbm_view={"bytes_per_px": bpp, "achieved_gbs": bpp * px_step / (avg * 1e-3) / 1e9,
+                                 "frac": bpp * px_step / (avg * 1e-3) / 1e9 / HBM_PEAK_GBS})
         elif name == "network":
             # the network runs on the model's own stream, overlapped with the next step's
             # kernels: its event span is not a kernel duration (see network_batch1024)
