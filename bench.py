@@ -252,6 +252,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="real-time serving run (1 s cadence +- 100 ms); 600 reproduces the full scenario")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="ingest on the context's stream after the previous step's flux")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, copy 1 GiB device-to-device once (reference for HBM counters)")
     args = ap.parse_args()
@@ -278,7 +280,10 @@ def main():
         """Times `steps` steps after `warmup`; returns (elapsed s, latencies, stage profile, windows).
         frames: the cubes to cycle through (default: the device-resident pool)."""
         frames = pool if frames is None else frames
-        ctx = Context(B, H, W, sky_mask=st.mask, filter_precision=precision)
+        # the next step's ingest and QC run beside this step's catalogue and flux
+        # (the cubes are resident before the loop starts)
+        ctx = Context(B, H, W, sky_mask=st.mask, filter_precision=precision,
+                      pipeline_ingest=0 if args.no_pipeline else 1)
         model = Model(synth.cnn_weights(), precision=precision, max_batch=1024)
         torch.cuda.synchronize()
         n_inf = [0]
@@ -399,6 +404,7 @@ def main():
                                f"{'circular sky mask, ' if spec.mask else ''}{spec.n_sources} dispersed sources, "
                                f"one cube per step (QC + detect + associate + flux/backfill + network)",
                    "kappa": ctx.cfg.kappa, "bg_sigma": ctx.cfg.bg_sigma, "clip_iters": ctx.cfg.clip_iters,
+                   "pipeline_ingest": int(ctx.cfg.pipeline_ingest),
                    "network_precision": "fp32", "windows_inferred": n_inferred[0]},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "max": float(lat_ms.max())},

@@ -91,6 +91,12 @@ typedef struct {
     int32_t peak_cap;         /* per band per step; B * peak_cap <= 8192        */
     int32_t filter_precision; /* LPF_PREC_FP32, or BF16 / FP16 operands on MFMA  */
     int32_t debug_planes;     /* 1: also keep S (and the clip mask) readable    */
+    int32_t pipeline_ingest;  /* 1: ingest and QC of the next step run on a
+                                 stream of the context's own, beside this
+                                 step's catalogue and flux (see
+                                 lpf_ingest_frame); the image cache holds one
+                                 step more.  0: everything on the context's
+                                 stream                                        */
 } lpf_config;
 
 /* One peak of the map P = Q and Y (Sec. 2.1.2) with the local estimates. */
@@ -138,6 +144,11 @@ void lpf_destroy(lpf_ctx* ctx);
 /* Quality control (App. A) of the cube for step t and its entry into the
  * image cache.  cube: [B][H][W] float32, device memory if cube_on_device,
  * else host memory (copied before return).  A device cube is only read.
+ * Ordering: after earlier work on the context's stream; with
+ * pipeline_ingest = 1 only after the previous step's filters instead (the
+ * first ingest after create waits for the whole stream), so a device cube
+ * must then be complete before the previous lpf_detect call was made, or be
+ * produced on a stream the caller has synchronised.
  * Per band: mean and RMS over all pixels (float64 sums), robust z of each
  * across bands, max |zeta| of sky pixels against the running mean/std of
  * accepted steps; a band failing any test (or holding a non-finite value)

@@ -44,6 +44,7 @@ class Config(C.Structure):
         ("qc_band_z", C.c_float), ("qc_rms_z", C.c_float), ("qc_rms_floor", C.c_float),
         ("qc_pixel_zeta", C.c_float), ("qc_warmup", C.c_int32), ("max_sources", C.c_int32),
         ("peak_cap", C.c_int32), ("filter_precision", C.c_int32), ("debug_planes", C.c_int32),
+        ("pipeline_ingest", C.c_int32),
     ]
 
 

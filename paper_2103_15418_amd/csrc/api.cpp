@@ -78,6 +78,7 @@ int validate(const lpf_config* c, std::string* why) {
     if (c->filter_precision != LPF_PREC_FP32 &&
         (c->clip_iters != 1 || c->W % 4 != 0 || (k != 15 && k != 24 && k != 36)))
         return bad("16-bit filters need clip_iters = 1, W % 4 = 0 and half-width 15, 24 or 36");
+    if (c->pipeline_ingest != 0 && c->pipeline_ingest != 1) return bad("pipeline_ingest must be 0 or 1");
     if (c->grid_rows) {
         bool used[kGridRows] = {};
         for (int b = 0; b < c->B; ++b) {
@@ -92,7 +93,9 @@ int validate(const lpf_config* c, std::string* why) {
 Derived derive(const lpf_config* c) {
     Derived d{};
     d.k = c->bg_halfwidth > 0 ? c->bg_halfwidth : (int)std::ceil(3.0 * (double)c->bg_sigma);
-    d.Tc = c->backfill_steps + 1;
+    // the cache holds the backfill window and the current step, and with a
+    // pipelined ingest also the next step, written while this one is measured
+    d.Tc = c->backfill_steps + 1 + (c->pipeline_ingest ? 1 : 0);
     d.HW = (size_t)c->H * c->W;
     d.plane = (size_t)c->B * d.HW;
     d.masked = c->sky_mask != nullptr;
@@ -292,16 +295,26 @@ int lpf_create(const lpf_config* cfg, void* ws, size_t bytes, void* stream, lpf_
     if (e == hipSuccess && c->buf.spread) e = zero(c->buf.spread, d.plane * sizeof(float));
     if (e == hipSuccess && c->buf.clip) e = zero(c->buf.clip, 2 * d.plane);
     if (e == hipSuccess) e = zero(c->buf.src_id, cfg->max_sources * sizeof(int32_t));
+    // detection counters (cleared again by the catalogue kernel of every step)
+    if (e == hipSuccess) e = zero(c->buf.peak_cnt, kMaxB * sizeof(int32_t));
+    if (e == hipSuccess) e = zero(c->buf.cand_cnt, kMaxB * sizeof(int32_t));
+    if (e == hipSuccess) e = zero(c->buf.changed, (size_t)(kMaxIters + 1) * kMaxB * sizeof(int32_t));
     if (e == hipSuccess) e = launch_table_init(c);
     if (e == hipSuccess) e = launch_pack_mask(c);
     if (e == hipSuccess) e = launch_inv_den(c);
-    if (e == hipSuccess && d.masked) {
-        // mask copy is from pageable host memory: finish before returning
+    if (e == hipSuccess && cfg->pipeline_ingest) {
+        e = hipStreamCreateWithFlags(&c->ing_stream, hipStreamNonBlocking);   // default priority
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_filt, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_qc, hipEventDisableTiming);
+    }
+    if (e == hipSuccess && (d.masked || cfg->pipeline_ingest)) {
+        // mask copy is from pageable host memory, and a pipelined ingest is
+        // not ordered after this initialisation: finish before returning
         e = hipStreamSynchronize(s);
     }
     if (e != hipSuccess) {
         dev_fail(c, e, "lpf_create");
-        delete c;
+        lpf_destroy(c);
         return LPF_EDEVICE;
     }
     *out = c;
@@ -310,9 +323,15 @@ int lpf_create(const lpf_config* cfg, void* ws, size_t bytes, void* stream, lpf_
 
 void lpf_destroy(lpf_ctx* c) {
     if (!c) return;
-    if (!c->poisoned) (void)hipStreamSynchronize(c->stream);
+    if (!c->poisoned) {
+        (void)hipStreamSynchronize(c->stream);
+        if (c->ing_stream) (void)hipStreamSynchronize(c->ing_stream);
+    }
     for (auto& e : c->prof_pool) (void)hipEventDestroy(e);
     if (c->ev_ready) (void)hipEventDestroy(c->ev_ready);
+    if (c->ev_filt) (void)hipEventDestroy(c->ev_filt);
+    if (c->ev_qc) (void)hipEventDestroy(c->ev_qc);
+    if (c->ing_stream) (void)hipStreamDestroy(c->ing_stream);
     delete c;
 }
 
@@ -323,20 +342,32 @@ int lpf_ingest_frame(lpf_ctx* c, int64_t t, const float* cube, int32_t on_device
     if (c->n_frames > 0 && t <= c->t_last) return fail(c, LPF_EORDER, "t must increase");
     const int slot = pmod(t, c->d.Tc);
     float* dst = c->buf.cache + (size_t)slot * c->d.plane;
+    // pipelined: the context's own ingest stream, ordered after the previous
+    // step's filters (which follow the flux that last read this cache slot),
+    // or after everything on the context's stream before the first detect
+    hipStream_t s = c->ing_stream ? c->ing_stream : c->stream;
+    if (c->ing_stream) {
+        if (!c->filt_recorded) LPF_HIP(c, hipEventRecord(c->ev_filt, c->stream), "event record");
+        LPF_HIP(c, hipStreamWaitEvent(s, c->ev_filt, 0), "event wait");
+    }
     if (on_device) {
-        StageTimer tm(c, 0);
-        LPF_HIP(c, launch_ingest(c, cube, true, slot), "ingest");
+        StageTimer tm(c, 0, s);
+        LPF_HIP(c, launch_ingest(c, cube, true, slot, s), "ingest");
     } else {
-        LPF_HIP(c, hipMemcpyAsync(dst, cube, c->d.plane * sizeof(float), hipMemcpyHostToDevice, c->stream),
+        LPF_HIP(c, hipMemcpyAsync(dst, cube, c->d.plane * sizeof(float), hipMemcpyHostToDevice, s),
                 "ingest H2D");
-        StageTimer tm(c, 0);
-        LPF_HIP(c, launch_ingest(c, dst, false, slot), "ingest");
+        StageTimer tm(c, 0, s);
+        LPF_HIP(c, launch_ingest(c, dst, false, slot, s), "ingest");
     }
     {
-        StageTimer tm(c, 1);
-        LPF_HIP(c, launch_qc_decide(c, slot, t), "qc");
+        StageTimer tm(c, 1, s);
+        LPF_HIP(c, launch_qc_decide(c, slot, t, s), "qc");
     }
-    if (!on_device) LPF_HIP(c, hipStreamSynchronize(c->stream), "ingest sync");
+    if (c->ing_stream) {
+        LPF_HIP(c, hipEventRecord(c->ev_qc, s), "event record");
+        c->qc_pending = true;
+    }
+    if (!on_device) LPF_HIP(c, hipStreamSynchronize(s), "ingest sync");
     if (c->n_frames == 0) c->t_start = t;
     c->t_last = t;
     c->n_frames++;
@@ -344,9 +375,9 @@ int lpf_ingest_frame(lpf_ctx* c, int64_t t, const float* cube, int32_t on_device
     c->host_n_ended = -1;
     if (rej_out) {
         uint32_t r = 0;
-        LPF_HIP(c, hipMemcpyAsync(&r, &c->buf.status->rejected, sizeof(r), hipMemcpyDeviceToHost, c->stream),
+        LPF_HIP(c, hipMemcpyAsync(&r, &c->buf.status->rejected, sizeof(r), hipMemcpyDeviceToHost, s),
                 "ingest D2H");
-        LPF_HIP(c, hipStreamSynchronize(c->stream), "ingest sync");
+        LPF_HIP(c, hipStreamSynchronize(s), "ingest sync");
         *rej_out = r;
     }
     return LPF_OK;
@@ -357,8 +388,18 @@ int lpf_detect(lpf_ctx* c, lpf_peak* peaks, int32_t cap, int32_t* n_peaks, lpf_s
     LPF_CHECK_CTX(c);
     if (c->phase != 1) return fail(c, LPF_ESTATE, "detect needs a fresh ingest");
     const int slot = pmod(c->t_last, c->d.Tc);
-    // (the per-step detection counters were cleared by the QC kernel of this ingest)
+    // (the detection counters were cleared by the previous step's catalogue)
+    if (c->qc_pending) {
+        LPF_HIP(c, hipStreamWaitEvent(c->stream, c->ev_qc, 0), "event wait");
+        c->qc_pending = false;
+    }
     LPF_HIP(c, launch_filters(c, slot), "filters");
+    if (c->ing_stream) {
+        // the next ingest may start now: it writes a cache slot nothing of
+        // this step reads, and state the catalogue and flux do not touch
+        LPF_HIP(c, hipEventRecord(c->ev_filt, c->stream), "event record");
+        c->filt_recorded = true;
+    }
     {
         StageTimer tm(c, 4);
         LPF_HIP(c, launch_catalog(c, c->t_last), "catalog");
@@ -409,6 +450,7 @@ int lpf_status(lpf_ctx* c, lpf_status_t* out) {
     LPF_CHECK_CTX(c);
     if (!out) return LPF_EINVAL;
     DevStatus st;
+    if (c->ing_stream) LPF_HIP(c, hipStreamSynchronize(c->ing_stream), "status sync");
     LPF_HIP(c, hipMemcpyAsync(&st, c->buf.status, sizeof(st), hipMemcpyDeviceToHost, c->stream), "status D2H");
     LPF_HIP(c, hipStreamSynchronize(c->stream), "status sync");
     out->t = c->t_last;
@@ -471,6 +513,7 @@ int lpf_debug_read(lpf_ctx* c, int32_t what, void* host, size_t bytes) {
     const void* src = nullptr;
     size_t need = 0;
     std::vector<int32_t> cur(kMaxB);
+    if (c->ing_stream) LPF_HIP(c, hipStreamSynchronize(c->ing_stream), "debug sync");
     LPF_HIP(c, hipStreamSynchronize(c->stream), "debug sync");
     switch (what) {
         case LPF_DBG_BANDSTATS: src = c->buf.bandstats; need = (size_t)c->cfg.B * 6 * sizeof(double); break;
@@ -517,6 +560,7 @@ int lpf_profile_enable(lpf_ctx* c, int32_t stages) {
 
 int lpf_profile_read(lpf_ctx* c, double* ms, int64_t* counts) {
     LPF_CHECK_CTX(c);
+    if (c->ing_stream) LPF_HIP(c, hipStreamSynchronize(c->ing_stream), "profile sync");
     LPF_HIP(c, hipStreamSynchronize(c->stream), "profile sync");
     for (int i = 0; i < LPF_STAGE_COUNT; ++i) {
         if (ms) ms[i] = 0.0;
@@ -535,6 +579,7 @@ int lpf_profile_read(lpf_ctx* c, double* ms, int64_t* counts) {
 
 int lpf_sync(lpf_ctx* c) {
     LPF_CHECK_CTX(c);
+    if (c->ing_stream) LPF_HIP(c, hipStreamSynchronize(c->ing_stream), "sync");
     LPF_HIP(c, hipStreamSynchronize(c->stream), "sync");
     return LPF_OK;
 }

@@ -32,11 +32,13 @@ struct CatArgs {
     int B, peak_cap, max_sources, n_mon;
     float r_dup2, r_assoc2;
     int64_t t;
-    const int32_t* peak_cnt;
+    int32_t* peak_cnt;
     PeakRec* peak_raw;
+    int32_t* changed;        // per-iteration changed flags, cleared for the next step
+    int n_changed;
     // deferred local-maximum test (strip filters): above-threshold pixels per band
     const int2* pk_cand;         // [B][H*W] (pixel index, S bits), null if peaks are already listed
-    const int32_t* pk_cand_cnt;  // [B]
+    int32_t* pk_cand_cnt;        // [B]
     const float* X;           // this step's cube [B][H][W]
     const float* C;           // centre plane [B][H][W]
     const uint8_t* M;         // sky mask [H][W] or null
@@ -202,11 +204,15 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
     const int64_t t = a.t;
 
     // per-band peak counts, read in parallel (one dependent read per band
-    // would serialise as many memory latencies)
+    // would serialise as many memory latencies), then the step's detection
+    // counters are cleared for the next step's filters
     if (tid < a.B) {
         s_cnt[tid] = a.peak_cnt[tid];
+        a.peak_cnt[tid] = 0;
         if (a.pk_cand) s_off[tid + 1] = a.pk_cand_cnt[tid];
+        a.pk_cand_cnt[tid] = 0;
     }
+    for (int i = tid; i < a.n_changed; i += kCatThreads) a.changed[i] = 0;
     __syncthreads();
 
     // ---- -1. deferred local-maximum test (Sec. 2.1.2) of the above-threshold
@@ -768,6 +774,8 @@ hipError_t launch_catalog(lpf_ctx* c, int64_t t) {
     a.t = t;
     a.peak_cnt = c->buf.peak_cnt;
     a.peak_raw = c->buf.peak_raw;
+    a.changed = c->buf.changed;
+    a.n_changed = (kMaxIters + 1) * c->cfg.B;
     a.peak_sorted = c->buf.peak_sorted;
     // the strip filters of one clip iteration leave the peak test to this kernel
     const bool deferred = c->d.strip && c->cfg.clip_iters == 1;

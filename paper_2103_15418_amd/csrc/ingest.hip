@@ -196,11 +196,6 @@ struct QcParams {
     double npix;
     double band_z, rms_z, rms_floor, zeta;
     int warm;
-    // per-step detection counters cleared here (one launch fewer per step)
-    int32_t* peak_cnt;   // [B]
-    int32_t* cand_cnt;   // [B]
-    int32_t* changed;    // [n_changed]
-    int n_changed;
 };
 
 // One wave per band reduces that band's block partials (lane l sums blocks
@@ -213,11 +208,6 @@ __global__ __launch_bounds__(1024) void k_qc_decide(QcParams q, const BandPartia
     __shared__ double s_mean[kMaxB], s_rms[kMaxB];
     __shared__ int s_nf[kMaxB];
     __shared__ float s_z[kMaxB];
-    for (int i = threadIdx.x; i < q.n_changed; i += blockDim.x) q.changed[i] = 0;
-    if ((int)threadIdx.x < q.B) {
-        q.peak_cnt[threadIdx.x] = 0;
-        q.cand_cnt[threadIdx.x] = 0;
-    }
     const int b = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (b < q.B) {
         double sx = 0.0, sxx = 0.0;
@@ -276,7 +266,7 @@ __global__ __launch_bounds__(1024) void k_qc_decide(QcParams q, const BandPartia
 
 }  // namespace
 
-hipError_t launch_ingest(lpf_ctx* c, const float* src, bool copy, int slot) {
+hipError_t launch_ingest(lpf_ctx* c, const float* src, bool copy, int slot, hipStream_t s) {
     const auto& d = c->d;
     const int B = c->cfg.B;
     float* slotp = c->buf.cache + (size_t)slot * d.plane;
@@ -285,7 +275,7 @@ hipError_t launch_ingest(lpf_ctx* c, const float* src, bool copy, int slot) {
     dim3 grid(d.nblk, B);
     const uint8_t* mk = d.masked ? c->buf.mask : nullptr;
 #define LPF_ING(C, V)                                                                        \
-    hipLaunchKernelGGL((k_ingest<C, V>), grid, dim3(kIngThreads), 0, c->stream, src, slotp,   \
+    hipLaunchKernelGGL((k_ingest<C, V>), grid, dim3(kIngThreads), 0, s, src, slotp,           \
                        c->buf.wf_mean, c->buf.wf_m2, c->buf.wf_mean, c->buf.wf_m2, c->buf.wf_n, \
                        c->buf.wf_cur, mk, d.HW, d.plane, chunk, c->cfg.qc_warmup, c->buf.partials)
     if (copy && vec) LPF_ING(true, true);
@@ -296,7 +286,7 @@ hipError_t launch_ingest(lpf_ctx* c, const float* src, bool copy, int slot) {
     return hipGetLastError();
 }
 
-hipError_t launch_qc_decide(lpf_ctx* c, int slot, int64_t t) {
+hipError_t launch_qc_decide(lpf_ctx* c, int slot, int64_t t, hipStream_t s) {
     QcParams q;
     q.B = c->cfg.B;
     q.nblk = c->d.nblk;
@@ -306,11 +296,7 @@ hipError_t launch_qc_decide(lpf_ctx* c, int slot, int64_t t) {
     q.rms_floor = c->cfg.qc_rms_floor;
     q.zeta = c->cfg.qc_pixel_zeta;
     q.warm = c->cfg.qc_warmup;
-    q.peak_cnt = c->buf.peak_cnt;
-    q.cand_cnt = c->buf.cand_cnt;
-    q.changed = c->buf.changed;
-    q.n_changed = (kMaxIters + 1) * c->cfg.B;
-    hipLaunchKernelGGL(k_qc_decide, dim3(1), dim3(64 * c->cfg.B), 0, c->stream, q, c->buf.partials, c->buf.wf_n,
+    hipLaunchKernelGGL(k_qc_decide, dim3(1), dim3(64 * c->cfg.B), 0, s, q, c->buf.partials, c->buf.wf_n,
                        c->buf.wf_cur, c->buf.bandstats, c->buf.cache_t, c->buf.cache_rej, slot, t,
                        c->buf.status);
     return hipGetLastError();

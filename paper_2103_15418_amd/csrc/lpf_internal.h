@@ -158,6 +158,11 @@ struct lpf_ctx {
     int32_t host_n_ended = -1;
     std::vector<int32_t> host_ended_ids;   // list order (the order of the ended-slot list)
     hipEvent_t ev_ready = nullptr;         // cross-stream hand-off in pooled inference
+    // pipelined ingest: ingest + QC on ing_stream, ordered after the previous
+    // step's filters (ev_filt); the next detect waits for the QC (ev_qc)
+    hipStream_t ing_stream = nullptr;
+    hipEvent_t ev_filt = nullptr, ev_qc = nullptr;
+    bool filt_recorded = false, qc_pending = false;
 };
 
 namespace lpf {
@@ -284,8 +289,8 @@ struct StageTimer {
 };
 
 // Launchers (defined in the .hip files); return hipError_t of the launch.
-hipError_t launch_ingest(lpf_ctx* c, const float* src, bool copy, int slot);
-hipError_t launch_qc_decide(lpf_ctx* c, int slot, int64_t t);
+hipError_t launch_ingest(lpf_ctx* c, const float* src, bool copy, int slot, hipStream_t s);
+hipError_t launch_qc_decide(lpf_ctx* c, int slot, int64_t t, hipStream_t s);
 hipError_t launch_filters(lpf_ctx* c, int slot);
 hipError_t launch_inv_den(lpf_ctx* c);
 hipError_t launch_pack_mask(lpf_ctx* c);
