@@ -290,13 +290,15 @@ def main():
         pending = []
 
         def step(t):
-            # the network's results of step t are collected during step t + 1,
-            # so the host enqueues the next frame while the device finishes
+            # the network's results of step t are collected during step t + 2
+            # (a pipelined context launches that network after the filters of
+            # step t + 1), so the host enqueues the next frame while the device
+            # finishes
             ctx.ingest(t, frames[t % len(frames)])
             ctx.detect(want=False)
             ctx.extract_flux()
             pending.append(model.infer_async([ctx]))
-            if len(pending) > 1:
+            if len(pending) > 2:
                 mu, L, src = model.collect(pending.pop(0))
                 n_inf[0] += len(mu)
 

@@ -195,6 +195,38 @@ int pmod(int64_t a, int m) {
 
 
 }  // namespace
+namespace {
+
+// The network on a gathered ticket's windows, on the model's stream after
+// event `after`, then the copy of its result block to the ticket's pinned slot.
+int launch_ticket(lpf_model* m, int slot, hipEvent_t after, lpf_ctx* c0) {
+    hipStream_t s = m->istream;
+    const CnnWork& w = m->work;
+    int32_t* hdr = w.sblk[slot];
+    float* mu = reinterpret_cast<float*>(hdr + 4 + 2 * (size_t)m->max_batch);
+    float* L = mu + 4 * (size_t)m->max_batch;
+    LPF_HIP(c0, hipStreamWaitEvent(s, after, 0), "event wait");
+    {
+        StageTimer tm(c0, 6, s);
+        LPF_HIP(c0, cnn_forward(m, w.swin[slot], hdr, m->max_batch, mu, L, s), "cnn");
+    }
+    LPF_HIP(c0, hipMemcpyAsync(m->h_res[slot], hdr, w.out_bytes, hipMemcpyDeviceToHost, s), "result D2H");
+    LPF_HIP(c0, hipEventRecord(m->ev_done[slot], s), "event record");
+    return LPF_OK;
+}
+
+// Issues a context's deferred launch: after `after`, or after its own gather.
+int flush_pending(lpf_ctx* c, hipEvent_t after) {
+    lpf_model* m = c->pend_model;
+    if (!m) return LPF_OK;
+    const int slot = c->pend_slot;
+    c->pend_model = nullptr;
+    c->pend_slot = -1;
+    m->pend_ctx[slot] = nullptr;
+    return launch_ticket(m, slot, after ? after : m->ev_gath[slot], c);
+}
+
+}  // namespace
 }  // namespace lpf
 
 using namespace lpf;
@@ -323,6 +355,11 @@ int lpf_create(const lpf_config* cfg, void* ws, size_t bytes, void* stream, lpf_
 
 void lpf_destroy(lpf_ctx* c) {
     if (!c) return;
+    if (!c->poisoned) (void)flush_pending(c, nullptr);   // its ticket stays collectible
+    if (c->pend_model) {
+        c->pend_model->pend_ctx[c->pend_slot] = nullptr;
+        c->pend_model = nullptr;
+    }
     if (!c->poisoned) {
         (void)hipStreamSynchronize(c->stream);
         if (c->ing_stream) (void)hipStreamSynchronize(c->ing_stream);
@@ -396,9 +433,12 @@ int lpf_detect(lpf_ctx* c, lpf_peak* peaks, int32_t cap, int32_t* n_peaks, lpf_s
     LPF_HIP(c, launch_filters(c, slot), "filters");
     if (c->ing_stream) {
         // the next ingest may start now: it writes a cache slot nothing of
-        // this step reads, and state the catalogue and flux do not touch
+        // this step reads, and state the catalogue and flux do not touch;
+        // so may the network of the previous step's ticket
         LPF_HIP(c, hipEventRecord(c->ev_filt, c->stream), "event record");
         c->filt_recorded = true;
+        const int rc = flush_pending(c, c->ev_filt);
+        if (rc != LPF_OK) return rc;
     }
     {
         StageTimer tm(c, 4);
@@ -632,16 +672,25 @@ int lpf_infer_async(lpf_ctx* const* ctxs, int32_t n_ctx, lpf_model* m, int64_t* 
     const CnnWork& w = m->work;
     int32_t* hdr = w.sblk[slot];
     int32_t* rows = hdr + 4;
-    float* mu = reinterpret_cast<float*>(rows + 2 * (size_t)m->max_batch);
-    float* L = mu + 4 * (size_t)m->max_batch;
     float* win = w.swin[slot];
     if (n_ctx == 1) {
         // one context: its stream gathers into this ticket's buffers and goes
-        // on; only the network waits (on the model's stream)
+        // on; only the network waits (on the model's stream).  A pipelined
+        // context defers the launch to after its next step's filters, so the
+        // network runs beside that step's catalogue rather than its filters.
         lpf_ctx* c = c0;
         LPF_HIP(c, launch_gather_ended(c, 0, hdr, win, rows, m->max_batch, c->stream, true), "gather");
-        LPF_HIP(c, hipEventRecord(m->ev_gathered, c->stream), "event record");
-        LPF_HIP(c, hipStreamWaitEvent(s, m->ev_gathered, 0), "event wait");
+        LPF_HIP(c, hipEventRecord(m->ev_gath[slot], c->stream), "event record");
+        if (c->ing_stream) {
+            const int rc = flush_pending(c, nullptr);   // a ticket gathered earlier, no detect since
+            if (rc != LPF_OK) return rc;
+            c->pend_model = m;
+            c->pend_slot = slot;
+            m->pend_ctx[slot] = c;
+        } else {
+            const int rc = launch_ticket(m, slot, m->ev_gath[slot], c);
+            if (rc != LPF_OK) return rc;
+        }
     } else {
         // several contexts: their streams hand over to the model's stream
         // (flux and rings of this step are final), which gathers them in
@@ -657,13 +706,9 @@ int lpf_infer_async(lpf_ctx* const* ctxs, int32_t n_ctx, lpf_model* m, int64_t* 
         LPF_HIP(c0, hipEventRecord(m->ev_gathered, s), "event record");
         for (int i = 0; i < n_ctx; ++i)
             LPF_HIP(ctxs[i], hipStreamWaitEvent(ctxs[i]->stream, m->ev_gathered, 0), "event wait");
+        const int rc = launch_ticket(m, slot, m->ev_gathered, c0);
+        if (rc != LPF_OK) return rc;
     }
-    {
-        StageTimer tm(c0, 6, s);
-        LPF_HIP(c0, cnn_forward(m, win, hdr, m->max_batch, mu, L, s), "cnn");
-    }
-    LPF_HIP(c0, hipMemcpyAsync(m->h_res[slot], hdr, w.out_bytes, hipMemcpyDeviceToHost, s), "result D2H");
-    LPF_HIP(c0, hipEventRecord(m->ev_done[slot], s), "event record");
     m->slot_ticket[slot] = m->next_ticket;
     *ticket = m->next_ticket++;
     return LPF_OK;
@@ -674,6 +719,10 @@ int lpf_infer_collect(lpf_model* m, int64_t ticket, float* mu_out, float* L_out,
     if (!m || !n_out || ticket < 0) return LPF_EINVAL;
     const int slot = (int)(ticket % kInflight);
     if (m->slot_ticket[slot] != ticket) return LPF_EINVAL;
+    if (m->pend_ctx[slot]) {   // launch not issued yet (no detect since the gather)
+        const int rc = flush_pending(m->pend_ctx[slot], nullptr);
+        if (rc != LPF_OK) return rc;
+    }
     if (hipEventSynchronize(m->ev_done[slot]) != hipSuccess) return LPF_EDEVICE;
     const char* blk = m->h_res[slot];
     const int32_t* hdr = reinterpret_cast<const int32_t*>(blk);

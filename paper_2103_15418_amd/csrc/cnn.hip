@@ -657,6 +657,7 @@ int model_create(const void* weights, size_t bytes, int precision, int maxb, voi
     if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_out, hipEventDisableTiming);
     for (int i = 0; i < kInflight && e == hipSuccess; ++i) {
         e = hipEventCreateWithFlags(&m->ev_done[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_gath[i], hipEventDisableTiming);
         if (e == hipSuccess)
             e = hipHostMalloc(reinterpret_cast<void**>(&m->h_res[i]), m->work.out_bytes, hipHostMallocDefault);
     }
@@ -672,7 +673,12 @@ void model_destroy(lpf_model* m) {
     if (!m) return;
     if (m->istream) (void)hipStreamSynchronize(m->istream);
     for (int i = 0; i < kInflight; ++i) {
+        if (m->pend_ctx[i]) {   // a deferred launch that will not happen: its ticket dies with the model
+            m->pend_ctx[i]->pend_model = nullptr;
+            m->pend_ctx[i]->pend_slot = -1;
+        }
         if (m->ev_done[i]) (void)hipEventDestroy(m->ev_done[i]);
+        if (m->ev_gath[i]) (void)hipEventDestroy(m->ev_gath[i]);
         if (m->h_res[i]) (void)hipHostFree(m->h_res[i]);
     }
     if (m->ev_gathered) (void)hipEventDestroy(m->ev_gathered);

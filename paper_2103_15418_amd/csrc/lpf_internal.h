@@ -163,6 +163,10 @@ struct lpf_ctx {
     hipStream_t ing_stream = nullptr;
     hipEvent_t ev_filt = nullptr, ev_qc = nullptr;
     bool filt_recorded = false, qc_pending = false;
+    // pipelined: a gathered inference ticket whose network launch waits for
+    // this context's next filters (or its collect)
+    lpf_model* pend_model = nullptr;
+    int pend_slot = -1;
 };
 
 namespace lpf {
@@ -209,6 +213,8 @@ struct lpf_model {
     hipStream_t istream = nullptr; // inference stream owned by the model
     hipEvent_t ev_gathered = nullptr, ev_in = nullptr, ev_out = nullptr;
     hipEvent_t ev_done[lpf::kInflight] = {};
+    hipEvent_t ev_gath[lpf::kInflight] = {};   // per-ticket gather done (single-context calls)
+    lpf_ctx* pend_ctx[lpf::kInflight] = {};    // context holding the ticket's deferred launch
     char* h_res[lpf::kInflight] = {};          // pinned result blocks
     int64_t slot_ticket[lpf::kInflight] = {-1, -1, -1, -1};
     int64_t next_ticket = 0;

@@ -112,3 +112,31 @@ def test_pipelined_ingest_asynchronous_steps():
         assert mu_a.tobytes() == mu_b.tobytes() and L_a.tobytes() == L_b.tobytes()
         n += len(src_a)
     assert len(g_seq) == len(g_pip) == T and n > 0
+
+
+def test_deferred_network_launch_flushed_by_destroy():
+    """A pipelined context defers its ticket's network to its next detect; a
+    ticket still deferred when the context is destroyed is launched then and
+    stays collectible, with the sequential context's results."""
+    torch = _torch_cuda()
+    from paper_2103_15418_amd import Context, Model
+    T = 13                      # episodes end at the last step
+    st = _stream(T)
+    dev = [torch.from_numpy(f).cuda() for f in _frames(st, T)]
+    torch.cuda.synchronize()
+    wts = synth.cnn_weights(seed=3)
+    out = []
+    for pipelined in (0, 1):
+        ctx = Context(8, 192, 192, sky_mask=st.mask, pipeline_ingest=pipelined, **PARAMS)
+        model = Model(wts, max_batch=32)
+        for t in range(T):
+            ctx.ingest(t, dev[t])
+            ctx.detect(want=False)
+            ctx.extract_flux()
+        tk = model.infer_async([ctx])
+        ctx.__del__()           # lpf_destroy with the launch still deferred
+        out.append(model.collect(tk))
+    (mu_a, L_a, src_a), (mu_b, L_b, src_b) = out
+    assert len(src_a) > 0
+    assert src_a.tobytes() == src_b.tobytes()
+    assert mu_a.tobytes() == mu_b.tobytes() and L_a.tobytes() == L_b.tobytes()
