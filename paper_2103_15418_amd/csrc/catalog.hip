@@ -4,7 +4,8 @@
 // -1. (strip filters) the local-maximum test of the above-threshold pixels
 //     the filter listed, appending peaks to the band lists;
 //  0. release records reported as ended at the previous step; end episodes
-//     a gap in t carried past their last measured step;
+//     a gap in t carried past their last measured step (done in the pass
+//     that lists the live sources, 4a, which needs nothing from 1-3);
 //  1. order all peaks by (band, row, col) -> the step's peak list;
 //  2. order them by (x descending, band, row, col) -> visiting order;
 //  3. duplicate removal: a peak is kept unless an earlier-visited kept peak
@@ -146,6 +147,40 @@ __device__ int block_scan(int v, int* s_tmp, int* total) {
     return res;
 }
 
+// Three exclusive block scans at once: the counts are packed 21 bits apart
+// into one 64-bit value (each count and total is below 2^21), so the block
+// pays one set of barriers.  o[k]: prefixes, tot[k]: totals.
+__device__ void block_scan3(const int* v, uint64_t* s_tmp64, int* o, int* tot) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t p = (uint64_t)v[0] | ((uint64_t)v[1] << 21) | ((uint64_t)v[2] << 42);
+    uint64_t x = p;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int lo = __shfl_up((int)(uint32_t)x, d, 64);
+        const int hi = __shfl_up((int)(uint32_t)(x >> 32), d, 64);
+        if (lane >= d) x += ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+    }
+    if (lane == 63) s_tmp64[w] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t acc = 0;
+        for (int i = 0; i < kCatThreads / 64; ++i) {
+            const uint64_t t = s_tmp64[i];
+            s_tmp64[i] = acc;
+            acc += t;
+        }
+        s_tmp64[kCatThreads / 64] = acc;
+    }
+    __syncthreads();
+    const uint64_t res = s_tmp64[w] + x - p, t = s_tmp64[kCatThreads / 64];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        o[k] = (int)((res >> (21 * k)) & 0x1fffffull);
+        tot[k] = (int)((t >> (21 * k)) & 0x1fffffull);
+    }
+}
+
 // Eight consecutive table entries s0 .. s0 + 7 of one thread (fill past S):
 // 16-byte loads when the group is whole, so a wave touches each cache line
 // once per instruction pair instead of once per entry.
@@ -158,6 +193,17 @@ __device__ inline void load8(const int32_t* p, int s0, int S, int fill, int* out
     } else {
 #pragma unroll
         for (int i = 0; i < 8; ++i) out[i] = s0 + i < S ? p[s0 + i] : fill;
+    }
+}
+
+__device__ inline void store8(int32_t* p, int s0, int S, const int* v) {
+    if (s0 + 8 <= S) {
+        *reinterpret_cast<int4*>(p + s0) = make_int4(v[0], v[1], v[2], v[3]);
+        *reinterpret_cast<int4*>(p + s0 + 4) = make_int4(v[4], v[5], v[6], v[7]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (s0 + i < S) p[s0 + i] = v[i];
     }
 }
 
@@ -196,6 +242,7 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
     __shared__ int s_off[kMaxB + 1];
     __shared__ int s_cnt[kMaxB];
     __shared__ int s_tmp[kCatThreads / 64 + 1];
+    __shared__ uint64_t s_tmp64[kCatThreads / 64 + 1];
     __shared__ int s_P, s_K, s_nlive, s_held, s_nfree, s_nnew, s_drop, s_next;
     __shared__ uint32_t s_overflow;
 
@@ -292,35 +339,6 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
         __syncthreads();   // the appended records and counts are read below
     }
 
-    // ---- 0. release previous ended records; end episodes left over by a gap
-    for (int s0 = tid; s0 < S; s0 += 8 * kCatThreads) {
-        int st[8];
-        int64_t tl[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int s = s0 + i * kCatThreads;
-            st[i] = s < S ? a.src_state[s] : kSrcFree;
-            tl[i] = s < S ? a.src_tlast[s] : 0;
-        }
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int s = s0 + i * kCatThreads;
-            if (s >= S) continue;
-            int v = st[i];
-            if (v == kSrcEnded) {
-                v = kSrcFree;
-            } else if (v == kSrcLive && t - tl[i] > a.n_mon) {
-                v = kSrcEnded;
-                a.src_tend[s] = tl[i] + a.n_mon;
-            }
-            a.src_state[s] = v;
-            a.src_new[s] = 0;
-        }
-    }
-    for (int w = tid; w < (S + 31) / 32; w += kCatThreads) {
-        s_taken[w] = 0u;
-        s_seen[w] = 0u;
-    }
     if (tid == 0) {
         int off = 0;
         uint32_t ovf = 0;
@@ -430,17 +448,39 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
     }
     __syncthreads();
 
-    // ---- 4a. live sources (compacted, slot order) and the free list
+    // ---- 0 + 4a. release the records reported as ended at the previous step
+    // and end the episodes left over by a gap, then list the live sources
+    // (compacted, slot order) and the free slots, in one pass over the table
+    for (int w = tid; w < (S + 31) / 32; w += kCatThreads) {
+        s_taken[w] = 0u;
+        s_seen[w] = 0u;
+    }
     int32_t* s_live = reinterpret_cast<int32_t*>(s_keys);        // [S <= 8192 fast path]
     int32_t* s_lpos = s_live + kCatMaxPeaks;
     {
-        // rounds of 8 consecutive slots per thread: loads are issued together and
-        // the scan keeps slot order
+        // rounds of 8 consecutive slots per thread: the loads (state, last
+        // detection, position) are issued together and the scan keeps slot order
         int base_l = 0, base_f = 0, base_h = 0;
         for (int base = 0; base < S; base += 8 * kCatThreads) {
             const int s0 = base + tid * 8;
-            int st[8];
+            int st[8], row[8], col[8];
+            int64_t tdet[8];
             load8(a.src_state, s0, S, -1, st);
+            load8(a.src_tlast, s0, S, (int64_t)0, tdet);
+            load8(a.src_row, s0, S, 0, row);
+            load8(a.src_col, s0, S, 0, col);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                if (st[i] == kSrcEnded) {
+                    st[i] = kSrcFree;
+                } else if (st[i] == kSrcLive && t - tdet[i] > a.n_mon) {
+                    st[i] = kSrcEnded;
+                    a.src_tend[s0 + i] = tdet[i] + a.n_mon;   // live => s0 + i < S
+                }
+            }
+            const int zeros[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            store8(a.src_state, s0, S, st);
+            store8(a.src_new, s0, S, zeros);
             int nl = 0, nf = 0, nh = 0;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
@@ -448,17 +488,18 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
                 nf += st[i] == kSrcFree;
                 nh += st[i] == kSrcLive || st[i] == kSrcEnded;
             }
-            int tl, tf, th;
-            int ol = base_l + block_scan(nl, s_tmp, &tl);
-            int of = base_f + block_scan(nf, s_tmp, &tf);
-            block_scan(nh, s_tmp, &th);
+            int cnt[3] = {nl, nf, nh}, pre[3], tot3[3];
+            block_scan3(cnt, s_tmp64, pre, tot3);
+            const int tl = tot3[0], tf = tot3[1], th = tot3[2];
+            int ol = base_l + pre[0];
+            int of = base_f + pre[1];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int sl = s0 + i;
                 if (st[i] == kSrcLive) {
                     if (ol < kCatMaxPeaks) {
                         s_live[ol] = sl;
-                        s_lpos[ol] = pack_pos(a.src_row[sl], a.src_col[sl]);
+                        s_lpos[ol] = pack_pos(row[i], col[i]);
                     }
                     ++ol;
                 } else if (st[i] == kSrcFree) {
@@ -682,10 +723,12 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
                 ne += st[i] == kSrcEnded;
             }
             // scans first: their barriers then wait on no outstanding stores
-            int tm, tn, te;
-            int om = base_m + block_scan(nm, s_tmp, &tm);
-            int on = base_n + block_scan(nn, s_tmp, &tn);
-            int oe = base_e + block_scan(ne, s_tmp, &te);
+            int cnt[3] = {nm, nn, ne}, pre[3], tot3[3];
+            block_scan3(cnt, s_tmp64, pre, tot3);
+            const int tm = tot3[0], tn = tot3[1], te = tot3[2];
+            int om = base_m + pre[0];
+            int on = base_n + pre[1];
+            int oe = base_e + pre[2];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int sl = s0 + i;
