@@ -38,8 +38,9 @@ struct CatArgs {
     int32_t* changed;        // per-iteration changed flags, cleared for the next step
     int n_changed;
     // deferred local-maximum test (strip filters): above-threshold pixels per band
-    const int2* pk_cand;         // [B][H*W] (pixel index, S bits), null if peaks are already listed
-    int32_t* pk_cand_cnt;        // [B]
+    const int2* pk_cand;         // [cap] (pixel index | band << 24, S bits), null if peaks are already listed
+    int32_t* pk_cand_cnt;        // [1]
+    int pk_cap;                  // entries the list can hold
     const float* X;           // this step's cube [B][H][W]
     const float* C;           // centre plane [B][H][W]
     const uint8_t* M;         // sky mask [H][W] or null
@@ -252,27 +253,26 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
 
     // per-band peak counts, read in parallel (one dependent read per band
     // would serialise as many memory latencies), then the step's detection
-    // counters are cleared for the next step's filters
+    // counters are cleared for the next step's filters.  The candidate count
+    // and the first round of candidates are read in the same round trip (the
+    // entries are used only below the count).
+    const int g8 = tid >> 3, r8 = tid & 7;
+    const int ncand = a.pk_cand ? a.pk_cand_cnt[0] : 0;
+    int2 e_first = make_int2(0, 0);
+    if (a.pk_cand && g8 < a.pk_cap) e_first = a.pk_cand[g8];
     if (tid < a.B) {
         s_cnt[tid] = a.peak_cnt[tid];
         a.peak_cnt[tid] = 0;
-        if (a.pk_cand) s_off[tid + 1] = a.pk_cand_cnt[tid];
-        a.pk_cand_cnt[tid] = 0;
     }
     for (int i = tid; i < a.n_changed; i += kCatThreads) a.changed[i] = 0;
-    __syncthreads();
+    __syncthreads();   // every lane has read the candidate count
+    if (tid == 0 && a.pk_cand) a.pk_cand_cnt[0] = 0;
 
     // ---- -1. deferred local-maximum test (Sec. 2.1.2) of the above-threshold
     // pixels the strip filters listed; peaks are appended to the band lists
     // (counts in LDS).  For the 7 x 7 window eight lanes share a pixel, one
     // window row each, so a wave tests eight pixels with seven loads a lane.
     if (a.pk_cand) {
-        if (tid == 0) {
-            s_off[0] = 0;
-            for (int b = 1; b <= a.B; ++b) s_off[b] += s_off[b - 1];
-        }
-        __syncthreads();
-        const int ncand = s_off[a.B];
         const size_t HW = (size_t)a.H * a.W;
         auto append = [&](int b, int gy, int gx, float xv, float cv, float sv) {
             const int idx = atomicAdd(&s_cnt[b], 1);
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
             a.peak_raw[(size_t)b * a.peak_cap + idx] = rec;
         };
         if (a.kp == 3) {
-            const int g = tid >> 3, r = tid & 7;
+            const int g = g8, r = r8;
             for (int base = 0; base < ncand; base += kCatThreads / 8) {   // uniform trip count
                 const int n = base + g;
                 const bool valid = n < ncand;
@@ -296,14 +296,15 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
                 int b = 0, gy = 0, gx = 0;
                 float xv = 0.0f, cv = 0.0f, sv = 1.0f;
                 if (valid) {
-                    while (n >= s_off[b + 1]) ++b;
-                    const int2 e = a.pk_cand[(size_t)b * HW + (n - s_off[b])];
+                    const int2 e = base == 0 ? e_first : a.pk_cand[n];
+                    b = e.x >> 24;
+                    const int pix = e.x & 0xffffff;
                     const float* Xb = a.X + (size_t)b * HW;
-                    gy = e.x / a.W;
-                    gx = e.x % a.W;
+                    gy = pix / a.W;
+                    gx = pix % a.W;
                     sv = __int_as_float(e.y);
-                    xv = Xb[e.x];
-                    if (r == 0) cv = a.C[(size_t)b * HW + e.x];
+                    xv = Xb[pix];
+                    if (r == 0) cv = a.C[(size_t)b * HW + pix];
                     const int yy = gy + r - 3;
                     if (r < 7 && yy >= 0 && yy < a.H) {
                         float v[7];
@@ -326,14 +327,13 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
             }
         } else {
             for (int n = tid; n < ncand; n += kCatThreads) {
-                int b = 0;
-                while (n >= s_off[b + 1]) ++b;
-                const int2 e = a.pk_cand[(size_t)b * HW + (n - s_off[b])];
+                const int2 e = a.pk_cand[n];
+                const int b = e.x >> 24, pix = e.x & 0xffffff;
                 const size_t bo = (size_t)b * HW;
-                const int gy = e.x / a.W, gx = e.x % a.W;
-                const float xv = a.X[bo + e.x];
+                const int gy = pix / a.W, gx = pix % a.W;
+                const float xv = a.X[bo + pix];
                 if (window_max(a.X + bo, a.M, a.H, a.W, a.kp, gy, gx, xv))
-                    append(b, gy, gx, xv, a.C[bo + e.x], __int_as_float(e.y));
+                    append(b, gy, gx, xv, a.C[bo + pix], __int_as_float(e.y));
             }
         }
         __syncthreads();   // the appended records and counts are read below
@@ -824,6 +824,7 @@ hipError_t launch_catalog(lpf_ctx* c, int64_t t) {
     const bool deferred = c->d.strip && c->cfg.clip_iters == 1;
     a.pk_cand = deferred ? c->buf.cand : nullptr;
     a.pk_cand_cnt = c->buf.cand_cnt;
+    a.pk_cap = (int)std::min<size_t>(c->d.plane, (size_t)INT32_MAX);
     a.X = c->buf.cache + (size_t)pmod_host(t, c->d.Tc) * c->d.plane;
     a.C = c->buf.centre;
     a.M = c->d.masked ? c->buf.mask : nullptr;

@@ -82,8 +82,8 @@ struct FiltArgs {
     const int32_t* active;  // per-band active flags (null = all)
     int32_t* changed;    // per-band changed flags (OUT_S_DYN / OUT_S_PEAKS with Y plane)
     int32_t* peak_cnt;   // [B]
-    int2* cand;          // [B][H*W] above-threshold pixels (pixel index, S bits) for the deferred peak test
-    int32_t* cand_cnt;   // [B]
+    int2* cand;          // [B*H*W] above-threshold pixels (pixel index | band << 24, S bits) for the deferred peak test
+    int32_t* cand_cnt;   // [1]
     PeakRec* peak_raw;   // [B][cap]
     int peak_cap;
     int kp;              // max-filter half-width
@@ -741,8 +741,10 @@ __device__ inline void strip_spread_epilogue(const FiltArgs& a, int b, size_t bo
     if (a.peak_cap > 0) {
         for (int q = 0; q < 4; ++q) {
             if (!y[q]) continue;
-            const int idx = atomicAdd(&a.cand_cnt[b], 1);   // < H * W: each pixel is listed once
-            a.cand[(size_t)b * a.H * a.W + idx] = make_int2((gy0 + q) * a.W + gx, __float_as_int(s[q]));
+            // one list for all bands (< B H W entries: each pixel is listed
+            // once); pixel index < 2^24 (H, W <= 4096), band in the top bits
+            const int idx = atomicAdd(a.cand_cnt, 1);
+            a.cand[idx] = make_int2(((gy0 + q) * a.W + gx) | (b << 24), __float_as_int(s[q]));
         }
     }
     if (a.changed) a.changed[b] = 1;
