@@ -853,6 +853,8 @@ __global__ __launch_bounds__(kStripThreads) void k_filter_strip(FiltArgs a, Taps
     };
 
     // taps in registers: B operand of the row pass, A operand of the column pass
+    // (with no shift and equal k ranges both passes use the same taps)
+    constexpr bool kSameTaps = G::S == G::SC && G::SHIFT == 0;
     float tap[G::S], tapc[G::SC];
 #pragma unroll
     for (int s = 0; s < G::S; ++s) {
@@ -862,7 +864,7 @@ __global__ __launch_bounds__(kStripThreads) void k_filter_strip(FiltArgs a, Taps
 #pragma unroll
     for (int s = 0; s < G::SC; ++s) {
         const int u = lq * G::SC + s - li;
-        tapc[s] = (u >= 0 && u <= 2 * K) ? tp.g[u] : 0.0f;
+        tapc[s] = kSameTaps ? 0.0f : ((u >= 0 && u <= 2 * K) ? tp.g[u] : 0.0f);
     }
 
     // ---- row pass: wave wv owns columns 16 wv .. 16 wv + 15 of both 16-row halves
@@ -899,10 +901,14 @@ __global__ __launch_bounds__(kStripThreads) void k_filter_strip(FiltArgs a, Taps
             for (int p4 = 0; p4 < G::SC / 4; ++p4) {
                 const int rr = (r0 + 4 * p4) % G::RING;
                 const float4 bv = *reinterpret_cast<const float4*>(cp + rr);
-                acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(tapc[4 * p4 + 0], bv.x, acc[ob], 0, 0, 0);
-                acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(tapc[4 * p4 + 1], bv.y, acc[ob], 0, 0, 0);
-                acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(tapc[4 * p4 + 2], bv.z, acc[ob], 0, 0, 0);
-                acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(tapc[4 * p4 + 3], bv.w, acc[ob], 0, 0, 0);
+                const float t0 = kSameTaps ? tap[4 * p4 + 0] : tapc[4 * p4 + 0];
+                const float t1 = kSameTaps ? tap[4 * p4 + 1] : tapc[4 * p4 + 1];
+                const float t2 = kSameTaps ? tap[4 * p4 + 2] : tapc[4 * p4 + 2];
+                const float t3 = kSameTaps ? tap[4 * p4 + 3] : tapc[4 * p4 + 3];
+                acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(t0, bv.x, acc[ob], 0, 0, 0);
+                acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(t1, bv.y, acc[ob], 0, 0, 0);
+                acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(t2, bv.z, acc[ob], 0, 0, 0);
+                acc[ob] = __builtin_amdgcn_mfma_f32_16x16x4f32(t3, bv.w, acc[ob], 0, 0, 0);
             }
         }
         // acc[ob][v] = output row ys + 32 j + 16 ob + 4 lq + v, column gx
@@ -1024,7 +1030,9 @@ __global__ __launch_bounds__(kStripThreads) void k_filter_strip16(FiltArgs a, Ta
         }
     };
 
-    // taps: B operand of the row pass, A operand of the column pass (8 k per lane and step)
+    // taps: B operand of the row pass, A operand of the column pass (8 k per lane
+    // and step); with no shift and equal k ranges both passes use the same taps
+    constexpr bool kSameTaps = G::KS == G::KC && G::SHIFT == 0;
     vec tap[G::KS], tapc[G::KC];
 #pragma unroll
     for (int st = 0; st < G::KS; ++st)
@@ -1038,7 +1046,7 @@ __global__ __launch_bounds__(kStripThreads) void k_filter_strip16(FiltArgs a, Ta
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int u = 32 * st + 8 * lq + e - li;
-            tapc[st][e] = (T)((u >= 0 && u <= 2 * K) ? tp.g[u] : 0.0f);
+            tapc[st][e] = kSameTaps ? (T)0.0f : (T)((u >= 0 && u <= 2 * K) ? tp.g[u] : 0.0f);
         }
 
     auto row_pass = [&](int bi) {
@@ -1072,7 +1080,7 @@ __global__ __launch_bounds__(kStripThreads) void k_filter_strip16(FiltArgs a, Ta
             for (int st = 0; st < G::KC; ++st) {
                 const int rr = (32 * j + ob * 16 + 32 * st + 8 * lq) % G::RING;
                 const vec bv = *reinterpret_cast<const vec*>(cp + rr);
-                acc[ob] = mfma16<T>(tapc[st], bv, acc[ob]);
+                acc[ob] = mfma16<T>(kSameTaps ? tap[st] : tapc[st], bv, acc[ob]);
             }
         }
         if (gx >= a.W) return;
