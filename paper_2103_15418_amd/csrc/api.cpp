@@ -149,8 +149,8 @@ size_t carve(const lpf_config* c, const Derived& d, char* base, DevBufs* b) {
     b->src_tlast = cv.take<int64_t>(S);
     b->src_tend = cv.take<int64_t>(S);
     b->src_new = cv.take<int32_t>(S);
-    b->list_measured = cv.take<int32_t>(S);
-    b->list_new = cv.take<int32_t>(S);
+    b->list_measured = cv.take<int2>(S);
+    b->list_new = cv.take<int2>(S);
     b->list_ended = cv.take<int32_t>(S);
     b->ring = cv.take<float>(S * c->B * kRing);
     b->ring_t = cv.take<int64_t>(S * kRing);

@@ -60,8 +60,8 @@ struct CatArgs {
     int64_t* src_tlast;
     int64_t* src_tend;
     int32_t* src_new;
-    int32_t* list_measured;
-    int32_t* list_new;
+    int2* list_measured;     // (slot, row << 16 | col): the flux kernel reads one record
+    int2* list_new;
     int32_t* list_ended;
     int64_t* ring_t;
     DevStatus* status;
@@ -742,17 +742,22 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
                     for (int r = 0; r < kRing / 2; ++r) rt[r] = make_longlong2(INT64_MIN, INT64_MIN);
                 }
                 const bool measured = st[i] == kSrcLive || (st[i] == kSrcEnded && te8[i] == t);
-                if (measured) a.list_measured[om++] = sl;
-                if (nw[i] || st[i] == kSrcEnded) {
+                const bool event = nw[i] || st[i] == kSrcEnded;
+                // positions only for the (few) held sources, in one round trip with the event fields
+                const int row = measured || event ? a.src_row[sl] : 0;
+                const int col = measured || event ? a.src_col[sl] : 0;
+                const int pos = (row << 16) | col;
+                if (measured) a.list_measured[om++] = make_int2(sl, pos);
+                if (event) {
                     lpf_source ev;
                     ev.id = a.src_id[sl];
-                    ev.row = a.src_row[sl];
-                    ev.col = a.src_col[sl];
+                    ev.row = row;
+                    ev.col = col;
                     ev.t_first = a.src_tfirst[sl];
                     ev.t_last_det = tl[i];
                     ev.t_end = te8[i];
                     if (nw[i]) {
-                        a.list_new[on] = sl;
+                        a.list_new[on] = make_int2(sl, pos);
                         ev.event = LPF_EVENT_NEW;
                         a.events[on++] = ev;
                     }

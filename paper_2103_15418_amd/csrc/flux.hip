@@ -24,13 +24,12 @@ struct FluxArgs {
     int Tc, B, H, W, kf, T_bf;
     int64_t t, t_start;
     size_t plane;
-    const int32_t* list;      // measured slots
+    const int2* list;         // measured sources (slot, row << 16 | col)
     const int32_t* count;     // their device count
-    const int32_t* list_new;  // slots opened at this step (backward fill)
+    const int2* list_new;     // sources opened at this step (backward fill)
     const int32_t* count_new;
+    int cap;                  // entries the lists can hold
     int flux_blocks;          // blocks [0, flux_blocks) measure, the rest fill backwards
-    const int32_t* src_row;
-    const int32_t* src_col;
     float* ring;
     int64_t* ring_t;
     uint32_t* ring_v;
@@ -93,21 +92,25 @@ __global__ __launch_bounds__(256) void k_flux(FluxArgs a) {
     else backfill_part(a, blockIdx.x - a.flux_blocks, gridDim.x - a.flux_blocks);
 }
 
+// The first entry of each lane is read with the count (used only below it),
+// so a lane's box loads follow after one round trip, not three.
 __device__ void flux_part(const FluxArgs& a, int blk, int nblk) {
+    const int64_t w0 = (int64_t)blk * blockDim.x + threadIdx.x;
     const int n = *a.count;
+    const int2 e0 = w0 / a.B < a.cap ? a.list[w0 / a.B] : make_int2(0, 0);
     const int cs = pmod(a.t, a.Tc);
     const uint32_t rej = a.cache_rej[cs];
     const float* frame = a.cache + (size_t)cs * a.plane;
     const int ri = pmod(a.t, kRing);
     const uint32_t allb = (a.B == 32) ? 0xffffffffu : ((1u << a.B) - 1u);
-    for (int64_t w = (int64_t)blk * blockDim.x + threadIdx.x; w < (int64_t)n * a.B;
-         w += (int64_t)nblk * blockDim.x) {
-        const int s = a.list[w / a.B];
+    for (int64_t w = w0; w < (int64_t)n * a.B; w += (int64_t)nblk * blockDim.x) {
+        const int2 e = w == w0 ? e0 : a.list[w / a.B];
+        const int s = e.x;
         const int b = (int)(w % a.B);
         const float f = ((rej >> b) & 1u)
                             ? 0.0f
-                            : box_max_any(frame + (size_t)b * a.H * a.W, a.H, a.W, a.src_row[s],
-                                          a.src_col[s], a.kf);
+                            : box_max_any(frame + (size_t)b * a.H * a.W, a.H, a.W, e.y >> 16, e.y & 0xffff,
+                                          a.kf);
         a.ring[((size_t)s * a.B + b) * kRing + ri] = f;
         if (b == 0) {
             a.ring_t[(size_t)s * kRing + ri] = a.t;
@@ -122,12 +125,14 @@ __device__ void backfill_part(const FluxArgs& a, int blk, int nblk) {
     // after t, and would alias step t in the ring: the fill stops there
     const int T_eff = a.T_bf < kRing - 1 ? a.T_bf : kRing - 1;
     if (T_eff <= 0) return;
-    const int n = *a.count_new;
     const int64_t per_src = (int64_t)T_eff * a.B;
+    const int64_t w0 = (int64_t)blk * blockDim.x + threadIdx.x;
+    const int n = *a.count_new;
+    const int2 e0 = w0 / per_src < a.cap ? a.list_new[w0 / per_src] : make_int2(0, 0);
     const uint32_t allb = (a.B == 32) ? 0xffffffffu : ((1u << a.B) - 1u);
-    for (int64_t w = (int64_t)blk * blockDim.x + threadIdx.x; w < (int64_t)n * per_src;
-         w += (int64_t)nblk * blockDim.x) {
-        const int s = a.list_new[w / per_src];
+    for (int64_t w = w0; w < (int64_t)n * per_src; w += (int64_t)nblk * blockDim.x) {
+        const int2 e = w == w0 ? e0 : a.list_new[w / per_src];
+        const int s = e.x;
         const int rem = (int)(w % per_src);
         const int d = rem / a.B, b = rem % a.B;
         const int64_t tau = a.t - T_eff + d;
@@ -138,8 +143,8 @@ __device__ void backfill_part(const FluxArgs& a, int blk, int nblk) {
         const float* frame = a.cache + (size_t)cs * a.plane;
         const float f = ((rej >> b) & 1u)
                             ? 0.0f
-                            : box_max_any(frame + (size_t)b * a.H * a.W, a.H, a.W, a.src_row[s],
-                                          a.src_col[s], a.kf);
+                            : box_max_any(frame + (size_t)b * a.H * a.W, a.H, a.W, e.y >> 16, e.y & 0xffff,
+                                          a.kf);
         const int ri = pmod(tau, kRing);
         a.ring[((size_t)s * a.B + b) * kRing + ri] = f;
         if (b == 0) {
@@ -300,8 +305,6 @@ hipError_t launch_flux(lpf_ctx* c, int slot, int64_t t) {
     a.t = t;
     a.t_start = c->t_start;
     a.plane = c->d.plane;
-    a.src_row = c->buf.src_row;
-    a.src_col = c->buf.src_col;
     a.ring = c->buf.ring;
     a.ring_t = c->buf.ring_t;
     a.ring_v = c->buf.ring_v;
@@ -309,6 +312,7 @@ hipError_t launch_flux(lpf_ctx* c, int slot, int64_t t) {
     a.count = &c->buf.status->n_measured;
     a.list_new = c->buf.list_new;
     a.count_new = &c->buf.status->n_new;
+    a.cap = c->cfg.max_sources;
     a.flux_blocks = 128;
     hipLaunchKernelGGL(k_flux, dim3(a.T_bf > 0 ? 384 : 128), dim3(256), 0, c->stream, a);
     return hipGetLastError();

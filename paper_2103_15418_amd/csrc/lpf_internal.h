@@ -107,8 +107,8 @@ struct DevBufs {
     int64_t* src_tlast;
     int64_t* src_tend;
     int32_t* src_new;      // 1 if opened this step
-    int32_t* list_measured;  // [max_sources]
-    int32_t* list_new;
+    int2* list_measured;     // [max_sources] (slot, row << 16 | col)
+    int2* list_new;          // [max_sources] (slot, row << 16 | col)
     int32_t* list_ended;
     // rings
     float* ring;           // [S][B][64]
