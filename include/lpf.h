@@ -236,9 +236,9 @@ int lpf_infer_windows(const lpf_model* model, const float* windows, int32_t n, f
  * the ticket: on the context's own stream when n_ctx is 1, else on the
  * model's stream), the network runs on the model's stream and the results
  * are copied into a pinned host slot; nothing waits.  For one context with
- * pipeline_ingest = 1 the network is launched after the filters of that
- * context's next lpf_detect (beside its catalogue), or by lpf_infer_collect
- * or lpf_destroy of the context if those come first.  Each context's later
+ * pipeline_ingest = 1 the network is launched after the centre pass of that
+ * context's next lpf_detect (beside its spread pass and catalogue), or by
+ * lpf_infer_collect or lpf_destroy of the context if those come first.  Each context's later
  * work is ordered after the gather, so the caller may ingest the next frame
  * at once.  *ticket
  * identifies the results for lpf_infer_collect.  At most 4 tickets may be

@@ -338,6 +338,7 @@ int lpf_create(const lpf_config* cfg, void* ws, size_t bytes, void* stream, lpf_
         e = hipStreamCreateWithFlags(&c->ing_stream, hipStreamNonBlocking);   // default priority
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_filt, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_qc, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_centre, hipEventDisableTiming);
     }
     if (e == hipSuccess && (d.masked || cfg->pipeline_ingest)) {
         // mask copy is from pageable host memory, and a pipelined ingest is
@@ -368,6 +369,7 @@ void lpf_destroy(lpf_ctx* c) {
     if (c->ev_ready) (void)hipEventDestroy(c->ev_ready);
     if (c->ev_filt) (void)hipEventDestroy(c->ev_filt);
     if (c->ev_qc) (void)hipEventDestroy(c->ev_qc);
+    if (c->ev_centre) (void)hipEventDestroy(c->ev_centre);
     if (c->ing_stream) (void)hipStreamDestroy(c->ing_stream);
     delete c;
 }
@@ -433,11 +435,12 @@ int lpf_detect(lpf_ctx* c, lpf_peak* peaks, int32_t cap, int32_t* n_peaks, lpf_s
     LPF_HIP(c, launch_filters(c, slot), "filters");
     if (c->ing_stream) {
         // the next ingest may start now: it writes a cache slot nothing of
-        // this step reads, and state the catalogue and flux do not touch;
-        // so may the network of the previous step's ticket
+        // this step reads, and state the catalogue and flux do not touch
         LPF_HIP(c, hipEventRecord(c->ev_filt, c->stream), "event record");
         c->filt_recorded = true;
-        const int rc = flush_pending(c, c->ev_filt);
+        // the network of the previous step's ticket runs beside this step's
+        // spread pass and catalogue (launched after the centre pass)
+        const int rc = flush_pending(c, c->ev_centre);
         if (rc != LPF_OK) return rc;
     }
     {

@@ -1345,6 +1345,7 @@ hipError_t launch_filters(lpf_ctx* c, int slot) {
         e = c->d.strip ? dispatch_strip<IN_MX, OUT_C_E>(c, a, B) : dispatch_k<IN_MX, OUT_C_STATIC>(c, a, B);
         if (e != hipSuccess) return e;
     }
+    if (c->ev_centre && (e = hipEventRecord(c->ev_centre, c->stream)) != hipSuccess) return e;
     StageTimer tm3(c, 3);
     a = base_args(c, slot);
     if (iters == 1) {

@@ -162,9 +162,10 @@ struct lpf_ctx {
     // step's filters (ev_filt); the next detect waits for the QC (ev_qc)
     hipStream_t ing_stream = nullptr;
     hipEvent_t ev_filt = nullptr, ev_qc = nullptr;
+    hipEvent_t ev_centre = nullptr;   // after this step's centre pass (deferred network launch)
     bool filt_recorded = false, qc_pending = false;
     // pipelined: a gathered inference ticket whose network launch waits for
-    // this context's next filters (or its collect)
+    // this context's next centre pass (or its collect)
     lpf_model* pend_model = nullptr;
     int pend_slot = -1;
 };
