@@ -291,9 +291,9 @@ def main():
 
         def step(t):
             # the network's results of step t are collected during step t + 2
-            # (a pipelined context launches that network after the filters of
-            # step t + 1), so the host enqueues the next frame while the device
-            # finishes
+            # (a pipelined context launches that network after the centre pass
+            # of step t + 1), so the host enqueues the next frame while the
+            # device finishes
             ctx.ingest(t, frames[t % len(frames)])
             ctx.detect(want=False)
             ctx.extract_flux()
