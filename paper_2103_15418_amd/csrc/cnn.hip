@@ -674,6 +674,8 @@ void model_destroy(lpf_model* m) {
     if (m->istream) (void)hipStreamSynchronize(m->istream);
     for (int i = 0; i < kInflight; ++i) {
         if (m->pend_ctx[i]) {   // a deferred launch that will not happen: its ticket dies with the model
+            // its gather (on the context's stream) still writes this model's buffers
+            if (m->ev_gath[i]) (void)hipEventSynchronize(m->ev_gath[i]);
             m->pend_ctx[i]->pend_model = nullptr;
             m->pend_ctx[i]->pend_slot = -1;
         }

@@ -140,3 +140,36 @@ def test_deferred_network_launch_flushed_by_destroy():
     assert len(src_a) > 0
     assert src_a.tobytes() == src_b.tobytes()
     assert mu_a.tobytes() == mu_b.tobytes() and L_a.tobytes() == L_b.tobytes()
+
+
+def test_model_destroyed_with_deferred_ticket():
+    """A model destroyed while a pipelined context still holds its deferred
+    ticket: the context goes on (its next detect launches nothing of the
+    model) and a new model's results equal the sequential context's."""
+    torch = _torch_cuda()
+    from paper_2103_15418_amd import Context, Model
+    T = 16
+    st = _stream(T)
+    dev = [torch.from_numpy(f).cuda() for f in _frames(st, T)]
+    torch.cuda.synchronize()
+    wts = synth.cnn_weights(seed=3)
+    out = []
+    for pipelined in (0, 1):
+        ctx = Context(8, 192, 192, sky_mask=st.mask, pipeline_ingest=pipelined, **PARAMS)
+        for t in range(12):
+            ctx.ingest(t, dev[t])
+            ctx.detect(want=False)
+            ctx.extract_flux()
+        doomed = Model(wts, max_batch=32)
+        doomed.infer_async([ctx])
+        doomed.__del__()        # lpf_model_destroy with the ticket deferred
+        for t in range(12, T):
+            ctx.ingest(t, dev[t])
+            ctx.detect(want=False)
+            ctx.extract_flux()
+        model = Model(wts, max_batch=32)
+        out.append((model.collect(model.infer_async([ctx])), ctx.status()))
+    (r_a, s_a), (r_b, s_b) = out
+    assert s_a == s_b
+    for x, y in zip(r_a, r_b):
+        assert x.tobytes() == y.tobytes()
