@@ -391,52 +391,81 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
     }
     __syncthreads();
 
-    // ---- 3. duplicate removal: neighbour lists, then greedy resolution.
-    // nbr[q] = {count, up to kNbr earlier-visited peaks within dup_radius};
-    // held in LDS (the sort-key area) for steps with at most kLdsPeaks peaks.
-    int32_t* nbr = P <= kLdsPeaks ? reinterpret_cast<int32_t*>(s_keys) : a.nbr;
-    for (int q = tid; q < P; q += kCatThreads) {
-        const int pq = s_pos[q];
-        int32_t* nb = nbr + (size_t)q * (kNbr + 1);
-        int cnt = 0;
-        for (int r = 0; r < q; ++r) {
-            if (dist2(pq, s_pos[r]) <= a.r_dup2) {
-                if (cnt < kNbr) nb[1 + cnt] = r;
-                ++cnt;
+    // ---- 3. duplicate removal: a peak is kept unless an earlier-visited kept
+    // peak lies within dup_radius.  Up to 64 peaks: wave 0 holds one peak per
+    // lane, builds each lane's 64-bit mask of earlier neighbours from
+    // positions read lane by lane, and resolves the greedy order with one
+    // mask test per peak.  More peaks: neighbour lists, then the greedy pass
+    // on one lane.
+    if (P <= 64) {
+        if (tid < 64) {
+            const int q = tid;
+            const int pq = q < P ? s_pos[q] : 0;
+            uint64_t nbm = 0ull;
+            for (int r = 0; r < P; ++r) {   // uniform
+                const int pr = __builtin_amdgcn_readlane(pq, r);
+                if (r < q && dist2(pq, pr) <= a.r_dup2) nbm |= 1ull << r;
             }
+            const uint32_t nlo = (uint32_t)nbm, nhi = (uint32_t)(nbm >> 32);
+            uint64_t kept = 0ull;
+            for (int j = 0; j < P; ++j) {   // uniform: the greedy order
+                const uint64_t m = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)nhi, j) << 32) |
+                                   (uint32_t)__builtin_amdgcn_readlane((int)nlo, j);
+                if ((m & kept) == 0ull) kept |= 1ull << j;
+            }
+            if (q < P) s_flag[q] = (uint8_t)((kept >> q) & 1ull);
+            if (q < P && ((kept >> q) & 1ull))   // kept list in visiting order
+                a.kept[__popcll(kept & ((1ull << q) - 1ull))] = q;
+            if (q == 0) s_K = __popcll(kept);
         }
-        nb[0] = cnt;
-    }
-    __syncthreads();
-    // A peak without an earlier neighbour is kept whatever the others do: mark
-    // those in parallel; the greedy pass visits only peaks with neighbours.
-    for (int q = tid; q < P; q += kCatThreads) s_flag[q] = nbr[(size_t)q * (kNbr + 1)] == 0 ? 1 : 2;
-    __syncthreads();
-    if (tid == 0) {
-        int K = 0;
-        for (int q = 0; q < P; ++q) {
-            if (s_flag[q] == 1) {
-                ++K;
-                continue;
+        __syncthreads();
+    } else {
+        // nbr[q] = {count, up to kNbr earlier-visited peaks within dup_radius};
+        // held in LDS (the sort-key area) for steps with at most kLdsPeaks peaks.
+        int32_t* nbr = P <= kLdsPeaks ? reinterpret_cast<int32_t*>(s_keys) : a.nbr;
+        for (int q = tid; q < P; q += kCatThreads) {
+            const int pq = s_pos[q];
+            int32_t* nb = nbr + (size_t)q * (kNbr + 1);
+            int cnt = 0;
+            for (int r = 0; r < q; ++r) {
+                if (dist2(pq, s_pos[r]) <= a.r_dup2) {
+                    if (cnt < kNbr) nb[1 + cnt] = r;
+                    ++cnt;
+                }
             }
-            const int32_t* nb = nbr + (size_t)q * (kNbr + 1);
-            const int cnt = nb[0];
-            bool keep = true;
-            if (cnt > kNbr) {  // long list: test every earlier peak that was kept
-                for (int r = 0; r < q && keep; ++r)
-                    if (s_flag[r] == 1 && dist2(s_pos[q], s_pos[r]) <= a.r_dup2) keep = false;
-            } else {
-                for (int r = 0; r < cnt && keep; ++r)
-                    if (s_flag[nb[1 + r]] == 1) keep = false;
-            }
-            s_flag[q] = keep ? 1 : 0;
-            K += keep;
+            nb[0] = cnt;
         }
-        s_K = K;
+        __syncthreads();
+        // A peak without an earlier neighbour is kept whatever the others do: mark
+        // those in parallel; the greedy pass visits only peaks with neighbours.
+        for (int q = tid; q < P; q += kCatThreads) s_flag[q] = nbr[(size_t)q * (kNbr + 1)] == 0 ? 1 : 2;
+        __syncthreads();
+        if (tid == 0) {
+            int K = 0;
+            for (int q = 0; q < P; ++q) {
+                if (s_flag[q] == 1) {
+                    ++K;
+                    continue;
+                }
+                const int32_t* nb = nbr + (size_t)q * (kNbr + 1);
+                const int cnt = nb[0];
+                bool keep = true;
+                if (cnt > kNbr) {  // long list: test every earlier peak that was kept
+                    for (int r = 0; r < q && keep; ++r)
+                        if (s_flag[r] == 1 && dist2(s_pos[q], s_pos[r]) <= a.r_dup2) keep = false;
+                } else {
+                    for (int r = 0; r < cnt && keep; ++r)
+                        if (s_flag[nb[1 + r]] == 1) keep = false;
+                }
+                s_flag[q] = keep ? 1 : 0;
+                K += keep;
+            }
+            s_K = K;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     const int K = s_K;
-    {   // kept list in visiting order (parallel compaction)
+    if (P > 64) {   // kept list in visiting order (parallel compaction)
         const int per = (P + kCatThreads - 1) / kCatThreads;
         const int q0 = tid * per, q1 = min(P, q0 + per);
         int nk = 0;
