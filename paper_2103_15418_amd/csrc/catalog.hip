@@ -373,12 +373,17 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
     __syncthreads();
     if (P > 1) sort_keys(s_keys, Ppad);
     // copy in (band, row, col) order; the same lane writes the visiting-order
-    // key of position n (x descending, then rank n); padding keys stay ~0
+    // key of position n (x descending, then rank n); padding keys stay ~0.
+    // Positions also go to LDS (the candidate-list area, free until phase 4b)
+    // when they fit, so the visiting order needs no read of the copy.
+    int32_t* s_npos = s_cand;
+    const bool pos_lds = P <= kLdsKept * (kCand + 1);
     for (int n = tid; n < P; n += kCatThreads) {
         const uint32_t ref = (uint32_t)(s_keys[n] & 0xffffffffu);
         const PeakRec rec = a.peak_raw[ref];
         a.peak_sorted[n] = rec;
         s_keys[n] = ((uint64_t)(~ordered(rec.x)) << 32) | (uint32_t)n;
+        if (pos_lds) s_npos[n] = pack_pos(rec.row, rec.col);
     }
     __syncthreads();
 
@@ -387,7 +392,7 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
     for (int q = tid; q < P; q += kCatThreads) {
         const int n = (int)(s_keys[q] & 0xffffffffu);
         a.order[q] = n;
-        s_pos[q] = pack_pos(a.peak_sorted[n].row, a.peak_sorted[n].col);
+        s_pos[q] = pos_lds ? s_npos[n] : pack_pos(a.peak_sorted[n].row, a.peak_sorted[n].col);
     }
     __syncthreads();
 
