@@ -44,7 +44,8 @@ def test_config_validation_host_only():
     for bad in (dict(B=17), dict(B=0), dict(H=5000), dict(ring_len=32), dict(clip_iters=0),
                 dict(peak_cap=600), dict(bg_halfwidth=41), dict(filter_precision=3),
                 dict(filter_precision=1, clip_iters=2), dict(filter_precision=2, bg_halfwidth=10),
-                dict(max_sources=0), dict(peak_halfwidth=0)):
+                dict(max_sources=0), dict(peak_halfwidth=0), dict(pipeline_ingest=2),
+                dict(pipeline_ingest=-1), dict(kappa=-1.0)):
         c = P.default_config(16, 1024, 1024)
         for k, v in bad.items():
             setattr(c, k, v)
@@ -76,3 +77,16 @@ def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(A, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         A.lib()
+
+
+def test_pipelined_ingest_holds_one_cube_more():
+    """With the pipelined ingest the image cache holds backfill + 2 cubes (the
+    next step is written while this one is measured): exactly one cube more."""
+    import paper_2103_15418_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("library not built")
+    for B, H, W in ((16, 1024, 1024), (4, 96, 80)):
+        seq = P.workspace_size(P.default_config(B, H, W))
+        pip = P.workspace_size(P.default_config(B, H, W, pipeline_ingest=1))
+        cube = B * H * W * 4
+        assert cube <= pip - seq <= cube + 256
