@@ -6,8 +6,8 @@ is linear.  The network maps a dynamic spectrum to [mu ; L], where L is a
 lower-triangular matrix with positive diagonal (a Cholesky factor, so
 Sigma = L L^T is a valid covariance).
 
-Architecture (the paper gives none; these sizes are the ones this build
-serves): input 1 x 16 x 64; four 3x3 convolutions, stride 1, zero padding 1,
+Architecture (the paper gives none; these are the sizes the network kernels
+serve): input 1 x 16 x 64; four 3x3 convolutions, stride 1, zero padding 1,
 1->32->32->64->64 channels, each followed by phi; flatten in (channel, row,
 column) order; dense 65536->128 with phi; dense 128->14.  Outputs 0..3 are
 mu (DM, width, amplitude, arrival); outputs 4..13 fill L row by row
