@@ -73,30 +73,63 @@ __device__ inline int batch_n(const int* n_dev, int n_cap) {
 }
 
 // conv1: x [n][16][64] -> out [n][16][64][32]
+// First convolution (1 -> 32 channels, 3x3, pad 1): one lane per output pixel
+// loads the pixel's 3 x 3 neighbourhood once and computes all 32 channels,
+// the weights and biases being wave-uniform values, then writes the pixel's
+// 32 outputs (contiguous in NHWC) as 16-byte vectors.  Per channel the sum
+// runs over (kh, kw) in order starting from the bias.
+template <typename TO>
+__device__ inline void conv1_pixel(const float* __restrict__ x, const float* __restrict__ w,
+                                   const float* __restrict__ bias, TO* __restrict__ out, int64_t pix,
+                                   float alpha) {
+    const int col = (int)(pix % kGW);
+    const int row = (int)((pix / kGW) % kGH);
+    const int64_t n = pix / (kGW * kGH);
+    const float* xi = x + n * kGH * kGW;
+    float xv[9];
+    bool ok[9];
+#pragma unroll
+    for (int kh = 0; kh < 3; ++kh)
+#pragma unroll
+        for (int kw = 0; kw < 3; ++kw) {
+            const int r = row + kh - 1, q = col + kw - 1;
+            const bool in = r >= 0 && r < kGH && q >= 0 && q < kGW;
+            ok[kh * 3 + kw] = in;
+            xv[kh * 3 + kw] = in ? xi[r * kGW + q] : 0.0f;
+        }
+    float acc[32];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) acc[c] = bias[c];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        if (!ok[t]) continue;
+#pragma unroll
+        for (int c = 0; c < 32; ++c) acc[c] = fmaf(w[t * 32 + c], xv[t], acc[c]);
+    }
+    TO* o = out + pix * 32;
+    if constexpr (sizeof(TO) == 4) {
+#pragma unroll
+        for (int c = 0; c < 32; c += 4)
+            *reinterpret_cast<float4*>(o + c) = make_float4(act_fn(acc[c], alpha), act_fn(acc[c + 1], alpha),
+                                                            act_fn(acc[c + 2], alpha), act_fn(acc[c + 3], alpha));
+    } else {
+        typedef TO vec __attribute__((ext_vector_type(8)));
+#pragma unroll
+        for (int c = 0; c < 32; c += 8) {
+            vec v;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = (TO)act_fn(acc[c + e], alpha);
+            *reinterpret_cast<vec*>(o + c) = v;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_conv1(const float* __restrict__ x, const float* __restrict__ w,
                                                const float* __restrict__ bias, float* __restrict__ out,
                                                const int* __restrict__ n_dev, int n_cap, float alpha) {
-    const int64_t total = (int64_t)batch_n(n_dev, n_cap) * kGH * kGW * 32;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % 32);
-        const int64_t pix = i / 32;
-        const int col = (int)(pix % kGW);
-        const int row = (int)((pix / kGW) % kGH);
-        const int64_t n = pix / (kGW * kGH);
-        const float* xi = x + n * kGH * kGW;
-        float acc = bias[c];
-        for (int kh = 0; kh < 3; ++kh) {
-            const int r = row + kh - 1;
-            if (r < 0 || r >= kGH) continue;
-            for (int kw = 0; kw < 3; ++kw) {
-                const int q = col + kw - 1;
-                if (q < 0 || q >= kGW) continue;
-                acc = fmaf(w[(kh * 3 + kw) * 32 + c], xi[r * kGW + q], acc);
-            }
-        }
-        out[i] = act_fn(acc, alpha);
-    }
+    const int64_t npix = (int64_t)batch_n(n_dev, n_cap) * kGH * kGW;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x)
+        conv1_pixel<float>(x, w, bias, out, p, alpha);
 }
 
 // conv (Cin -> Cout), 3x3, pad 1, on MFMA f32 32x32x2.
@@ -232,27 +265,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_conv1_16(const float* __restrict__ x, const float* __restrict__ w,
                                                   const float* __restrict__ bias, T* __restrict__ out,
                                                   const int* __restrict__ n_dev, int n_cap, float alpha) {
-    const int64_t total = (int64_t)batch_n(n_dev, n_cap) * kGH * kGW * 32;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(i % 32);
-        const int64_t pix = i / 32;
-        const int col = (int)(pix % kGW);
-        const int row = (int)((pix / kGW) % kGH);
-        const int64_t n = pix / (kGW * kGH);
-        const float* xi = x + n * kGH * kGW;
-        float acc = bias[c];
-        for (int kh = 0; kh < 3; ++kh) {
-            const int r = row + kh - 1;
-            if (r < 0 || r >= kGH) continue;
-            for (int kw = 0; kw < 3; ++kw) {
-                const int q = col + kw - 1;
-                if (q < 0 || q >= kGW) continue;
-                acc = fmaf(w[(kh * 3 + kw) * 32 + c], xi[r * kGW + q], acc);
-            }
-        }
-        out[i] = (T)act_fn(acc, alpha);
-    }
+    const int64_t npix = (int64_t)batch_n(n_dev, n_cap) * kGH * kGW;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (int64_t)gridDim.x * blockDim.x)
+        conv1_pixel<T>(x, w, bias, out, p, alpha);
 }
 
 // conv Cin -> Cout on v_mfma_f32_32x32x16_{bf16,f16}: a lane feeds 8 consecutive
@@ -504,7 +519,7 @@ hipError_t forward16(const lpf_model* m, const float* windows, const int* n_dev,
     T* a = static_cast<T*>(w.act16_a);
     T* b = static_cast<T*>(w.act16_b);
     const GridCaps gc(n_dev);
-    hipLaunchKernelGGL((k_conv1_16<T>), dim3(grid_cap(((int64_t)n_cap * kGH * kGW * 32 + 255) / 256, gc.conv1)),
+    hipLaunchKernelGGL((k_conv1_16<T>), dim3(grid_cap(((int64_t)n_cap * kGH * kGW + 255) / 256, gc.conv1)),
                        dim3(256), 0, s, windows, W + lay.w1, W + lay.b1, a, n_dev, n_cap, m->alpha);
     hipLaunchKernelGGL((k_conv16<T, 32, 32>), dim3(grid_cap((int64_t)n_cap * (kGH / 2), gc.conv)), dim3(256), 0, s,
                        a, w16 + kW16o2, W + lay.b2, b, n_dev, n_cap, m->alpha);
@@ -533,7 +548,7 @@ hipError_t cnn_forward(const lpf_model* m, const float* windows, const int* n_de
     } else if (m->precision == LPF_PREC_FP16) {
         e = forward16<_Float16>(m, windows, n_dev, n_cap, s);
     } else {
-        hipLaunchKernelGGL(k_conv1, dim3(grid_cap(((int64_t)n_cap * kGH * kGW * 32 + 255) / 256, gc.conv1)),
+        hipLaunchKernelGGL(k_conv1, dim3(grid_cap(((int64_t)n_cap * kGH * kGW + 255) / 256, gc.conv1)),
                            dim3(256), 0, s, windows, W + lay.w1, W + lay.b1, w.act_a, n_dev, n_cap, m->alpha);
         hipLaunchKernelGGL((k_conv_mfma<32, 32>), dim3(grid_cap((int64_t)n_cap * (kGH / 2), gc.conv)), dim3(256),
                            0, s, w.act_a, W + lay.w2, W + lay.b2, w.act_b, n_dev, n_cap, m->alpha);
