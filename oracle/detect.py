@@ -21,8 +21,12 @@ import numpy as np
 from .filters import centre_spread
 
 
-def sigma_clip(X: np.ndarray, M: np.ndarray, g: np.ndarray, kappa: float, n_iter: int):
-    """Returns (Y, C, S, den, iterations_run); C, S, den from the last iteration."""
+def sigma_clip(X: np.ndarray, M: np.ndarray, g: np.ndarray, kappa: float, n_iter: int,
+               trace: list = None):
+    """Returns (Y, C, S, den, iterations_run); C, S, den from the last iteration.
+
+    trace (optional list): receives (Y_before, C, S, den) of every iteration
+    run, for inspection; it does not change the result."""
     X = np.asarray(X, dtype=np.float64)
     M = np.asarray(M, dtype=bool)
     Y = np.zeros(X.shape, dtype=bool)
@@ -31,6 +35,8 @@ def sigma_clip(X: np.ndarray, M: np.ndarray, g: np.ndarray, kappa: float, n_iter
     for it in range(1, max(1, n_iter) + 1):
         Wt = M & ~Y
         C, S, den = centre_spread(X, Wt, g)
+        if trace is not None:
+            trace.append((Y, C, S, den))
         Ynew = Y | (M & (den > 0.0) & (X > C + kappa * np.sqrt(S)))
         changed = bool((Ynew != Y).any())
         Y = Ynew

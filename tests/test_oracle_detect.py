@@ -136,6 +136,63 @@ def test_clip_iterations_accumulate_and_stop():
     assert np.array_equal(Ynext, Y3)
 
 
+def read_golden_iters(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                n, k, j, v = line.split()
+                rows.append((int(n), k, int(j), float(v)))
+    return rows
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_golden_two_clip_iterations(transpose):
+    """Hand-derived repeated clipping (tests/golden/box3_two_clip_iterations.txt):
+    a pixel is clipped only in the second iteration, once its bright neighbour
+    has left the statistics; the loop stops when the mask repeats.  The
+    transposed image (one column) must give the transposed result."""
+    X = np.zeros((1, 9), dtype=np.float32)
+    X[0, 4], X[0, 5] = 12.0, 3.0
+    M = np.ones((1, 9), dtype=bool)
+    if transpose:
+        X, M = X.T.copy(), M.T.copy()
+    g = taps_1d(KERNEL_BOX, 0.0, 1)
+    runs = {}
+    for n in (1, 2, 5):
+        trace = []
+        Y, C, S, den, it = sigma_clip(X, M, g, 1.0, n, trace=trace)
+        assert len(trace) == it
+        if transpose:
+            Y, C, S = Y.T, C.T, S.T
+        runs[n] = dict(Y=Y[0], C=C[0], S=S[0], RUN=it)
+        # the peak map does not depend on the number of iterations here
+        recs = band_peaks(0, X, M, g, 1.0, n, 3)[0]
+        assert [(r[1], r[2]) for r in recs] == ([(4, 0)] if transpose else [(0, 4)])
+    for n, key, j, v in read_golden_iters("box3_two_clip_iterations.txt"):
+        got = runs[n][key] if key == "RUN" else runs[n][key][j]
+        assert abs(float(got) - v) < 1e-12, (n, key, j, float(got), v)
+
+
+def test_clip_reading_excludes_rather_than_replaces():
+    """The reading of "clip" (excluded from the next iteration's statistics)
+    differs from the alternative (clipped values replaced by their centre) on
+    the hand-derived example: with replacement, pixel 5 of the golden row is
+    not clipped in iteration 2 (C5 = (5 + 3 + 0)/3, S5 from x4 := 5)."""
+    X = np.zeros((1, 9), dtype=np.float32)
+    X[0, 4], X[0, 5] = 12.0, 3.0
+    M = np.ones((1, 9), dtype=bool)
+    g = taps_1d(KERNEL_BOX, 0.0, 1)
+    Y2 = sigma_clip(X, M, g, 1.0, 2)[0]
+    assert Y2[0, 5]
+    # the alternative, written out: iteration 2 on x with x4 replaced by C4 = 5
+    Xr = X.astype(np.float64).copy()
+    Xr[0, 4] = 5.0
+    C, S, den = centre_spread(Xr, M, g)
+    assert not (Xr[0, 5] > C[0, 5] + np.sqrt(S[0, 5]))
+
+
 def test_peak_records_sig():
     X = np.zeros((40, 40), dtype=np.float32)
     rng = np.random.default_rng(1)
