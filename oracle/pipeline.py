@@ -67,11 +67,12 @@ class OracleStream:
         return rej
 
     # -- step 2 + 3: detection, association (Sec. 2.1, 2.2) ------------------------------
-    def detect(self):
+    def find_peaks(self):
+        """Peak records of every accepted band of the current step (Sec. 2.1),
+        and the bitmask of bands whose list exceeded peak_cap (dropped whole)."""
         c = self.cfg
-        t = self.t
-        X = self.cache[t]
-        rej = self.rejected[t]
+        X = self.cache[self.t]
+        rej = self.rejected[self.t]
         peaks: List[tuple] = []
         overflow = 0
         for b in range(c.B):
@@ -82,10 +83,18 @@ class OracleStream:
                 overflow |= 1 << b   # a band with too many peaks is dropped whole
                 continue
             peaks.extend(recs)
-        new_ids, ended_ids, measured, dropped = self.catalog.step(t, peaks)
+        return peaks, overflow
+
+    def associate(self, peaks: List[tuple], overflow: int = 0):
+        """Duplicate removal, association and monitoring (Sec. 2.2) of a peak
+        list of the current step."""
+        new_ids, ended_ids, measured, dropped = self.catalog.step(self.t, peaks)
         self.last.update(peaks=peaks, new=new_ids, ended=ended_ids, measured=measured,
                          dropped=dropped, overflow=overflow)
         return peaks, new_ids, ended_ids
+
+    def detect(self):
+        return self.associate(*self.find_peaks())
 
     # -- step 4: flux + backward fill (Sec. 2.2) ------------------------------------------
     def extract_flux(self):

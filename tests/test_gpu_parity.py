@@ -8,7 +8,7 @@ import synth
 from oracle import cnn as ocnn
 from oracle.filters import taps_1d
 
-from parity import check_peaks_bracket, check_planes, cnn_scale, make_pair
+from parity import check_centre_sampled, check_welford, cnn_scale, make_pair, run_steps
 
 pytestmark = pytest.mark.gpu
 
@@ -22,75 +22,6 @@ def _torch_cuda():
 
 def _log(msg):
     print(msg, flush=True)
-
-
-def run_steps(ctx, orc, frames, ts, compare_planes=False, label=""):
-    """Runs both paths over the frames; compares QC, peaks, events and spectra
-    every step while the peak lists agree exactly.  Returns stats."""
-    stats = dict(steps=0, exact_steps=0, excused=0, events=0, spectra=0)
-    synced = True
-    g = orc.g
-    M = orc.M
-    for t, cube in zip(ts, frames):
-        _log(f"{label} step t={t}")
-        rej_o = orc.ingest(t, cube)
-        rej_d = ctx.ingest(t, cube, want_rejected=True)
-        bs = ctx.debug_read("bandstats")
-        L = orc.last
-        for b in range(ctx.B):
-            if not np.isfinite(L["rms"][b]):
-                assert bs[b, 5] > 0 and (rej_d >> b & 1), (t, b)   # non-finite band: counted, rejected
-                continue
-            assert abs(bs[b, 0] - L["mean"][b]) <= 1e-12 * max(1.0, abs(L["rms"][b])), (t, b)
-            assert abs(bs[b, 1] - L["rms"][b]) <= 1e-12 * max(1.0, L["rms"][b]), (t, b)
-        if rej_o != rej_d:
-            # allowed only when a score sits within 1e-5 of its threshold
-            c = orc.cfg
-            for b in range(ctx.B):
-                if (rej_o ^ rej_d) >> b & 1:
-                    near = (abs(abs(L["z_mean"][b]) - c.qc_band_z) <= 1e-5 * c.qc_band_z
-                            or abs(abs(L["z_rms"][b]) - c.qc_rms_z) <= 1e-5 * c.qc_rms_z
-                            or abs(L["zeta"][b] - c.qc_pixel_zeta) <= 1e-5 * c.qc_pixel_zeta)
-                    assert near, (t, b, rej_o, rej_d)
-            synced = False
-        peaks_o, new_o, ended_o = orc.detect()
-        pd, ev, rc = ctx.detect()
-        X = orc.cache[t]
-        if compare_planes:
-            check_planes(ctx.debug_read("centre"), ctx.debug_read("spread"), X, M, g, rej_o, label)
-        stats["excused"] += check_peaks_bracket(pd, X, M, g, orc.cfg.kappa, orc.cfg.k_peak, rej_o,
-                                                f"{label} t={t}")
-        same = sorted((int(p["band"]), int(p["row"]), int(p["col"])) for p in pd) == \
-            sorted((p[0], p[1], p[2]) for p in peaks_o)
-        if not same:
-            synced = False
-        orc.extract_flux()
-        ctx.extract_flux()
-        stats["steps"] += 1
-        if not synced:
-            continue
-        stats["exact_steps"] += 1
-        # events: new (id order) then ended (id order)
-        exp = [(sid, 1) for sid in new_o] + [(sid, 2) for sid in ended_o]
-        got = [(int(e["id"]), int(e["event"])) for e in ev]
-        assert got == exp, (label, t, got[:8], exp[:8])
-        for e in ev:
-            r = orc.catalog.sources[int(e["id"])]
-            assert (int(e["row"]), int(e["col"])) == (r.row, r.col)
-            assert int(e["t_first"]) == r.t_first and int(e["t_last_det"]) == r.t_last_det
-            if e["event"] == 2:
-                assert int(e["t_end"]) == r.t_end
-        stats["events"] += len(ev)
-        # spectra of every held source: bitwise
-        for sid in list(orc.catalog.sources)[:64]:
-            grid, valid = orc.spectrum(sid)
-            out, vd, tl = ctx.read_spectrum(sid)
-            rows = [orc.cfg.grid_row(b) for b in range(ctx.B)]
-            assert np.array_equal(vd, valid), (label, t, sid)
-            exp_vals = np.where(valid, grid[rows, :], 0.0).astype(np.float32)
-            assert np.array_equal(out, exp_vals), (label, t, sid)
-            stats["spectra"] += 1
-    return stats
 
 
 def test_planes_and_peaks_ragged_tiles_with_mask():
@@ -110,7 +41,7 @@ def test_planes_and_peaks_ragged_tiles_with_mask():
         frames.append(cube)
         ts.append(t)
     st = run_steps(ctx, orc, frames, ts, compare_planes=True, label="ragged")
-    assert st["exact_steps"] >= 2
+    assert st["steps"] == 3
 
 
 @pytest.mark.parametrize("kernel,s,k", [(0, 8.0, 0), (0, 3.0, 0), (1, 0.0, 5), (0, 5.0, 15), (0, 12.0, 36)])
@@ -150,6 +81,60 @@ def test_strip_filters_ragged(k, strip_h, monkeypatch):
     run_steps(ctx, orc, frames, [0, 1], compare_planes=True, label=f"strip-k{k}-h{strip_h}")
 
 
+def _clip_frames(rng, B, H, W, mask, n, n_src=14):
+    """Noise with Gaussian blobs (sigma 1.5 px) of 6-30: iteration 1 clips the
+    cores, later iterations the wings that the cores' spread had hidden."""
+    frames = []
+    ii, jj = np.mgrid[0:H, 0:W]
+    for _ in range(n):
+        cube = rng.standard_normal((B, H, W))
+        for _ in range(n_src):
+            b = int(rng.integers(B))
+            ci, cj = rng.uniform(8, H - 8), rng.uniform(8, W - 8)
+            cube[b] += rng.uniform(6.0, 30.0) * np.exp(-((ii - ci) ** 2 + (jj - cj) ** 2) / (2 * 1.5 ** 2))
+        cube = cube.astype(np.float32)
+        if mask is not None:
+            cube *= mask
+        frames.append(cube)
+    return frames
+
+
+@pytest.mark.parametrize("W,k,iters,masked,seed", [(196, 15, 2, True, 1), (201, 9, 3, True, 2),
+                                                   (196, 24, 5, True, 0), (201, 24, 3, False, 0),
+                                                   (200, 36, 2, True, 0)])
+def test_clip_iterations(W, k, iters, masked, seed):
+    """Several sigma-clip iterations (Sec. 2.1.1 repeat, App. C; clipped
+    pixels leave the next iteration's statistics): the clip mask Y, C and S of
+    the last iteration and the peak list P = Q and Y against the oracle's
+    iterations on ragged images with and without a sky mask, the first pass
+    on the strip kernels where W % 4 = 0 and later passes on the tile
+    kernels; events and spectra as every other stream test.  Differences are
+    allowed only in the zones around pixels whose margin lies within 1e-3 of
+    the threshold in some iteration (none for these seeds, so everything is
+    compared).  At five iterations one band stops before the others."""
+    _torch_cuda()
+    rng = np.random.default_rng(1000 * seed + W + k + iters)
+    B, H = 3, 150
+    mask = synth.sky_mask(H, W) if masked else None
+    ctx, orc = make_pair(B, H, W, sky_mask=mask, debug_planes=1, kappa=4.0, bg_halfwidth=k,
+                         bg_sigma=max(k / 3.0, 5.0), clip_iters=iters)
+    frames = _clip_frames(rng, B, H, W, mask, 3)
+    res = run_steps(ctx, orc, frames, [0, 1, 2], label=f"clip-W{W}-k{k}-n{iters}")
+    assert res["steps"] == 3 and res["fragile"] == 0 and res["excused"] == 0, res
+
+
+def test_clip_iterations_tiny_workload():
+    """The tiny workload (4 x 256^2, 16 steps) with three clip iterations at
+    kappa = 4.5: every step compared as in test_tiny_stream_full_pipeline."""
+    _torch_cuda()
+    st = synth.Stream(synth.spec_tiny())
+    s = st.spec
+    ctx, orc = make_pair(s.B, s.H, s.W, debug_planes=1, clip_iters=3)
+    frames = [st.frame(t) for t in range(s.T)]
+    res = run_steps(ctx, orc, frames, list(range(s.T)), label="tiny-clip3")
+    assert res["steps"] == s.T and res["spectra"] > 0, res
+
+
 def test_tiny_stream_full_pipeline():
     """4 subbands x 16 steps of 256^2 (the tiny workload): QC, peaks, events,
     dynamic spectra every step, then the network on the ended episodes."""
@@ -159,64 +144,74 @@ def test_tiny_stream_full_pipeline():
     ctx, orc = make_pair(s.B, s.H, s.W, debug_planes=1)
     frames = [st.frame(t) for t in range(s.T)]
     res = run_steps(ctx, orc, frames, list(range(s.T)), compare_planes=True, label="tiny")
-    assert res["exact_steps"] == s.T
+    assert res["steps"] == s.T and res["resyncs"] == 0
     assert res["spectra"] > 0
 
 
 def test_instrument_scale_sampled_and_lists():
-    """16 x 1024^2 in the circular mask (instrument workload), first steps:
-    QC statistics, Welford state, peak bracketing and events at full size;
-    C and S at sampled pixels computed one by one by the oracle."""
+    """16 x 1024^2 in the circular mask (instrument workload), first steps
+    with the dense oracle: QC statistics and scores, Welford state, peak
+    bracketing, events, spectra; C at sampled pixels."""
     _torch_cuda()
     spec = synth.spec_instrument(T=4)
     st = synth.Stream(spec)
-    ctx, orc = make_pair(spec.B, spec.H, spec.W, sky_mask=st.mask, debug_planes=1)
+    ctx, orc = make_pair(spec.B, spec.H, spec.W, sky_mask=st.mask)
     frames = [st.frame(t) for t in range(spec.T)]
     res = run_steps(ctx, orc, frames, list(range(spec.T)), label="instrument")
-    assert res["exact_steps"] >= 3
-    # Welford state of accepted steps
-    mean_d = ctx.debug_read("welford_mean")
-    m2_d = ctx.debug_read("welford_m2")
-    n = orc.stats.n
-    for b in range(spec.B):
-        ssq = orc.stats.m2[b] + n[b] * orc.stats.mean[b] ** 2
-        rms = np.sqrt(ssq / max(1, n[b]))
-        assert np.all(np.abs(mean_d[b] - orc.stats.mean[b]) <= 1e-5 * rms + 1e-30)
-        assert np.all(np.abs(m2_d[b] - orc.stats.m2[b]) <= 1e-5 * ssq + 1e-30)
-    # sampled C, S of the last step
+    assert res["steps"] == spec.T and res["resyncs"] <= 1
+    check_welford(ctx, orc, "instrument")
     X = orc.cache[spec.T - 1]
-    Cd, Sd = ctx.debug_read("centre"), ctx.debug_read("spread")
-    g = orc.g
-    k = orc.cfg.k_bg
-    rng = np.random.default_rng(7)
-    from oracle.filters import centre_spread
-    for _ in range(24):
-        b = int(rng.integers(spec.B))
-        i, j = int(rng.integers(spec.H)), int(rng.integers(spec.W))
-        r0, r1 = max(0, i - 2 * k), min(spec.H, i + 2 * k + 1)
-        c0, c1 = max(0, j - 2 * k), min(spec.W, j + 2 * k + 1)
-        C, S, den = centre_spread(X[b, r0:r1, c0:c1], orc.M[r0:r1, c0:c1], g)
-        ci, cj = i - r0, j - c0
-        scale = 1.0 + abs(C[ci, cj])
-        assert abs(Cd[b, i, j] - C[ci, cj]) <= 1e-5 * scale
-        assert abs(Sd[b, i, j] - S[ci, cj]) <= 1e-5 * (1.0 + S[ci, cj] + C[ci, cj] ** 2)
+    check_centre_sampled(ctx.debug_read("centre"), X, orc.M, orc.g, orc.cfg.k_bg, orc.rejected[spec.T - 1],
+                         np.random.default_rng(7), n=48, label="instrument")
+
+
+def _qc_stream(T=16, H=256):
+    spec = synth.spec_streaming(T=T, H=H)
+    spec.n_sources = 10
+    spec.rfi_p = 0.1
+    spec.rfi_from_t = 2
+    return synth.Stream(spec)
 
 
 def test_qc_rejects_rfi_and_nonfinite_like_oracle():
-    """Streaming-style RFI (stripes, x5 noise) and a NaN pixel: same band
-    decisions and statistics as the oracle, rejected bands produce no peaks."""
+    """Streaming-style RFI (stripes, x5 noise) from step 2, a NaN pixel at
+    step 5 and, after the pixel test has armed (8 accepted steps), a single
+    +40 pixel in a clean band at step 12 that only the running z catches:
+    the same decisions as the oracle, band mean / RMS at 1e-12, their robust
+    z at 1e-9 and max |zeta| at 1e-5 every step, rejected bands without
+    peaks, Welford state of the accepted steps."""
     _torch_cuda()
-    spec = synth.spec_streaming(T=14, H=256)
-    spec.n_sources = 10
-    spec.rfi_p = 0.15
-    spec.rfi_from_t = 2
-    st = synth.Stream(spec)
-    ctx, orc = make_pair(spec.B, spec.H, spec.W, sky_mask=st.mask, qc_warmup=3)
+    st = _qc_stream()
+    spec = st.spec
+    ctx, orc = make_pair(spec.B, spec.H, spec.W, sky_mask=st.mask, qc_warmup=8)
     frames = [st.frame(t) for t in range(spec.T)]
     frames[5][3, 100, 100] = np.nan
+    zeta_band = next(b for b in range(spec.B) if (12, b) not in st.rfi)
+    frames[12][zeta_band, 128, 130] += 40.0
     res = run_steps(ctx, orc, frames, list(range(spec.T)), label="rfi")
-    assert res["exact_steps"] >= spec.T - 1
-    assert sum(bin(r).count("1") for r in orc.rejected.values()) > 0
+    assert res["steps"] == spec.T, res
+    assert res["zeta_checked"] >= 8 * spec.B // 2, res
+    # every injected RFI band-step rejected; the +40 pixel rejected by zeta alone
+    for t in range(spec.T):
+        assert orc.rejected[t] & st.rfi_mask(t) == st.rfi_mask(t), t
+    check_welford(ctx, orc, "rfi")
+
+
+def test_qc_zeta_alone_rejects():
+    """The pixel test by itself: after warm-up a clean band gains one +40
+    pixel; its band mean and RMS z stay below 5 and its max |zeta| exceeds
+    30, on both sides."""
+    _torch_cuda()
+    rng = np.random.default_rng(17)
+    B, H, W = 6, 128, 128
+    ctx, orc = make_pair(B, H, W, qc_warmup=8)
+    frames = [rng.standard_normal((B, H, W)).astype(np.float32) for _ in range(11)]
+    frames[10][2, 64, 70] += 40.0
+    run_steps(ctx, orc, frames, list(range(11)), label="zeta")
+    L = orc.last
+    assert orc.rejected[10] == 1 << 2
+    assert abs(L["z_mean"][2]) < 5 and abs(L["z_rms"][2]) < 5 and L["zeta"][2] > 30
+    assert ctx.debug_read("bandstats")[2, 4] > 30
 
 
 def test_gap_in_time_and_backfill():
@@ -233,7 +228,7 @@ def test_gap_in_time_and_backfill():
             cube[1, 40, 50] += 25.0
         frames.append(cube)
     res = run_steps(ctx, orc, frames, ts, label="gap")
-    assert res["exact_steps"] == len(ts) and res["events"] >= 2
+    assert res["steps"] == len(ts) and res["events"] >= 2
 
 
 def test_association_conflicts_and_duplicates():
@@ -259,7 +254,7 @@ def test_association_conflicts_and_duplicates():
             cube[1, 21, 22] += 31.0            # duplicate of the previous one (1.4 px)
         frames.append(cube)
     res = run_steps(ctx, orc, frames, ts, label="conflicts")
-    assert res["exact_steps"] == len(ts) and res["events"] >= 5
+    assert res["steps"] == len(ts) and res["events"] >= 5 and res["resyncs"] == 0
 
 
 def test_network_fp32_parity_ragged_batch():

@@ -6,7 +6,8 @@ output (max and median, relative to the same condition scales as the FP32
 tests) and check loose bounds derived from the unit roundoff
 (bf16 u = 2^-8, fp16 u = 2^-11, a few roundings per output):
 filters |err| <= 8u * scale, network |err| <= 16u * scale; and that the 16-bit
-candidate lists agree with FP32 except near the threshold.
+candidate lists agree with FP32 except where the oracle's sig lies within
+that filter bound, carried to sig, of the threshold.
 """
 
 import numpy as np
@@ -53,11 +54,12 @@ def test_filter_planes_16bit_error(prec):
         C, S, den = centre_spread(X, M, g)
         pos = (den > 0) & M
         safe = np.where(den > 0, den, 1.0)
-        scC = correlate_2d(M * np.abs(X.astype(np.float64)), g) / safe
-        scS = correlate_2d(M * (np.abs(X.astype(np.float64)) + np.abs(C)) ** 2, g) / safe
-        rc = (np.abs(Cd[b] - C) / scC)[pos]
-        rs = (np.abs(Sd[b] - S) / scS)[pos]
-        worst_c, worst_s = max(worst_c, rc.max()), max(worst_s, rs.max())
+        scC = (correlate_2d(M * np.abs(X.astype(np.float64)), g) / safe)[pos]
+        scS = (correlate_2d(M * (np.abs(X.astype(np.float64)) + np.abs(C)) ** 2, g) / safe)[pos]
+        assert np.isfinite(Cd[b][pos]).all() and np.isfinite(Sd[b][pos]).all(), (NAME[prec], b)
+        rc = np.abs(Cd[b][pos] - C[pos]) / scC
+        rs = np.abs(Sd[b][pos] - S[pos]) / scS
+        worst_c, worst_s = max(worst_c, float(np.max(rc))), max(worst_s, float(np.max(rs)))
         med_c.append(np.median(rc))
         med_s.append(np.median(rs))
     print(f"{NAME[prec]} filter error / scale: C max {worst_c:.2e} median {np.median(med_c):.2e}; "
@@ -92,9 +94,20 @@ def test_candidates_16bit_vs_fp32(prec):
         if diff:
             from oracle.filters import taps_1d
             g = taps_1d(0, 8.0, 24)
-            for (b, i, j) in diff:
-                Q, sig, C, S = oracle_sig_map(cube[b], st.mask.astype(bool), g, 3)
-                if abs(sig[i, j] - 4.5) > 64 * U[prec] * (1 + abs(sig[i, j])):
+            M = st.mask.astype(bool)
+            den = correlate_2d(M.astype(np.float64), g)
+            maps = {}
+            for (b, i, j) in sorted(diff):
+                # the filters' error bound (8u of the scales, as gated above)
+                # carried to sig = (x - c)/sqrt(s):
+                #   |d sig| <= 8u (scC / sqrt(S) + |sig| scS / (2 S))
+                if b not in maps:
+                    Q, sig, C, S = oracle_sig_map(cube[b], M, g, 3)
+                    xa = np.abs(cube[b].astype(np.float64))
+                    maps[b] = (sig, S, correlate_2d(M * xa, g) / den, correlate_2d(M * (xa + np.abs(C)) ** 2, g) / den)
+                sig, S, scC, scS = maps[b]
+                bound = 8 * U[prec] * (scC[i, j] / np.sqrt(S[i, j]) + abs(sig[i, j]) * scS[i, j] / (2 * S[i, j]))
+                if abs(sig[i, j] - 4.5) > bound:
                     far += 1
     jac = inter / max(1, union)
     print(f"{NAME[prec]} candidates vs fp32: Jaccard {jac:.4f} ({inter}/{union}), far differences {far}",
