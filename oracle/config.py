@@ -15,6 +15,7 @@ import numpy as np
 
 KERNEL_GAUSS = 0
 KERNEL_BOX = 1
+KERNEL_DISK = 2   # circular uniform kernel (Sec. 2.1.1 names it as the alternative)
 
 
 @dataclasses.dataclass
@@ -27,7 +28,7 @@ class OracleConfig:
     kappa: float = 4.5                       # Sec. 3.4 uses 4.5 on real data
     s: float = 8.0                           # Gaussian width (px); paper gives heuristics only
     k_bg: int = 0                            # <= 0: ceil(3 s)
-    kernel: int = KERNEL_GAUSS               # Gaussian, or square uniform (Sec. 2.1.1)
+    kernel: int = KERNEL_GAUSS               # Gaussian, square uniform, or circular uniform (Sec. 2.1.1)
     n_iter: int = 1                          # sigma-clip iterations (Sec. 3.1 runs one)
     k_peak: int = 3                          # max-filter half-width (Sec. 2.1.2)
     k_flux: int = 2                          # flux box half-width (size unstated)
@@ -43,10 +44,15 @@ class OracleConfig:
     qc_warmup: int = 8                       # accepted frames before the zeta test arms
     max_sources: int = 8192
     peak_cap: int = 512                      # per band and frame
+    prefilter_sigma: float = 0.0             # > 0: detect on the image correlated with a Gaussian PSF of this width
+    prefilter_k: int = 0                     # its half-width; <= 0: ceil(4 sigma)
+    flux_bg_width: int = 0                   # > 0: flux minus the mean of an annulus this wide around the box
 
     def __post_init__(self):
         if self.k_bg <= 0:
             self.k_bg = int(math.ceil(3.0 * self.s))
+        if self.prefilter_sigma > 0 and self.prefilter_k <= 0:
+            self.prefilter_k = int(math.ceil(4.0 * self.prefilter_sigma))
         if self.freqs_mhz is None:
             self.freqs_mhz = np.linspace(60.0, 70.0, self.B)
 

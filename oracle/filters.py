@@ -14,7 +14,9 @@ Readings used here (the paper is silent on them):
   that image edges and the circular sky mask do not bias C and S towards
   zero:  C = (G*(W.X)) / (G*W),  S = (G*(W.(X-C)^2)) / (G*W), both 0 where
   G*W = 0;
-* the uniform alternative the paper mentions is the square box 1/(2k+1)^2.
+* the uniform alternatives the paper mentions are the square box
+  1/(2k+1)^2 and the circular (disk) kernel, uniform on the offsets with
+  u^2 + v^2 <= k^2; the disk is not separable and is applied as a 2-D sum.
 
 Because exp(-(n^2+m^2)/2s^2) = exp(-n^2/2s^2) exp(-m^2/2s^2), G equals the
 outer product g (x) g of the 1-D taps g_u = exp(-u^2/2s^2) / sum_v exp(-v^2/2s^2)
@@ -27,7 +29,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .config import KERNEL_BOX, KERNEL_GAUSS
+from .config import KERNEL_BOX, KERNEL_DISK, KERNEL_GAUSS
 
 
 def taps_1d(kernel: int, s: float, k: int) -> np.ndarray:
@@ -40,6 +42,34 @@ def taps_1d(kernel: int, s: float, k: int) -> np.ndarray:
     else:
         raise ValueError("unknown kernel")
     return e / e.sum()
+
+
+def disk_kernel(k: int) -> np.ndarray:
+    """float64 [2k+1][2k+1]: 1/N on the offsets with u^2 + v^2 <= k^2."""
+    u = np.arange(-k, k + 1)
+    inside = (u[:, None] ** 2 + u[None, :] ** 2) <= k * k
+    return inside / inside.sum()
+
+
+def kernel_taps(kernel: int, s: float, k: int) -> np.ndarray:
+    """1-D taps of a separable kernel, or the 2-D disk kernel."""
+    if kernel == KERNEL_DISK:
+        return disk_kernel(k)
+    return taps_1d(kernel, s, k)
+
+
+def correlate_kernel2d(img: np.ndarray, K: np.ndarray) -> np.ndarray:
+    """out[i, j] = sum_{u,v} K[u, v] img[i+u, j+v], zero outside the image."""
+    k = (K.shape[0] - 1) // 2
+    H, W = img.shape
+    pad = np.zeros((H + 2 * k, W + 2 * k), dtype=np.float64)
+    pad[k:k + H, k:k + W] = img
+    out = np.zeros((H, W), dtype=np.float64)
+    for a in range(2 * k + 1):
+        for b in range(2 * k + 1):
+            if K[a, b] != 0.0:
+                out += K[a, b] * pad[a:a + H, b:b + W]
+    return out
 
 
 def correlate_rows(img: np.ndarray, g: np.ndarray) -> np.ndarray:
@@ -60,7 +90,10 @@ def correlate_cols(img: np.ndarray, g: np.ndarray) -> np.ndarray:
 
 
 def correlate_2d(img: np.ndarray, g: np.ndarray) -> np.ndarray:
-    """(g (x) g) correlated with img, zero extension."""
+    """(g (x) g) correlated with img, zero extension (g 1-D taps), or the 2-D
+    kernel g correlated with img."""
+    if np.ndim(g) == 2:
+        return correlate_kernel2d(np.asarray(img, dtype=np.float64), g)
     return correlate_cols(correlate_rows(np.asarray(img, dtype=np.float64), g), g)
 
 
@@ -69,6 +102,7 @@ def centre_spread(X: np.ndarray, Wt: np.ndarray, g: np.ndarray):
 
     X  : float image (any float dtype; evaluated in float64)
     Wt : bool/0-1 weight plane (sky mask and not already clipped)
+    g  : 1-D taps of a separable kernel, or a 2-D kernel
     Returns (C, S, den) in float64.
     """
     X = np.asarray(X, dtype=np.float64)
@@ -80,3 +114,11 @@ def centre_spread(X: np.ndarray, Wt: np.ndarray, g: np.ndarray):
     R = X - C
     S = np.where(pos, correlate_2d(w * R * R, g) / safe, 0.0)
     return C, S, den
+
+
+def prefilter(X: np.ndarray, M: np.ndarray, g_psf: np.ndarray) -> np.ndarray:
+    """Image correlated with the PSF taps over the sky mask, normalised like C:
+    (G_psf*(M.X)) / (G_psf*M), 0 where the denominator is 0 (the matched
+    filter of a point source in white noise)."""
+    C, _, _ = centre_spread(X, M, g_psf)
+    return C

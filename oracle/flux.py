@@ -23,9 +23,29 @@ def box_max(img: np.ndarray, i: int, j: int, k: int) -> float:
     return float(np.asarray(img[r0:r1, c0:c1], dtype=np.float64).max())
 
 
-def measure(cube: np.ndarray, i: int, j: int, k: int) -> np.ndarray:
-    """Per-band box maxima at (i, j), float64 [B]."""
-    return np.array([box_max(cube[b], i, j, k) for b in range(cube.shape[0])])
+def annulus_mean(img: np.ndarray, i: int, j: int, k: int, w: int) -> float:
+    """Mean of the pixels at Chebyshev distance k+1 .. k+w from (i, j) inside
+    the image (float64 sum)."""
+    H, W = img.shape
+    r0, r1 = max(0, i - k - w), min(H, i + k + w + 1)
+    c0, c1 = max(0, j - k - w), min(W, j + k + w + 1)
+    tot, n = 0.0, 0
+    for r in range(r0, r1):
+        for c in range(c0, c1):
+            if max(abs(r - i), abs(c - j)) > k:
+                tot += float(img[r, c])
+                n += 1
+    return tot / n if n else 0.0
+
+
+def measure(cube: np.ndarray, i: int, j: int, k: int, bg_width: int = 0) -> np.ndarray:
+    """Per-band box maxima at (i, j), float64 [B].  With bg_width > 0 the
+    background-subtracted flux: the box maximum minus the mean of the
+    surrounding annulus bg_width pixels wide, rounded once to float32."""
+    if bg_width <= 0:
+        return np.array([box_max(cube[b], i, j, k) for b in range(cube.shape[0])])
+    return np.array([float(np.float32(box_max(cube[b], i, j, k) - annulus_mean(cube[b], i, j, k, bg_width)))
+                     for b in range(cube.shape[0])])
 
 
 def window(series: dict, t_end: int, B: int, ring_len: int, grid_rows) -> tuple:

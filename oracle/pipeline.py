@@ -16,7 +16,7 @@ from . import cnn as cnn_mod
 from .catalog import Catalog
 from .config import OracleConfig
 from .detect import band_peaks
-from .filters import taps_1d
+from .filters import kernel_taps, prefilter, taps_1d
 from .flux import measure, window
 from .qc import RunningStats, band_reject
 
@@ -25,7 +25,9 @@ class OracleStream:
     def __init__(self, cfg: OracleConfig):
         self.cfg = cfg
         self.M = cfg.mask
-        self.g = taps_1d(cfg.kernel, cfg.s, cfg.k_bg)
+        self.g = kernel_taps(cfg.kernel, cfg.s, cfg.k_bg)
+        # optional matched pre-filter: detection runs on the image correlated with the PSF
+        self.g_psf = (taps_1d(0, cfg.prefilter_sigma, cfg.prefilter_k) if cfg.prefilter_sigma > 0 else None)
         self.stats = RunningStats(cfg.B, cfg.H, cfg.W)
         self.catalog = Catalog(cfg.max_sources, cfg.n_mon, cfg.r_dup, cfg.r_assoc)
         self.cache: Dict[int, np.ndarray] = {}       # step -> quality-controlled cube
@@ -67,11 +69,21 @@ class OracleStream:
         return rej
 
     # -- step 2 + 3: detection, association (Sec. 2.1, 2.2) ------------------------------
+    def detection_image(self, t=None):
+        """The cube detection runs on at step t: the quality-controlled cube,
+        or its PSF-correlated form when the pre-filter is on, rounded to
+        float32 as the device stores it, so that the local-maximum test
+        compares the same kind of values on both sides."""
+        X = self.cache[self.t if t is None else t]
+        if self.g_psf is None:
+            return X
+        return np.stack([prefilter(X[b], self.M, self.g_psf) for b in range(X.shape[0])]).astype(np.float32)
+
     def find_peaks(self):
         """Peak records of every accepted band of the current step (Sec. 2.1),
         and the bitmask of bands whose list exceeded peak_cap (dropped whole)."""
         c = self.cfg
-        X = self.cache[self.t]
+        X = self.detection_image()
         rej = self.rejected[self.t]
         peaks: List[tuple] = []
         overflow = 0
@@ -111,7 +123,7 @@ class OracleStream:
 
     def _record(self, sid: int, tau: int, i: int, j: int):
         c = self.cfg
-        f = measure(self.cache[tau], i, j, c.k_flux)
+        f = measure(self.cache[tau], i, j, c.k_flux, c.flux_bg_width)
         rej = self.rejected[tau]
         v = np.array([not (rej >> b & 1) for b in range(c.B)])
         self.series.setdefault(sid, {})[tau] = (f, v)

@@ -1,0 +1,209 @@
+"""Training of the parameter-inference network on simulated dynamic spectra
+and the dispersion-measure accuracy table (Sec. 2.3.3, Sec. 3.2, Table 1).
+
+    python -m paper_2103_15418_amd.train [--samples 32768] [--out weights.npz] [--table table.json]
+
+Training is an offline step: it uses PyTorch's autograd on the GPU (Adam with
+default settings, mini-batches, early stopping on the likelihood of a held-
+out tenth) for the network the library's kernels evaluate (four 3 x 3
+convolutions 1->32->32->64->64 with leaky rectifiers, dense 65536->128->14;
+mu = out[0:4] = (DM, width, amplitude, arrival), L packed row by row with a
+softplus diagonal, Sigma = L L^T).  The loss per sample is the Gaussian
+negative log likelihood 1/2 log det Sigma + 1/2 (theta - mu)^T Sigma^-1
+(theta - mu) = sum_i log L_ii + 1/2 |L^-1 (theta - mu)|^2.  The trained
+weights are then loaded into the library (lpf_model_create) and the table is
+computed from the library's own inference on fresh simulated spectra.
+
+Table (per amplitude bin (0,1], (1,2], (2,4], (4,8], the paper's fluence
+bins): MAE and RMSE of the inferred DM, both also relative to the true DM
+(mean of |e| / DM and root mean of (e / DM)^2), and the fraction of samples
+whose true DM lies within 1, 2, 3 inferred standard deviations
+sigma_DM = sqrt(Sigma_00).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+BINS = ((0.0, 1.0), (1.0, 2.0), (2.0, 4.0), (4.0, 8.0))
+DIAG = (0, 2, 5, 9)   # packed positions of L_00, L_11, L_22, L_33
+
+
+def build_net(alpha: float):
+    import torch
+    import torch.nn as nn
+
+    class Net(nn.Module):
+        def __init__(self):
+            super().__init__()
+            self.conv = nn.ModuleList([nn.Conv2d(ci, co, 3, padding=1)
+                                       for ci, co in ((1, 32), (32, 32), (32, 64), (64, 64))])
+            self.fc1 = nn.Linear(64 * 16 * 64, 128)
+            self.fc2 = nn.Linear(128, 14)
+            self.alpha = alpha
+
+        def forward(self, x):
+            a = x[:, None]
+            for c in self.conv:
+                a = torch.nn.functional.leaky_relu(c(a), self.alpha)
+            h = torch.nn.functional.leaky_relu(self.fc1(a.flatten(1)), self.alpha)
+            return self.fc2(h)
+
+    return Net()
+
+
+def head(out):
+    """raw [n][14] -> (mu [n][4], lower-triangular L [n][4][4])."""
+    import torch
+    mu = out[:, :4]
+    n = out.shape[0]
+    L = out.new_zeros((n, 4, 4))
+    k = 4
+    for i in range(4):
+        for j in range(i + 1):
+            v = out[:, k]
+            L[:, i, j] = torch.nn.functional.softplus(v) if i == j else v
+            k += 1
+    return mu, L
+
+
+def nll(out, theta):
+    import torch
+    mu, L = head(out)
+    r = (theta - mu)[:, :, None]
+    z = torch.linalg.solve_triangular(L, r, upper=False)[:, :, 0]
+    logdet = torch.log(torch.diagonal(L, dim1=1, dim2=2)).sum(1)
+    return (logdet + 0.5 * (z * z).sum(1)).mean()
+
+
+def export(net) -> dict:
+    """Weights in PyTorch layouts, as the library's blob expects."""
+    w = {}
+    for l, c in enumerate(net.conv, start=1):
+        w[f"conv{l}.w"] = c.weight.detach().float().cpu().numpy().copy()
+        w[f"conv{l}.b"] = c.bias.detach().float().cpu().numpy().copy()
+    for name in ("fc1", "fc2"):
+        m = getattr(net, name)
+        w[f"{name}.w"] = m.weight.detach().float().cpu().numpy().copy()
+        w[f"{name}.b"] = m.bias.detach().float().cpu().numpy().copy()
+    w["alpha"] = float(net.alpha)
+    return w
+
+
+def train(samples=32768, seed=2103_15418 + 11, batch=256, patience=5, max_epochs=100, alpha=0.01,
+          log=print, device="cuda"):
+    import torch
+    from synth.pulses import RANGES, simulate
+    torch.manual_seed(seed)
+    x, th, _ = simulate(samples, seed)
+    nv = samples // 10
+    dev = torch.device(device)
+    xt, tt = torch.from_numpy(x[nv:]).to(dev), torch.from_numpy(th[nv:]).to(dev)
+    xv, tv = torch.from_numpy(x[:nv]).to(dev), torch.from_numpy(th[:nv]).to(dev)
+    net = build_net(alpha).to(dev)
+    with torch.no_grad():
+        # start at the prior: mean and spread of the uniform parameter ranges
+        lo = np.array([RANGES[k][0] for k in ("dm", "width", "amp", "t0")])
+        hi = np.array([RANGES[k][1] for k in ("dm", "width", "amp", "t0")])
+        net.fc2.weight.mul_(0.01)
+        net.fc2.bias.zero_()
+        net.fc2.bias[:4] = torch.tensor((lo + hi) / 2, dtype=torch.float32)
+        sd = (hi - lo) / np.sqrt(12.0)
+        for i, p in enumerate(DIAG):
+            net.fc2.bias[4 + p] = float(np.log(np.expm1(sd[i])))
+    opt = torch.optim.Adam(net.parameters())
+    best, best_state, bad, hist = np.inf, None, 0, []
+    g = torch.Generator(device="cpu")
+    g.manual_seed(seed)
+    for ep in range(max_epochs):
+        net.train()
+        perm = torch.randperm(xt.shape[0], generator=g).to(dev)
+        tot = 0.0
+        for i in range(0, xt.shape[0], batch):
+            idx = perm[i:i + batch]
+            loss = nll(net(xt[idx]), tt[idx])
+            opt.zero_grad()
+            loss.backward()
+            opt.step()
+            tot += float(loss.detach()) * len(idx)
+        net.eval()
+        with torch.no_grad():
+            vl = float(sum(nll(net(xv[i:i + 1024]), tv[i:i + 1024]) * len(xv[i:i + 1024])
+                           for i in range(0, nv, 1024)) / nv)
+        hist.append((ep, tot / xt.shape[0], vl))
+        log(f"[train] epoch {ep} train nll {tot / xt.shape[0]:.4f} val nll {vl:.4f}")
+        if vl < best - 1e-4:
+            best, bad = vl, 0
+            best_state = {k: v.detach().clone() for k, v in net.state_dict().items()}
+        else:
+            bad += 1
+            if bad >= patience:
+                break
+    net.load_state_dict(best_state)
+    return net, hist
+
+
+def dm_table(mu, Lp, theta):
+    """Table 1 quantities per amplitude bin from inferred mu [n][4], packed L
+    [n][10] and true theta [n][4]."""
+    e = mu[:, 0].astype(np.float64) - theta[:, 0]
+    sig = np.abs(Lp[:, 0].astype(np.float64))          # sqrt(Sigma_00) = |L_00|
+    dm = theta[:, 0].astype(np.float64)
+    A = theta[:, 2]
+    rows = {}
+    for lo, hi in BINS:
+        s = (A > lo) & (A <= hi) & (dm > 0)
+        rows[f"({lo:g}, {hi:g}]"] = {
+            "n": int(s.sum()),
+            "MAE": float(np.mean(np.abs(e[s]))), "MAE/DM": float(np.mean(np.abs(e[s]) / dm[s])),
+            "RMSE": float(np.sqrt(np.mean(e[s] ** 2))), "RMSE/DM": float(np.sqrt(np.mean((e[s] / dm[s]) ** 2))),
+            "within_1sigma": float(np.mean(np.abs(e[s]) <= sig[s])),
+            "within_2sigma": float(np.mean(np.abs(e[s]) <= 2 * sig[s])),
+            "within_3sigma": float(np.mean(np.abs(e[s]) <= 3 * sig[s])),
+        }
+    return rows
+
+
+def evaluate(weights: dict, n=8192, seed=2103_15418 + 12, precision=0):
+    """The library's inference (lpf_infer_windows) on fresh simulated spectra."""
+    import torch
+    from synth.pulses import simulate
+    from . import Model
+    x, th, _ = simulate(n, seed)
+    m = Model(weights, precision=precision, max_batch=1024)
+    mu, L = m.infer_windows(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    return dm_table(mu.cpu().numpy(), L.cpu().numpy(), th), (x, th, mu.cpu().numpy(), L.cpu().numpy())
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--samples", type=int, default=32768)
+    ap.add_argument("--epochs", type=int, default=100)
+    ap.add_argument("--out", default=None, help="write the trained weights (npz)")
+    ap.add_argument("--table", default=None, help="write the DM table (json)")
+    args = ap.parse_args(argv)
+    t0 = time.time()
+    net, hist = train(args.samples, max_epochs=args.epochs)
+    w = export(net)
+    res = {"samples": args.samples, "epochs": len(hist), "train_s": time.time() - t0,
+           "history": hist, "fp32": evaluate(w)[0], "bf16": evaluate(w, precision=1)[0]}
+    if args.out:
+        np.savez(args.out, **{k: v for k, v in w.items() if k != "alpha"}, alpha=np.float32(w["alpha"]))
+    if args.table:
+        with open(args.table, "w") as f:
+            json.dump(res, f, indent=1)
+    print(json.dumps({k: v for k, v in res.items() if k != "history"}))
+
+
+if __name__ == "__main__":
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    main()
