@@ -32,6 +32,8 @@ PARAM_MAP = dict(kappa="kappa", bg_sigma="s", bg_halfwidth="k_bg", kernel="kerne
                  qc_rms_floor="qc_rms_floor", qc_pixel_zeta="qc_pixel_zeta",
                  qc_warmup="qc_warmup", max_sources="max_sources", peak_cap="peak_cap")
 DEVICE_ONLY = ("debug_planes", "filter_precision")
+FLOAT_PARAMS = ("kappa", "bg_sigma", "dup_radius", "assoc_radius", "qc_band_z", "qc_rms_z", "qc_rms_floor",
+                "qc_pixel_zeta")
 
 
 def make_pair(B, H, W, sky_mask=None, grid_rows=None, **params):
@@ -42,6 +44,11 @@ def make_pair(B, H, W, sky_mask=None, grid_rows=None, **params):
     if "k_bg" in ok and ok["k_bg"] <= 0:
         ok.pop("k_bg")
     ocfg = OracleConfig(B=B, H=H, W=W, sky_mask=sky_mask, **ok)
+    # the C configuration holds these parameters as float32: the oracle gets
+    # the same values (e.g. 0.05 becomes 0.0500000007..., which moves a
+    # floored RMS z by 1.5e-8 relative)
+    for key in FLOAT_PARAMS:
+        setattr(ocfg, PARAM_MAP[key], float(np.float32(getattr(ctx.cfg, key))))
     if grid_rows is not None:
         rows = list(grid_rows)
         ocfg.grid_row = lambda b, rows=rows: rows[b]
