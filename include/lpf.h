@@ -230,6 +230,23 @@ int lpf_infer(lpf_ctx* const* ctxs, int32_t n_ctx, const lpf_model* model,
 int lpf_infer_windows(const lpf_model* model, const float* windows, int32_t n, float* mu_out,
                       float* L_out, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the network
+ * on n <= LPF_STATIC_MAX_WINDOWS device windows, as lpf_infer_windows
+ * computes it, with its intermediate buffers (activations, fc1 partials,
+ * hidden layer) in a file-scope device array of the library (about 18 MiB,
+ * one copy per GPU, held until the process ends) instead of the model's
+ * workspace.  Launches directly on hip_stream; allocates nothing and makes
+ * no allocating call.  The model still supplies the weights; windows, mu_out
+ * and L_out are caller-owned device buffers as in lpf_infer_windows.
+ * LPF_EINVAL for n > LPF_STATIC_MAX_WINDOWS or null buffers, LPF_EDEVICE on
+ * a HIP error.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (different streams or threads) race and must be
+ * serialised by the caller. */
+enum { LPF_STATIC_MAX_WINDOWS = 32 };
+int lpf_infer_windows_static(const lpf_model* model, const float* windows, int32_t n, float* mu_out,
+                             float* L_out, void* hip_stream);
+
 /* Asynchronous form of lpf_infer over the episodes that ended at the last
  * detect of each context (Sec. 2.2 episode end -> Sec. 2.3 inference): the
  * counts stay on the device, the windows are gathered there (into buffers of

@@ -100,6 +100,7 @@ def lib() -> C.CDLL:
         "lpf_infer_async": (i32, [vp, i32, vp, C.POINTER(C.c_int64)]),
         "lpf_infer_collect": (i32, [vp, C.c_int64, vp, vp, vp, i32, C.POINTER(i32)]),
         "lpf_infer_windows": (i32, [vp, vp, i32, vp, vp, vp]),
+        "lpf_infer_windows_static": (i32, [vp, vp, i32, vp, vp, vp]),
         "lpf_debug_read": (i32, [vp, i32, vp, sz]),
         "lpf_sync": (i32, [vp]),
         "lpf_profile_enable": (i32, [vp, i32]),
@@ -377,6 +378,17 @@ class Model:
         if rc != LPF_OK:
             raise LpfError(rc, "infer_windows")
         return mu, L
+
+    def infer_windows_static(self, windows, mu, L, stream=None):
+        """The allocation-free form: the network's intermediate buffers live in
+        the library's static device array; mu [n][4] and L [n][10] are the
+        caller's torch CUDA float32 tensors (n <= 32).  Returns the status."""
+        torch = _torch()
+        assert windows.is_cuda and windows.dtype == torch.float32 and windows.is_contiguous()
+        assert mu.is_contiguous() and L.is_contiguous()
+        return int(lib().lpf_infer_windows_static(self.h, C.c_void_p(windows.data_ptr()), int(windows.shape[0]),
+                                                  C.c_void_p(mu.data_ptr()), C.c_void_p(L.data_ptr()),
+                                                  C.c_void_p(_stream_ptr(stream))))
 
 
 FRAME_DTYPE = np.dtype([("stream_id", "<i4"), ("pad0", "<i4"), ("t", "<i8"), ("arrival_ns", "<i8"),

@@ -19,6 +19,8 @@ hipError_t cnn_forward(const lpf_model* m, const float* windows, const int* n_de
                        float* L, hipStream_t s);
 hipError_t launch_gather_ended(lpf_ctx* c, int ci, int32_t* hdr, float* out, int32_t* rows, int cap,
                                hipStream_t s, bool first);
+hipError_t cnn_forward_static(const lpf_model* m, const float* windows, int n, float* mu, float* L, hipStream_t s);
+int static_max_windows();
 float* model_window_buffer(const lpf_model* m);
 float* model_mu_buffer(const lpf_model* m);
 float* model_L_buffer(const lpf_model* m);
@@ -660,6 +662,15 @@ int lpf_infer_windows(const lpf_model* m, const float* windows, int32_t n, float
     if (hipEventRecord(m->ev_out, m->istream) != hipSuccess) return LPF_EDEVICE;
     if (hipStreamWaitEvent(s, m->ev_out, 0) != hipSuccess) return LPF_EDEVICE;
     return LPF_OK;
+}
+
+int lpf_infer_windows_static(const lpf_model* m, const float* windows, int32_t n, float* mu, float* L,
+                             void* stream) {
+    if (!m || n < 0 || (n > 0 && (!windows || !mu || !L))) return LPF_EINVAL;
+    if (n > static_max_windows()) return LPF_EINVAL;
+    if (n == 0) return LPF_OK;
+    hipError_t e = cnn_forward_static(m, windows, n, mu, L, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LPF_OK : LPF_EDEVICE;
 }
 
 int lpf_infer_async(lpf_ctx* const* ctxs, int32_t n_ctx, lpf_model* m, int64_t* ticket) {

@@ -17,6 +17,7 @@
 // LDS) with a fixed-order reduction; fc2 and the head run on the ALUs.
 
 #include <cmath>
+#include <mutex>
 
 #include "lpf_internal.h"
 
@@ -510,14 +511,37 @@ struct GridCaps {
         : conv1(n_dev ? 1024 : 4096), conv(n_dev ? 512 : 2048), fc1_rows(n_dev ? 2 : 4), small(n_dev ? 128 : 1024) {}
 };
 
+// Device buffers one forward pass writes besides its outputs: two activation
+// planes, the fc1 split-K partials (leading dimension ldp rows) and the
+// hidden layer.  A model's own workspace provides them, or the library's
+// static scratch array (lpf_infer_windows_static).
+struct NetBufs {
+    void* act_a;
+    void* act_b;
+    float* part;
+    float* hidden;
+    int ldp;
+};
+
+NetBufs model_bufs(const lpf_model* m) {
+    const CnnWork& w = m->work;
+    NetBufs nb;
+    nb.act_a = m->precision == LPF_PREC_FP32 ? static_cast<void*>(w.act_a) : w.act16_a;
+    nb.act_b = m->precision == LPF_PREC_FP32 ? static_cast<void*>(w.act_b) : w.act16_b;
+    nb.part = w.part;
+    nb.hidden = w.hidden;
+    nb.ldp = pad32(m->max_batch);
+    return nb;
+}
+
 template <typename T>
-hipError_t forward16(const lpf_model* m, const float* windows, const int* n_dev, int n_cap, hipStream_t s) {
+hipError_t forward16(const lpf_model* m, const NetBufs& nb, const float* windows, const int* n_dev, int n_cap,
+                     hipStream_t s) {
     const ModelLayout& lay = m->lay;
     const float* W = m->wts;
-    const CnnWork& w = m->work;
-    const T* w16 = static_cast<const T*>(w.w16);
-    T* a = static_cast<T*>(w.act16_a);
-    T* b = static_cast<T*>(w.act16_b);
+    const T* w16 = static_cast<const T*>(m->work.w16);
+    T* a = static_cast<T*>(nb.act_a);
+    T* b = static_cast<T*>(nb.act_b);
     const GridCaps gc(n_dev);
     hipLaunchKernelGGL((k_conv1_16<T>), dim3(grid_cap(((int64_t)n_cap * kGH * kGW + 255) / 256, gc.conv1)),
                        dim3(256), 0, s, windows, W + lay.w1, W + lay.b1, a, n_dev, n_cap, m->alpha);
@@ -528,44 +552,104 @@ hipError_t forward16(const lpf_model* m, const float* windows, const int* n_dev,
     hipLaunchKernelGGL((k_conv16<T, 64, 64>), dim3(grid_cap((int64_t)n_cap * kGH, gc.conv)), dim3(256), 0, s, a,
                        w16 + kW16o4, W + lay.b4, b, n_dev, n_cap, m->alpha);
     hipLaunchKernelGGL((k_fc1_16<T>), dim3(kNSplit, grid_cap((n_cap + 31) / 32, gc.fc1_rows)), dim3(256), 0, s, b,
-                       w16 + kW16of1, w.part, n_dev, n_cap, pad32(m->max_batch));
+                       w16 + kW16of1, nb.part, n_dev, n_cap, nb.ldp);
     return hipGetLastError();
 }
 
 // Runs the network on the device windows [0, n) with n = *n_dev clamped to
-// n_cap when n_dev is given, else n = n_cap (n_cap <= max_batch).
-hipError_t cnn_forward(const lpf_model* m, const float* windows, const int* n_dev, int n_cap, float* mu,
-                       float* L, hipStream_t s) {
+// n_cap when n_dev is given, else n = n_cap (n_cap <= the rows nb holds).
+hipError_t forward_on(const lpf_model* m, const NetBufs& nb, const float* windows, const int* n_dev, int n_cap,
+                      float* mu, float* L, hipStream_t s) {
     if (n_cap <= 0) return hipSuccess;
     const ModelLayout& lay = m->lay;
     const float* W = m->wts;
-    const CnnWork& w = m->work;
-    const int ldp = pad32(m->max_batch);
     const GridCaps gc(n_dev);
     hipError_t e = hipSuccess;
     if (m->precision == LPF_PREC_BF16) {
-        e = forward16<__bf16>(m, windows, n_dev, n_cap, s);
+        e = forward16<__bf16>(m, nb, windows, n_dev, n_cap, s);
     } else if (m->precision == LPF_PREC_FP16) {
-        e = forward16<_Float16>(m, windows, n_dev, n_cap, s);
+        e = forward16<_Float16>(m, nb, windows, n_dev, n_cap, s);
     } else {
+        float* a = static_cast<float*>(nb.act_a);
+        float* b = static_cast<float*>(nb.act_b);
         hipLaunchKernelGGL(k_conv1, dim3(grid_cap(((int64_t)n_cap * kGH * kGW + 255) / 256, gc.conv1)),
-                           dim3(256), 0, s, windows, W + lay.w1, W + lay.b1, w.act_a, n_dev, n_cap, m->alpha);
+                           dim3(256), 0, s, windows, W + lay.w1, W + lay.b1, a, n_dev, n_cap, m->alpha);
         hipLaunchKernelGGL((k_conv_mfma<32, 32>), dim3(grid_cap((int64_t)n_cap * (kGH / 2), gc.conv)), dim3(256),
-                           0, s, w.act_a, W + lay.w2, W + lay.b2, w.act_b, n_dev, n_cap, m->alpha);
+                           0, s, a, W + lay.w2, W + lay.b2, b, n_dev, n_cap, m->alpha);
         hipLaunchKernelGGL((k_conv_mfma<32, 64>), dim3(grid_cap((int64_t)n_cap * kGH, gc.conv)), dim3(256), 0, s,
-                           w.act_b, W + lay.w3, W + lay.b3, w.act_a, n_dev, n_cap, m->alpha);
+                           b, W + lay.w3, W + lay.b3, a, n_dev, n_cap, m->alpha);
         hipLaunchKernelGGL((k_conv_mfma<64, 64>), dim3(grid_cap((int64_t)n_cap * kGH, gc.conv)), dim3(256), 0, s,
-                           w.act_a, W + lay.w4, W + lay.b4, w.act_b, n_dev, n_cap, m->alpha);
-        hipLaunchKernelGGL(k_fc1_mfma, dim3(kNSplit, grid_cap((n_cap + 31) / 32, gc.fc1_rows)), dim3(256), 0, s, w.act_b,
-                           W + lay.f1, w.part, n_dev, n_cap, ldp);
+                           a, W + lay.w4, W + lay.b4, b, n_dev, n_cap, m->alpha);
+        hipLaunchKernelGGL(k_fc1_mfma, dim3(kNSplit, grid_cap((n_cap + 31) / 32, gc.fc1_rows)), dim3(256), 0, s, b,
+                           W + lay.f1, nb.part, n_dev, n_cap, nb.ldp);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fc1_reduce, dim3(grid_cap(((int64_t)n_cap * kHidden + 255) / 256, gc.small)), dim3(256), 0,
-                       s, w.part, W + lay.fb1, w.hidden, n_dev, n_cap, ldp, m->alpha);
+                       s, nb.part, W + lay.fb1, nb.hidden, n_dev, n_cap, nb.ldp, m->alpha);
     hipLaunchKernelGGL(k_fc2_head, dim3(grid_cap(((int64_t)n_cap * kOut + 255) / 256, gc.small)), dim3(256), 0, s,
-                       w.hidden, W + lay.f2, W + lay.fb2, mu, L, n_dev, n_cap);
+                       nb.hidden, W + lay.f2, W + lay.fb2, mu, L, n_dev, n_cap);
     return hipGetLastError();
+}
+
+hipError_t cnn_forward(const lpf_model* m, const float* windows, const int* n_dev, int n_cap, float* mu,
+                       float* L, hipStream_t s) {
+    return forward_on(m, model_bufs(m), windows, n_dev, n_cap, mu, L, s);
+}
+
+// ---- allocation-free inference: a file-scope device scratch array --------
+// Holds the buffers of one forward pass of up to kStaticWindows windows:
+// two float32 activation planes, the fc1 partials (32 rows) and the hidden
+// layer.  Each device has its own copy; host code reaches it only through
+// the address hipGetSymbolAddress returns on that device.
+constexpr int kStaticWindows = 32;
+constexpr size_t kStaticAct = (size_t)kStaticWindows * kGH * kGW * 64 * sizeof(float);   // 8 MiB
+constexpr size_t kStaticPart = (size_t)kNSplit * kStaticWindows * kHidden * sizeof(float);  // 2 MiB
+constexpr size_t kStaticHidden = (size_t)kStaticWindows * kHidden * sizeof(float);
+constexpr size_t kStaticBytes = 2 * kStaticAct + kStaticPart + kStaticHidden;
+static_assert(kStaticAct % 256 == 0 && kStaticPart % 256 == 0, "scratch sub-buffer alignment");
+
+__device__ __align__(256) char scratch[kStaticBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array, looked up once per device
+// (with that device current) and kept.
+hipError_t scratch_address(char** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+int static_max_windows() { return kStaticWindows; }
+size_t static_scratch_bytes() { return kStaticBytes; }
+
+// The network on n <= kStaticWindows device windows with the scratch array
+// as its buffers, on stream s; no allocation of any kind.
+hipError_t cnn_forward_static(const lpf_model* m, const float* windows, int n, float* mu, float* L, hipStream_t s) {
+    char* base = nullptr;
+    hipError_t e = scratch_address(&base);
+    if (e != hipSuccess) return e;
+    NetBufs nb;
+    nb.act_a = base;
+    nb.act_b = base + kStaticAct;
+    nb.part = reinterpret_cast<float*>(base + 2 * kStaticAct);
+    nb.hidden = reinterpret_cast<float*>(base + 2 * kStaticAct + kStaticPart);
+    nb.ldp = kStaticWindows;
+    return forward_on(m, nb, windows, nullptr, n, mu, L, s);
 }
 
 float* model_window_buffer(const lpf_model* m) { return m->work.windows; }
