@@ -61,7 +61,10 @@ enum {
     LPF_EDEVICE = -5, /* HIP error; the context is poisoned                   */
     LPF_ESTATE = -6   /* call order violated                                  */
 };
-enum { LPF_KERNEL_GAUSS = 0, LPF_KERNEL_BOX = 1 };
+/* Background kernel (Sec. 2.1.1): Gaussian, square uniform, or circular
+ * uniform (disk of radius bg_halfwidth: offsets with u^2 + v^2 <= k^2; float32
+ * filters with one clip iteration, k <= 32). */
+enum { LPF_KERNEL_GAUSS = 0, LPF_KERNEL_BOX = 1, LPF_KERNEL_DISK = 2 };
 enum { LPF_PREC_FP32 = 0, LPF_PREC_BF16 = 1, LPF_PREC_FP16 = 2 };
 
 /* Method parameters.  Names follow Sec. 2.1-2.2 and App. A. */
@@ -73,7 +76,7 @@ typedef struct {
     float kappa;              /* threshold in spreads: y = x > c + kappa sqrt(s) */
     float bg_sigma;           /* Gaussian width s, pixels                       */
     int32_t bg_halfwidth;     /* kernel half-width k; <= 0 -> ceil(3 s); <= 40  */
-    int32_t kernel;           /* LPF_KERNEL_GAUSS or LPF_KERNEL_BOX (square)     */
+    int32_t kernel;           /* LPF_KERNEL_GAUSS, _BOX (square) or _DISK         */
     int32_t clip_iters;       /* sigma-clip iterations, 1..16                    */
     int32_t peak_halfwidth;   /* max-filter half-width (paper: 3), 1..8          */
     int32_t flux_halfwidth;   /* flux box half-width, 0..8                       */
@@ -97,6 +100,16 @@ typedef struct {
                                  lpf_ingest_frame); the image cache holds one
                                  step more.  0: everything on the context's
                                  stream                                        */
+    /* detection variants (Sec. 2.1.1 and Sec. 2.2 readings) */
+    float psf_sigma;          /* > 0: detection runs on the image correlated
+                                 with a Gaussian PSF of this width (pixels) over
+                                 the sky mask and normalised like C (a matched
+                                 filter for point sources); flux still reads
+                                 the quality-controlled image.  0: off        */
+    int32_t psf_halfwidth;    /* PSF kernel half-width; <= 0 -> ceil(4 psf_sigma); <= 40 */
+    int32_t flux_bg_width;    /* > 0: flux = box maximum minus the mean of the
+                                 annulus of this width around the box (local
+                                 background); 0: raw box maximum              */
 } lpf_config;
 
 /* One peak of the map P = Q and Y (Sec. 2.1.2) with the local estimates. */
@@ -175,6 +188,27 @@ int lpf_detect(lpf_ctx* ctx, lpf_peak* peaks_out, int32_t cap, int32_t* n_peaks,
  * measured on the cached steps [max(t - backfill, first t), t - 1].
  * Device-only and asynchronous. */
 int lpf_extract_flux(lpf_ctx* ctx);
+
+/* Batch forms of the three per-step calls for n contexts (several image
+ * streams of uneven B, H, W; Sec. 3.5: every stream must keep up with its
+ * cadence) as grouped launches: each stage runs as one kernel launch over up
+ * to 8 contexts, whose workgroups find their context's arguments in a table
+ * passed with the launch (the filter passes group contexts with the same
+ * float32 strip kernel, one clip iteration and equal taps; others run their
+ * own launches).  Results are bitwise those of the per-context calls.
+ * Requirements: the contexts are distinct, were created on one hipStream_t
+ * (the launches go there) and have pipeline_ingest = 0 (LPF_EINVAL
+ * otherwise).  Every context is checked before anything is launched: a call
+ * order or time order violation of any context returns LPF_ESTATE /
+ * LPF_EORDER with nothing done.  Nothing is read back: per-context counters
+ * and outputs come from lpf_status, lpf_read_spectrum and lpf_infer*.
+ * lpf_ingest_batch: t[n] steps, cubes[n] cubes (device memory if
+ * cubes_on_device, else host memory copied before return, which then
+ * synchronises). */
+int lpf_ingest_batch(lpf_ctx* const* ctxs, const int64_t* t, const float* const* cubes,
+                     int32_t cubes_on_device, int32_t n);
+int lpf_detect_batch(lpf_ctx* const* ctxs, int32_t n);
+int lpf_extract_flux_batch(lpf_ctx* const* ctxs, int32_t n);
 
 /* Counters of the last step; synchronises. */
 int lpf_status(lpf_ctx* ctx, lpf_status_t* out);
@@ -272,6 +306,44 @@ int lpf_infer_async(lpf_ctx* const* ctxs, int32_t n_ctx, lpf_model* model, int64
 int lpf_infer_collect(lpf_model* model, int64_t ticket, float* mu_out, float* L_out, int32_t* src_out,
                       int32_t cap, int32_t* n_out);
 
+/* ---- candidates, alerts and state persistence ---------------------------- */
+
+/* Candidate selection on the network's outputs (Sec. 2.3.1: nearby noise is
+ * not dispersed, so low dispersion measures are excluded; Sec. 3.3-3.4: on
+ * real data the inferred DM is kept above 50 and candidates are ranked by the
+ * inferred standard deviation of the DM, large values marking false
+ * positives).  mu [n][4] and L [n][10] as lpf_infer returns them (host).
+ * sigma_DM = sqrt(Sigma_00) with Sigma = L L^T, i.e. |L_00|.  Keeps the rows
+ * with mu_DM > dm_min and sigma_DM <= sigma_max, ordered by sigma_DM
+ * ascending (ties: row); idx_out [n] receives their row indices, *n_out
+ * their count; sigma_out [n] (nullable) every row's sigma_DM.  Host only. */
+int lpf_select_candidates(const float* mu, const float* L, int32_t n, float dm_min, float sigma_max,
+                          int32_t* idx_out, float* sigma_out, int32_t* n_out);
+
+/* Image data of a candidate for an alert (Sec. 1: a trigger saves the data of
+ * interest): the (2 half + 1)^2 box around (row, col) of the cached
+ * quality-controlled cube of each step t_first .. t_first + n_steps - 1.
+ * out: host [n_steps][B][2 half + 1][2 half + 1] float32, zero outside the
+ * image, in rejected bands and for steps no longer cached; have (nullable):
+ * host [n_steps], 1 where the step was cached.  half <= 32, n_steps <= the
+ * cache depth (backfill_steps + 1, + 1 with pipeline_ingest).  Synchronises. */
+int lpf_read_cutouts(lpf_ctx* ctx, int32_t row, int32_t col, int32_t half, int64_t t_first, int32_t n_steps,
+                     float* out, uint8_t* have);
+
+/* Checkpoint of a context's state between steps (after lpf_extract_flux, or
+ * before the first ingest): image cache, running QC statistics, source table,
+ * dynamic-spectrum rings, the last step's lists and counters, and the step
+ * bookkeeping, as one host byte block of lpf_checkpoint_size bytes.
+ * lpf_checkpoint_save synchronises (LPF_ESTATE inside a step, LPF_ENOMEM for
+ * a short buffer).  lpf_checkpoint_load restores it into a context created
+ * with the same configuration and sky mask that has taken no step yet
+ * (LPF_EINVAL for another configuration or mask, LPF_ESTATE after a step);
+ * the stream then continues with bitwise the results the saved context
+ * would give.  Inference tickets are not part of a context's state. */
+int lpf_checkpoint_size(lpf_ctx* ctx, size_t* bytes);
+int lpf_checkpoint_save(lpf_ctx* ctx, void* host_buf, size_t bytes);
+int lpf_checkpoint_load(lpf_ctx* ctx, const void* host_buf, size_t bytes);
+
 /* ---- inspection (tests, diagnostics) ------------------------------------- */
 enum {
     LPF_DBG_BANDSTATS = 1, /* double [B][6]: mean, rms, z_mean, z_rms, zeta_max, nonfinite */
@@ -281,7 +353,14 @@ enum {
     LPF_DBG_CENTRE = 5,       /* float [B][H][W] C of the last iteration          */
     LPF_DBG_SPREAD = 6,       /* float [B][H][W] S (needs debug_planes)           */
     LPF_DBG_CLIPMASK = 7,     /* uint8 [B][H][W] Y (needs debug_planes or iters>1) */
-    LPF_DBG_CACHE = 8         /* float [B][H][W] cached cube of the last step     */
+    LPF_DBG_CACHE = 8,        /* float [B][H][W] cached cube of the last step     */
+    LPF_DBG_PEAKS = 9,        /* lpf_peak [n_peaks] of the last detect, (band, row,
+                                 col) order (n_peaks from lpf_status)             */
+    LPF_DBG_EVENTS = 10,      /* lpf_source [n_new + n_ended] of the last detect:
+                                 new sources in id order, then ended episodes in
+                                 the device's list order                          */
+    LPF_DBG_PREFILTERED = 11  /* float [B][H][W] PSF-correlated detection image
+                                 of the last detect (psf_sigma > 0)               */
 };
 /* Copies an internal buffer to host memory (bytes must match); synchronises.
  * Rows of rejected bands in the centre/spread planes are unspecified. */
@@ -306,14 +385,16 @@ const char* lpf_last_error(const lpf_ctx* ctx);
 /* ---- serving loop -----------------------------------------------------------
  * Several image streams of different shapes served concurrently on one GPU
  * (Sec. 3.5: the pipeline must keep up with the 1 s cadence of the stream).
- * A dispatcher thread owned by the server takes frames in arrival order and
- * launches each on its stream's own HIP stream as soon as that stream's
- * previous frame is done, so work of different streams overlaps on the
- * device; the network runs once per dispatch round on the episodes that ended
- * in all streams whose frames completed (pooled batch).  Streams are admitted
- * while the sum of their workspaces fits the HBM budget; closing a stream
- * frees its memory for later admissions.  Server memory (workspaces, HIP
- * streams) is allocated by the server and released by close / destroy. */
+ * A dispatcher thread owned by the server works in rounds: each round takes
+ * the next frame of every idle stream that has one and runs ingest, detect
+ * and extract_flux for all of them as batch calls (lpf_*_batch: grouped
+ * launches on the server's one HIP stream), then one pooled network ticket
+ * over the episodes that ended in those streams (lpf_infer_async).  Up to
+ * four rounds are in flight; a frame is done when its round's network
+ * results are on the host.  A stream's next frame joins a round after its
+ * previous frame is done.  Streams are active while the sum of their
+ * workspaces fits the HBM budget; a stream that does not fit is refused or
+ * waits in admission order until closed streams free their share. */
 typedef struct lpf_server lpf_server;
 
 typedef struct {
@@ -322,27 +403,46 @@ typedef struct {
     int64_t arrival_ns, done_ns; /* host steady clock, as given / measured     */
     uint32_t rejected_bands;
     int32_t n_peaks, n_new, n_ended;
-    int32_t status;              /* LPF_OK or the error of this frame           */
+    int32_t status;              /* LPF_OK or the error of this frame's round:
+                                    LPF_EFULL if more episodes ended in the
+                                    round than the model's max_batch (those
+                                    beyond it are not inferred)              */
 } lpf_frame_result;
 
-/* model: network for the pooled inference (not owned).  record != 0 keeps
- * every frame's peaks, events and inference outputs for lpf_server_fetch
- * (tests; adds synchronisation per frame). */
+/* model: network for the pooled inference (not owned; the server uses its
+ * asynchronous tickets, so the model must serve no other caller meanwhile).
+ * record != 0 keeps every frame's peaks, events and inference outputs for
+ * lpf_server_fetch (tests; adds synchronisation per round).  The server
+ * creates one HIP stream (default priority) and its dispatcher thread. */
 int lpf_server_create(const lpf_model* model, size_t hbm_budget_bytes, int32_t record, lpf_server** out);
 void lpf_server_destroy(lpf_server* srv);
-/* Admits a stream if its workspace fits the remaining budget (LPF_ENOMEM
- * otherwise, nothing allocated).  *stream_id: handle for submit / close. */
-int lpf_server_admit(lpf_server* srv, const lpf_config* cfg, int32_t* stream_id);
-/* Waits for the stream's submitted frames, destroys it and frees its memory. */
+/* Admits a stream with configuration cfg (pipeline_ingest is ignored: served
+ * contexts run on the server's stream).  dev_workspace: caller-owned device
+ * memory of at least lpf_workspace_size(cfg) bytes (256-byte aligned) that
+ * outlives the stream, or NULL to let the server allocate it when the stream
+ * becomes active and free it at close.  The workspace size counts against
+ * the budget while the stream is active.  If it does not fit (or other
+ * streams are already waiting): with queue = 0 LPF_ENOMEM and nothing is
+ * kept; with queue = 1 the stream waits (frames may be submitted and are
+ * held) until lpf_server_close of other streams frees enough budget.
+ * *stream_id: handle for submit / close; *active (nullable): 1 if active
+ * now, 0 if waiting.  The sky mask and grid rows are copied. */
+int lpf_server_admit(lpf_server* srv, const lpf_config* cfg, void* dev_workspace, size_t ws_bytes,
+                     int32_t queue, int32_t* stream_id, int32_t* active);
+/* Waits for the stream's submitted frames (a waiting stream's frames are
+ * dropped), destroys it, releases its budget share (and its workspace if the
+ * server allocated it) and activates waiting streams that now fit. */
 int lpf_server_close(lpf_server* srv, int32_t stream_id);
 /* Queues one frame.  cube: [B][H][W] float32 (device memory if on_device);
  * it must stay valid until the frame is reported done.  arrival_ns: the
- * frame's arrival time on the host steady clock (latency origin). */
+ * frame's arrival time on the host steady clock (latency origin).  t must
+ * increase per stream (a frame out of order fails its round). */
 int lpf_server_submit(lpf_server* srv, int32_t stream_id, int64_t t, const float* cube, int32_t on_device,
                       int64_t arrival_ns);
 /* Completed frames since the last poll (at most cap); non-blocking. */
 int lpf_server_poll(lpf_server* srv, lpf_frame_result* out, int32_t cap, int32_t* n);
-/* Blocks until every submitted frame is done. */
+/* Blocks until every submitted frame of the active streams is done;
+ * LPF_ESTATE if waiting streams still hold frames. */
 int lpf_server_drain(lpf_server* srv);
 /* Recorded outputs of frame (stream_id, t) (record mode): peaks in (band,
  * row, col) order, events as lpf_detect, inference rows (mu [4], L [10], id)
@@ -350,7 +450,7 @@ int lpf_server_drain(lpf_server* srv);
 int lpf_server_fetch(lpf_server* srv, int32_t stream_id, int64_t t, lpf_peak* peaks, int32_t peak_cap,
                      int32_t* n_peaks, lpf_source* events, int32_t ev_cap, int32_t* n_events, float* mu,
                      float* L, int32_t* ids, int32_t inf_cap, int32_t* n_inf);
-/* Bytes of budget in use / workspace bytes a configuration would need. */
+/* Budget in use (workspaces of active streams), the budget, active streams. */
 int lpf_server_usage(const lpf_server* srv, size_t* used, size_t* budget, int32_t* n_streams);
 /* Host time server steady clock (ns), for arrival stamps. */
 int64_t lpf_now_ns(void);

@@ -6,7 +6,8 @@ this package is its thin binding.  Importing it does not touch the GPU;
 using a Context or Model without the built library raises.
 """
 
-from ._abi import (DBG, EVENT_ENDED, EVENT_NEW, KERNEL_BOX, KERNEL_GAUSS, LIB_PATH,  # noqa: F401
+from ._abi import (DBG, EVENT_ENDED, EVENT_NEW, KERNEL_BOX, KERNEL_DISK, KERNEL_GAUSS, LIB_PATH,  # noqa: F401
                    LPF_EFULL, LPF_EINVAL, LPF_OK, PEAK_DTYPE, PREC_BF16, PREC_FP16, PREC_FP32,
-                   SOURCE_DTYPE, Config, Context, LpfError, Model, Server, default_config, lib, now_ns,
-                   pack_weights, workspace_size)
+                   SOURCE_DTYPE, Config, Context, LpfError, Model, Server, default_config, detect_batch,
+                   extract_flux_batch, ingest_batch, lib, now_ns, pack_weights, select_candidates,
+                   workspace_size)

@@ -18,11 +18,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblpf.so")
 
 LPF_OK, LPF_EINVAL, LPF_ENOMEM, LPF_EFULL, LPF_EORDER, LPF_EDEVICE, LPF_ESTATE = 0, -1, -2, -3, -4, -5, -6
-KERNEL_GAUSS, KERNEL_BOX = 0, 1
+KERNEL_GAUSS, KERNEL_BOX, KERNEL_DISK = 0, 1, 2
 PREC_FP32, PREC_BF16, PREC_FP16 = 0, 1, 2
 EVENT_NEW, EVENT_ENDED = 1, 2
 DBG = dict(bandstats=1, welford_mean=2, welford_m2=3, welford_n=4, centre=5, spread=6,
-           clipmask=7, cache=8)
+           clipmask=7, cache=8, peaks=9, events=10, prefiltered=11)
 _ERRNAMES = {LPF_EINVAL: "EINVAL", LPF_ENOMEM: "ENOMEM", LPF_EFULL: "EFULL",
              LPF_EORDER: "EORDER", LPF_EDEVICE: "EDEVICE", LPF_ESTATE: "ESTATE"}
 
@@ -44,7 +44,8 @@ class Config(C.Structure):
         ("qc_band_z", C.c_float), ("qc_rms_z", C.c_float), ("qc_rms_floor", C.c_float),
         ("qc_pixel_zeta", C.c_float), ("qc_warmup", C.c_int32), ("max_sources", C.c_int32),
         ("peak_cap", C.c_int32), ("filter_precision", C.c_int32), ("debug_planes", C.c_int32),
-        ("pipeline_ingest", C.c_int32),
+        ("pipeline_ingest", C.c_int32), ("psf_sigma", C.c_float), ("psf_halfwidth", C.c_int32),
+        ("flux_bg_width", C.c_int32),
     ]
 
 
@@ -90,6 +91,9 @@ def lib() -> C.CDLL:
         "lpf_ingest_frame": (i32, [vp, i64, vp, i32, C.POINTER(C.c_uint32)]),
         "lpf_detect": (i32, [vp, vp, i32, C.POINTER(i32), vp, i32, C.POINTER(i32)]),
         "lpf_extract_flux": (i32, [vp]),
+        "lpf_ingest_batch": (i32, [vp, vp, vp, i32, i32]),
+        "lpf_detect_batch": (i32, [vp, i32]),
+        "lpf_extract_flux_batch": (i32, [vp, i32]),
         "lpf_status": (i32, [vp, C.POINTER(Status)]),
         "lpf_read_spectrum": (i32, [vp, i32, vp, vp, C.POINTER(i64)]),
         "lpf_model_weights_bytes": (sz, []),
@@ -102,13 +106,18 @@ def lib() -> C.CDLL:
         "lpf_infer_windows": (i32, [vp, vp, i32, vp, vp, vp]),
         "lpf_infer_windows_static": (i32, [vp, vp, i32, vp, vp, vp]),
         "lpf_debug_read": (i32, [vp, i32, vp, sz]),
+        "lpf_select_candidates": (i32, [vp, vp, i32, C.c_float, C.c_float, vp, vp, C.POINTER(i32)]),
+        "lpf_read_cutouts": (i32, [vp, i32, i32, i32, i64, i32, vp, vp]),
+        "lpf_checkpoint_size": (i32, [vp, C.POINTER(sz)]),
+        "lpf_checkpoint_save": (i32, [vp, vp, sz]),
+        "lpf_checkpoint_load": (i32, [vp, vp, sz]),
         "lpf_sync": (i32, [vp]),
         "lpf_profile_enable": (i32, [vp, i32]),
         "lpf_profile_read": (i32, [vp, vp, vp]),
         "lpf_last_error": (C.c_char_p, [vp]),
         "lpf_server_create": (i32, [vp, sz, i32, C.POINTER(vp)]),
         "lpf_server_destroy": (None, [vp]),
-        "lpf_server_admit": (i32, [vp, C.POINTER(Config), C.POINTER(i32)]),
+        "lpf_server_admit": (i32, [vp, C.POINTER(Config), vp, sz, i32, C.POINTER(i32), C.POINTER(i32)]),
         "lpf_server_close": (i32, [vp, i32]),
         "lpf_server_submit": (i32, [vp, i32, i64, vp, i32, i64]),
         "lpf_server_poll": (i32, [vp, vp, i32, C.POINTER(i32)]),
@@ -255,11 +264,46 @@ class Context:
             "bandstats": ((B, 6), np.float64), "welford_mean": ((B, H, W), np.float32),
             "welford_m2": ((B, H, W), np.float32), "welford_n": ((B,), np.int32),
             "centre": ((B, H, W), np.float32), "spread": ((B, H, W), np.float32),
-            "clipmask": ((B, H, W), np.uint8), "cache": ((B, H, W), np.float32)}[what]
+            "clipmask": ((B, H, W), np.uint8), "cache": ((B, H, W), np.float32),
+            "prefiltered": ((B, H, W), np.float32)}[what]
         out = np.zeros(shape, dtype=dt)
         self._check(lib().lpf_debug_read(self.h, DBG[what], C.c_void_p(out.ctypes.data), out.nbytes),
                     f"debug_read({what})")
         return out
+
+    def last_lists(self):
+        """Peaks and raw events of the last detect, read from the device
+        (for calls that returned nothing, e.g. the batch forms)."""
+        st = self.status()
+        peaks = np.zeros(st["n_peaks"], dtype=PEAK_DTYPE)
+        events = np.zeros(st["n_new"] + st["n_ended"], dtype=SOURCE_DTYPE)
+        self._check(lib().lpf_debug_read(self.h, DBG["peaks"], C.c_void_p(peaks.ctypes.data), peaks.nbytes),
+                    "debug_read(peaks)")
+        self._check(lib().lpf_debug_read(self.h, DBG["events"], C.c_void_p(events.ctypes.data), events.nbytes),
+                    "debug_read(events)")
+        return peaks, events
+
+    def read_cutouts(self, row: int, col: int, half: int, t_first: int, n_steps: int):
+        """[n_steps][B][2h+1][2h+1] boxes of the cached cubes and the cached flags."""
+        side = 2 * half + 1
+        out = np.zeros((n_steps, self.B, side, side), dtype=np.float32)
+        have = np.zeros(n_steps, dtype=np.uint8)
+        self._check(lib().lpf_read_cutouts(self.h, int(row), int(col), int(half), int(t_first), int(n_steps),
+                                           C.c_void_p(out.ctypes.data), C.c_void_p(have.ctypes.data)),
+                    "read_cutouts")
+        return out, have.astype(bool)
+
+    def checkpoint(self) -> np.ndarray:
+        """The context's state between steps as a uint8 array."""
+        n = C.c_size_t(0)
+        self._check(lib().lpf_checkpoint_size(self.h, C.byref(n)), "checkpoint_size")
+        buf = np.empty(n.value, dtype=np.uint8)
+        self._check(lib().lpf_checkpoint_save(self.h, C.c_void_p(buf.ctypes.data), buf.nbytes), "checkpoint_save")
+        return buf
+
+    def restore(self, buf: np.ndarray) -> None:
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        self._check(lib().lpf_checkpoint_load(self.h, C.c_void_p(buf.ctypes.data), buf.nbytes), "checkpoint_load")
 
     def sync(self):
         self._check(lib().lpf_sync(self.h), "sync")
@@ -281,6 +325,67 @@ class Context:
         self._check(lib().lpf_profile_read(self.h, C.c_void_p(ms.ctypes.data),
                                            C.c_void_p(cnt.ctypes.data)), "profile_read")
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(self.STAGES)}
+
+
+def select_candidates(mu: np.ndarray, L: np.ndarray, dm_min: float = 50.0, sigma_max: float = 50.0):
+    """lpf_select_candidates: (row indices ordered by sigma_DM, sigma_DM of every row)."""
+    mu = np.ascontiguousarray(mu, dtype=np.float32)
+    L = np.ascontiguousarray(L, dtype=np.float32)
+    n = len(mu)
+    idx = np.zeros(max(n, 1), dtype=np.int32)
+    sg = np.zeros(max(n, 1), dtype=np.float32)
+    k = C.c_int32(0)
+    rc = lib().lpf_select_candidates(C.c_void_p(mu.ctypes.data), C.c_void_p(L.ctypes.data), n, float(dm_min),
+                                     float(sigma_max), C.c_void_p(idx.ctypes.data), C.c_void_p(sg.ctypes.data),
+                                     C.byref(k))
+    if rc != LPF_OK:
+        raise LpfError(rc, "select_candidates")
+    return idx[:k.value].copy(), sg[:n].copy()
+
+
+def _ctx_array(ctxs: Sequence["Context"]):
+    return (C.c_void_p * len(ctxs))(*[c.h for c in ctxs])
+
+
+def _batch_check(ctxs, rc: int, what: str):
+    if rc != LPF_OK:
+        msgs = "; ".join(lib().lpf_last_error(c.h).decode() for c in ctxs if lib().lpf_last_error(c.h))
+        raise LpfError(rc, f"{what}: {msgs}")
+
+
+def ingest_batch(ctxs: Sequence["Context"], ts: Sequence[int], cubes: Sequence) -> None:
+    """lpf_ingest_batch: one cube per context, all torch CUDA tensors or all host arrays."""
+    torch = _torch()
+    holders, ptrs = [], []
+    on_dev = None
+    for c, cube in zip(ctxs, cubes):
+        if isinstance(cube, torch.Tensor):
+            assert cube.dtype == torch.float32 and cube.is_contiguous()
+            assert tuple(cube.shape) == (c.B, c.H, c.W)
+            dev = 1 if cube.is_cuda else 0
+            holders.append(cube)
+            ptrs.append(cube.data_ptr())
+        else:
+            a = np.ascontiguousarray(cube, dtype=np.float32)
+            assert a.shape == (c.B, c.H, c.W)
+            dev = 0
+            holders.append(a)
+            ptrs.append(a.ctypes.data)
+        assert on_dev is None or on_dev == dev, "cubes must all be on the device or all on the host"
+        on_dev = dev
+    parr = (C.c_void_p * len(ctxs))(*ptrs)
+    tarr = (C.c_int64 * len(ctxs))(*[int(t) for t in ts])
+    _batch_check(ctxs, lib().lpf_ingest_batch(_ctx_array(ctxs), tarr, parr, int(on_dev or 0), len(ctxs)),
+                 "ingest_batch")
+    del holders
+
+
+def detect_batch(ctxs: Sequence["Context"]) -> None:
+    _batch_check(ctxs, lib().lpf_detect_batch(_ctx_array(ctxs), len(ctxs)), "detect_batch")
+
+
+def extract_flux_batch(ctxs: Sequence["Context"]) -> None:
+    _batch_check(ctxs, lib().lpf_extract_flux_batch(_ctx_array(ctxs), len(ctxs)), "extract_flux_batch")
 
 
 LAYER_ORDER = ("conv1.w", "conv1.b", "conv2.w", "conv2.b", "conv3.w", "conv3.b",
@@ -414,17 +519,26 @@ class Server:
         self.model = model
         self._keep = {}
         self._masks = []
+        self._ws = {}       # caller-owned workspaces, released after close
+        self._active = {}
 
     def close_all(self):
         if getattr(self, "h", None) is not None:
             lib().lpf_server_destroy(self.h)
             self.h = None
             self._keep.clear()
+            self._ws.clear()
 
     def __del__(self):
         self.close_all()
 
-    def admit(self, B: int, H: int, W: int, sky_mask=None, grid_rows=None, **params) -> int:
+    def admit(self, B: int, H: int, W: int, sky_mask=None, grid_rows=None, queue: bool = False,
+              own_workspace: bool = True, **params) -> int:
+        """Admits a stream; its workspace is a torch uint8 tensor held here
+        until close (own_workspace=True), or allocated by the server when the
+        stream becomes active.  With queue=True a stream that does not fit the
+        budget waits (see is_active) instead of raising LPF_ENOMEM."""
+        torch = _torch()
         cfg = default_config(B, H, W, **params)
         keep = []
         if sky_mask is not None:
@@ -435,10 +549,17 @@ class Server:
             r = np.ascontiguousarray(grid_rows, dtype=np.int32)
             keep.append(r)
             cfg.grid_rows = r.ctypes.data
-        sid = C.c_int32(-1)
-        rc = lib().lpf_server_admit(self.h, C.byref(cfg), C.byref(sid))
+        ws, nbytes = None, 0
+        if own_workspace:
+            nbytes = workspace_size(cfg)
+            ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        sid, act = C.c_int32(-1), C.c_int32(0)
+        rc = lib().lpf_server_admit(self.h, C.byref(cfg), C.c_void_p(ws.data_ptr() if ws is not None else None),
+                                    nbytes, 1 if queue else 0, C.byref(sid), C.byref(act))
         if rc != LPF_OK:
             raise LpfError(rc, "admit")
+        self._ws[int(sid.value)] = ws
+        self._active[int(sid.value)] = bool(act.value)
         return int(sid.value)
 
     def close(self, sid: int):
@@ -447,6 +568,12 @@ class Server:
             raise LpfError(rc, "close")
         for key in [k for k in self._keep if k[0] == sid]:
             del self._keep[key]
+        self._ws.pop(int(sid), None)
+        self._active.pop(int(sid), None)
+
+    def admitted_active(self, sid: int) -> bool:
+        """Whether the stream was active when admit() returned."""
+        return self._active[int(sid)]
 
     def submit(self, sid: int, t: int, cube, arrival_ns: Optional[int] = None):
         torch = _torch()
@@ -474,7 +601,9 @@ class Server:
         return res
 
     def drain(self):
-        lib().lpf_server_drain(self.h)
+        rc = lib().lpf_server_drain(self.h)
+        if rc != LPF_OK:
+            raise LpfError(rc, "drain: frames held by waiting streams")
 
     def fetch(self, sid: int, t: int, peak_cap: int = 8192, ev_cap: int = 16384, inf_cap: int = 16384):
         peaks = np.zeros(peak_cap, dtype=PEAK_DTYPE)

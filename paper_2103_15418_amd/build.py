@@ -19,7 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblpf.so")
-SOURCES = ["api.cpp", "serve.cpp", "ingest.hip", "filter.hip", "catalog.hip", "flux.hip", "cnn.hip"]
+SOURCES = ["api.cpp", "serve.cpp", "ingest.hip", "filter.hip", "disk.hip", "catalog.hip", "flux.hip", "cnn.hip"]
 ARCH = os.environ.get("LPF_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

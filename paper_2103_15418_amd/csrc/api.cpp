@@ -57,10 +57,21 @@ int validate(const lpf_config* c, std::string* why) {
     if (c->B < 1 || c->B > kMaxB) return bad("B must be in 1..16");
     if (c->H < 1 || c->H > kMaxDim || c->W < 1 || c->W > kMaxDim) return bad("H, W must be in 1..4096");
     if (!(c->kappa >= 0.0f) || !std::isfinite(c->kappa)) return bad("kappa must be finite and >= 0");
-    if (c->kernel != LPF_KERNEL_GAUSS && c->kernel != LPF_KERNEL_BOX) return bad("unknown kernel");
+    if (c->kernel != LPF_KERNEL_GAUSS && c->kernel != LPF_KERNEL_BOX && c->kernel != LPF_KERNEL_DISK)
+        return bad("unknown kernel");
     if (c->kernel == LPF_KERNEL_GAUSS && !(c->bg_sigma > 0.0f)) return bad("bg_sigma must be > 0");
     int k = c->bg_halfwidth > 0 ? c->bg_halfwidth : (int)std::ceil(3.0 * (double)c->bg_sigma);
     if (k < 1 || k > kMaxK) return bad("background half-width must be in 1..40");
+    if (c->kernel == LPF_KERNEL_DISK &&
+        (k > disk_max_halfwidth() || c->clip_iters != 1 || c->filter_precision != LPF_PREC_FP32))
+        return bad("the disk kernel needs radius <= 32, clip_iters = 1 and float32 filters");
+    if (!(c->psf_sigma >= 0.0f) || !std::isfinite(c->psf_sigma)) return bad("psf_sigma must be finite and >= 0");
+    if (c->psf_sigma > 0.0f) {
+        const int kp = c->psf_halfwidth > 0 ? c->psf_halfwidth : (int)std::ceil(4.0 * (double)c->psf_sigma);
+        if (kp < 1 || kp > kMaxK) return bad("PSF half-width must be in 1..40");
+        if (c->filter_precision != LPF_PREC_FP32) return bad("the PSF pre-filter needs float32 filters");
+    }
+    if (c->flux_bg_width < 0 || c->flux_bg_width > 16) return bad("flux_bg_width in 0..16");
     if (c->clip_iters < 1 || c->clip_iters > kMaxIters) return bad("clip_iters must be in 1..16");
     if (c->peak_halfwidth < 1 || c->peak_halfwidth > kMaxPeakK) return bad("peak_halfwidth in 1..8");
     if (c->flux_halfwidth < 0 || c->flux_halfwidth > kMaxFluxK) return bad("flux_halfwidth in 0..8");
@@ -103,7 +114,10 @@ Derived derive(const lpf_config* c) {
     d.masked = c->sky_mask != nullptr;
     d.dyn = c->clip_iters > 1 || c->debug_planes != 0;
     d.mwords = (c->W + 31) / 32;
-    d.strip = c->W % 4 == 0 && (d.k == 15 || d.k == 24 || d.k == 36);
+    d.disk = c->kernel == LPF_KERNEL_DISK;
+    d.strip = !d.disk && c->W % 4 == 0 && (d.k == 15 || d.k == 24 || d.k == 36);
+    d.pre = c->psf_sigma > 0.0f;
+    d.kpsf = d.pre ? (c->psf_halfwidth > 0 ? c->psf_halfwidth : (int)std::ceil(4.0 * (double)c->psf_sigma)) : 0;
     size_t nb = (d.HW + 8191) / 8192;  // ~8K pixels per ingest block
     if (nb < 1) nb = 1;
     d.nblk = (int)nb;
@@ -133,7 +147,7 @@ size_t carve(const lpf_config* c, const Derived& d, char* base, DevBufs* b) {
     b->bandstats = cv.take<double>(6 * kMaxB);
     b->changed = cv.take<int32_t>((kMaxIters + 1) * kMaxB);
     b->peak_cnt = cv.take<int32_t>(kMaxB);
-    b->cand = d.strip ? cv.take<int2>(d.plane) : nullptr;
+    b->cand = (d.strip || d.disk) ? cv.take<int2>(d.plane) : nullptr;
     b->cand_cnt = cv.take<int32_t>(kMaxB);
     b->peak_raw = cv.take<PeakRec>((size_t)c->B * c->peak_cap);
     b->peak_sorted = cv.take<PeakRec>((size_t)c->B * c->peak_cap);
@@ -159,9 +173,11 @@ size_t carve(const lpf_config* c, const Derived& d, char* base, DevBufs* b) {
     b->ring_v = cv.take<uint32_t>(S * kRing);
     b->status = cv.take<DevStatus>(1);
     b->events = cv.take<lpf_source>(2 * S);
-    b->windows = nullptr;
     b->infer_slots = cv.take<int32_t>(S);
     b->infer_tend = cv.take<int64_t>(S);
+    b->pre = d.pre ? cv.take<float>(d.plane) : nullptr;
+    b->inv_den_psf = d.pre ? cv.take<float>(d.HW) : nullptr;
+    b->cutout = cv.take<float>((size_t)d.Tc * c->B * (2 * kMaxCutoutHalf + 1) * (2 * kMaxCutoutHalf + 1));
     return (cv.off + kAlign - 1) & ~(kAlign - 1);
 }
 
@@ -229,6 +245,38 @@ int flush_pending(lpf_ctx* c, hipEvent_t after) {
 }
 
 }  // namespace
+
+// 1 when the results of an asynchronous ticket are on the host, 0 if not yet,
+// negative on error or for an unknown ticket (serving loop).
+int ticket_state(lpf_model* m, int64_t ticket) {
+    const int slot = (int)(ticket % kInflight);
+    if (ticket < 0 || m->slot_ticket[slot] != ticket) return LPF_EINVAL;
+    if (m->pend_ctx[slot]) return 0;
+    const hipError_t q = hipEventQuery(m->ev_done[slot]);
+    if (q == hipSuccess) return 1;
+    return q == hipErrorNotReady ? 0 : LPF_EDEVICE;
+}
+
+// Peaks and events of a context's last detect, as lpf_detect returns them
+// (ended episodes sorted by id); synchronises (serving loop, record mode).
+int read_last_lists(lpf_ctx* c, std::vector<lpf_peak>* peaks, std::vector<lpf_source>* events) {
+    DevStatus st;
+    LPF_HIP(c, hipMemcpyAsync(&st, c->buf.status, sizeof(st), hipMemcpyDeviceToHost, c->stream), "status D2H");
+    LPF_HIP(c, hipStreamSynchronize(c->stream), "lists sync");
+    peaks->resize(std::max(st.n_peaks, 0));
+    if (!peaks->empty())
+        LPF_HIP(c, hipMemcpy(peaks->data(), c->buf.peak_sorted, peaks->size() * sizeof(lpf_peak),
+                             hipMemcpyDeviceToHost), "peaks D2H");
+    const int nev = std::max(st.n_new + st.n_ended, 0);
+    events->resize(nev);
+    if (nev > 0)
+        LPF_HIP(c, hipMemcpy(events->data(), c->buf.events, nev * sizeof(lpf_source), hipMemcpyDeviceToHost),
+                "events D2H");
+    std::sort(events->begin() + std::min(st.n_new, nev), events->end(),
+              [](const lpf_source& a, const lpf_source& b) { return a.id < b.id; });
+    return LPF_OK;
+}
+
 }  // namespace lpf
 
 using namespace lpf;
@@ -264,6 +312,9 @@ int lpf_config_default(lpf_config* c, int32_t B, int32_t H, int32_t W) {
     c->peak_cap = 512;
     c->filter_precision = LPF_PREC_FP32;
     c->debug_planes = 0;
+    c->psf_sigma = 0.0f;
+    c->psf_halfwidth = 0;
+    c->flux_bg_width = 0;
     return LPF_OK;
 }
 
@@ -315,6 +366,17 @@ int lpf_create(const lpf_config* cfg, void* ws, size_t bytes, void* stream, lpf_
         }
         for (int i = 0; i <= 2 * d.k; ++i) c->taps.g[i] = (float)(e[i] / sum);
     }
+    // PSF pre-filter taps: Gaussian of width psf_sigma normalised over [-kpsf, kpsf]
+    std::memset(&c->taps_psf, 0, sizeof(c->taps_psf));
+    if (d.pre) {
+        c->taps_psf.k = d.kpsf;
+        double sum = 0.0, e[2 * kMaxK + 1];
+        for (int u = -d.kpsf; u <= d.kpsf; ++u) {
+            e[u + d.kpsf] = std::exp(-(double)u * u / (2.0 * (double)cfg->psf_sigma * cfg->psf_sigma));
+            sum += e[u + d.kpsf];
+        }
+        for (int i = 0; i <= 2 * d.kpsf; ++i) c->taps_psf.g[i] = (float)(e[i] / sum);
+    }
     carve(cfg, d, static_cast<char*>(ws), &c->buf);
     hipStream_t s = c->stream;
     auto zero = [&](void* p, size_t n) { return p ? hipMemsetAsync(p, 0, n, s) : hipSuccess; };
@@ -335,7 +397,7 @@ int lpf_create(const lpf_config* cfg, void* ws, size_t bytes, void* stream, lpf_
     if (e == hipSuccess) e = zero(c->buf.changed, (size_t)(kMaxIters + 1) * kMaxB * sizeof(int32_t));
     if (e == hipSuccess) e = launch_table_init(c);
     if (e == hipSuccess) e = launch_pack_mask(c);
-    if (e == hipSuccess) e = launch_inv_den(c);
+    if (e == hipSuccess) e = d.disk ? launch_disk_inv_den(c) : launch_inv_den(c);
     if (e == hipSuccess && cfg->pipeline_ingest) {
         e = hipStreamCreateWithFlags(&c->ing_stream, hipStreamNonBlocking);   // default priority
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_filt, hipEventDisableTiming);
@@ -491,6 +553,350 @@ int lpf_extract_flux(lpf_ctx* c) {
     return LPF_OK;
 }
 
+// ---- batch forms: grouped launches over several contexts --------------------
+
+namespace {
+
+// Common checks of a batch call: distinct, healthy contexts on one stream,
+// none with a pipelined ingest.  Returns the shared stream through *s.
+int batch_check(lpf_ctx* const* cs, int32_t n, hipStream_t* s) {
+    if (!cs || n < 1) return LPF_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        LPF_CHECK_CTX(cs[i]);
+        if (cs[i]->stream != cs[0]->stream) return fail(cs[i], LPF_EINVAL, "batch contexts must share one stream");
+        if (cs[i]->ing_stream) return fail(cs[i], LPF_EINVAL, "batch calls need pipeline_ingest = 0");
+        for (int j = 0; j < i; ++j)
+            if (cs[j] == cs[i]) return fail(cs[i], LPF_EINVAL, "context repeated in a batch");
+    }
+    *s = cs[0]->stream;
+    return LPF_OK;
+}
+
+}  // namespace
+
+int lpf_ingest_batch(lpf_ctx* const* cs, const int64_t* t, const float* const* cubes, int32_t on_device,
+                     int32_t n) {
+    hipStream_t s = nullptr;
+    int rc = batch_check(cs, n, &s);
+    if (rc != LPF_OK) return rc;
+    if (!t || !cubes) return fail(cs[0], LPF_EINVAL, "null t or cubes");
+    for (int i = 0; i < n; ++i) {
+        lpf_ctx* c = cs[i];
+        if (!cubes[i]) return fail(c, LPF_EINVAL, "null cube");
+        if (c->phase == 1 || c->phase == 2) return fail(c, LPF_ESTATE, "ingest before detect/extract_flux finished");
+        if (c->n_frames > 0 && t[i] <= c->t_last) return fail(c, LPF_EORDER, "t must increase");
+    }
+    std::vector<int> slots(n);
+    std::vector<const float*> srcs(n);
+    for (int i = 0; i < n; ++i) {
+        lpf_ctx* c = cs[i];
+        slots[i] = pmod(t[i], c->d.Tc);
+        float* dst = c->buf.cache + (size_t)slots[i] * c->d.plane;
+        if (on_device) {
+            srcs[i] = cubes[i];
+        } else {
+            LPF_HIP(c, hipMemcpyAsync(dst, cubes[i], c->d.plane * sizeof(float), hipMemcpyHostToDevice, s),
+                    "ingest H2D");
+            srcs[i] = dst;
+        }
+    }
+    // grouped ingest passes (contexts with and without float4-aligned planes apart),
+    // then grouped QC decisions
+    for (int vec = 0; vec < 2; ++vec) {
+        std::vector<lpf_ctx*> gc;
+        std::vector<const float*> gs;
+        std::vector<int> gl;
+        for (int i = 0; i < n; ++i) {
+            if ((int)((cs[i]->d.HW % 4) == 0) != vec) continue;
+            gc.push_back(cs[i]);
+            gs.push_back(srcs[i]);
+            gl.push_back(slots[i]);
+        }
+        for (size_t k = 0; k < gc.size(); k += kGroupMax) {
+            const int m = (int)std::min<size_t>(kGroupMax, gc.size() - k);
+            LPF_HIP(gc[k], launch_ingest_group(gc.data() + k, gs.data() + k, gl.data() + k, m, on_device != 0,
+                                               vec != 0, s), "ingest");
+        }
+    }
+    for (int k = 0; k < n; k += kGroupMax) {
+        const int m = std::min(kGroupMax, n - k);
+        LPF_HIP(cs[k], launch_qc_decide_group(cs + k, slots.data() + k, t + k, m, s), "qc");
+    }
+    if (!on_device) LPF_HIP(cs[0], hipStreamSynchronize(s), "ingest sync");
+    for (int i = 0; i < n; ++i) {
+        lpf_ctx* c = cs[i];
+        if (c->n_frames == 0) c->t_start = t[i];
+        c->t_last = t[i];
+        c->n_frames++;
+        c->phase = 1;
+        c->host_n_ended = -1;
+    }
+    return LPF_OK;
+}
+
+int lpf_detect_batch(lpf_ctx* const* cs, int32_t n) {
+    hipStream_t s = nullptr;
+    int rc = batch_check(cs, n, &s);
+    if (rc != LPF_OK) return rc;
+    for (int i = 0; i < n; ++i)
+        if (cs[i]->phase != 1) return fail(cs[i], LPF_ESTATE, "detect needs a fresh ingest");
+    // filters: classes of groupable contexts share launches; the others run alone
+    std::vector<char> done(n, 0);
+    for (int i = 0; i < n; ++i) {
+        if (done[i]) continue;
+        std::vector<lpf_ctx*> gc;
+        std::vector<int> gl;
+        for (int j = i; j < n; ++j) {
+            if (done[j] || !filters_groupable(cs[i], cs[j])) continue;
+            done[j] = 1;
+            gc.push_back(cs[j]);
+            gl.push_back(pmod(cs[j]->t_last, cs[j]->d.Tc));
+        }
+        if (gc.empty()) {
+            done[i] = 1;
+            LPF_HIP(cs[i], launch_filters(cs[i], pmod(cs[i]->t_last, cs[i]->d.Tc)), "filters");
+            continue;
+        }
+        for (size_t k = 0; k < gc.size(); k += kGroupMax) {
+            const int m = (int)std::min<size_t>(kGroupMax, gc.size() - k);
+            LPF_HIP(gc[k], launch_filters_group(gc.data() + k, gl.data() + k, m, s), "filters");
+        }
+    }
+    std::vector<int64_t> ts(n);
+    for (int i = 0; i < n; ++i) ts[i] = cs[i]->t_last;
+    for (int k = 0; k < n; k += kGroupMax) {
+        const int m = std::min(kGroupMax, n - k);
+        LPF_HIP(cs[k], launch_catalog_group(cs + k, ts.data() + k, m, s), "catalog");
+    }
+    for (int i = 0; i < n; ++i) cs[i]->phase = 2;
+    return LPF_OK;
+}
+
+int lpf_extract_flux_batch(lpf_ctx* const* cs, int32_t n) {
+    hipStream_t s = nullptr;
+    int rc = batch_check(cs, n, &s);
+    if (rc != LPF_OK) return rc;
+    for (int i = 0; i < n; ++i)
+        if (cs[i]->phase != 2) return fail(cs[i], LPF_ESTATE, "extract_flux needs detect first");
+    std::vector<int64_t> ts(n);
+    for (int i = 0; i < n; ++i) ts[i] = cs[i]->t_last;
+    for (int k = 0; k < n; k += kGroupMax) {
+        const int m = std::min(kGroupMax, n - k);
+        LPF_HIP(cs[k], launch_flux_group(cs + k, ts.data() + k, m, s), "flux");
+    }
+    for (int i = 0; i < n; ++i) cs[i]->phase = 3;
+    return LPF_OK;
+}
+
+// ---- candidate selection and image cutouts (Sec. 2.3.1, Sec. 3.3-3.4) ---------
+
+int lpf_select_candidates(const float* mu, const float* L, int32_t n, float dm_min, float sigma_max,
+                          int32_t* idx_out, float* sigma_out, int32_t* n_out) {
+    if (n < 0 || !n_out || (n > 0 && (!mu || !L || !idx_out))) return LPF_EINVAL;
+    // Sigma = L L^T with L packed row by row: Sigma_00 = L_00^2, so sigma_DM = |L_00|
+    std::vector<int32_t> keep;
+    for (int i = 0; i < n; ++i) {
+        const float sg = std::fabs(L[(size_t)i * 10]);
+        if (sigma_out) sigma_out[i] = sg;
+        if (mu[(size_t)i * 4] > dm_min && sg <= sigma_max) keep.push_back(i);
+    }
+    std::stable_sort(keep.begin(), keep.end(),
+                     [&](int32_t a, int32_t b) { return std::fabs(L[(size_t)a * 10]) < std::fabs(L[(size_t)b * 10]); });
+    std::copy(keep.begin(), keep.end(), idx_out);
+    *n_out = (int32_t)keep.size();
+    return LPF_OK;
+}
+
+int lpf_read_cutouts(lpf_ctx* c, int32_t row, int32_t col, int32_t half, int64_t t_first, int32_t n_steps,
+                     float* out, uint8_t* have) {
+    LPF_CHECK_CTX(c);
+    if (!out || half < 0 || half > kMaxCutoutHalf || n_steps < 1 || n_steps > c->d.Tc)
+        return fail(c, LPF_EINVAL, "cutout: half in 0..32, 1 <= n_steps <= cache depth, out non-null");
+    if (c->ing_stream) LPF_HIP(c, hipStreamSynchronize(c->ing_stream), "cutout sync");
+    LPF_HIP(c, launch_cutouts(c, row, col, half, t_first, n_steps), "cutout");
+    const size_t side = (size_t)(2 * half + 1);
+    const size_t nval = (size_t)n_steps * c->cfg.B * side * side;
+    LPF_HIP(c, hipMemcpyAsync(out, c->buf.cutout, nval * sizeof(float), hipMemcpyDeviceToHost, c->stream), "cutout D2H");
+    std::vector<int64_t> ct(c->d.Tc);
+    LPF_HIP(c, hipMemcpyAsync(ct.data(), c->buf.cache_t, c->d.Tc * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream),
+            "cutout D2H");
+    LPF_HIP(c, hipStreamSynchronize(c->stream), "cutout sync");
+    if (have)
+        for (int k = 0; k < n_steps; ++k) {
+            const int64_t tau = t_first + k;
+            have[k] = (c->n_frames > 0 && ct[pmod(tau, c->d.Tc)] == tau) ? 1 : 0;
+        }
+    return LPF_OK;
+}
+
+// ---- checkpoint / resume ----------------------------------------------------
+
+namespace {
+
+constexpr char kCkptMagic[8] = {'L', 'P', 'F', 'C', 'K', 'P', 'T', '1'};
+
+// Fixed part of a checkpoint: the configuration values that fix the state's
+// layout and meaning, and the host-side step bookkeeping.
+struct CkptHeader {
+    char magic[8];
+    int32_t B, H, W, k, Tc, max_sources, peak_cap, kernel, clip_iters, peak_halfwidth, flux_halfwidth;
+    int32_t monitor_steps, backfill_steps, qc_warmup, pipeline_ingest, filter_precision, masked, n_regions;
+    float kappa, bg_sigma, dup_radius, assoc_radius, qc_band_z, qc_rms_z, qc_rms_floor, qc_pixel_zeta;
+    int32_t grid_rows[kMaxB];
+    int64_t t_last, t_start, n_frames;
+    int32_t phase, pad;
+};
+
+CkptHeader ckpt_header(const lpf_ctx* c, int n_regions) {
+    CkptHeader h;
+    std::memset(&h, 0, sizeof(h));
+    std::memcpy(h.magic, kCkptMagic, sizeof(kCkptMagic));
+    const lpf_config& f = c->cfg;
+    h.B = f.B; h.H = f.H; h.W = f.W; h.k = c->d.k; h.Tc = c->d.Tc; h.max_sources = f.max_sources;
+    h.peak_cap = f.peak_cap; h.kernel = f.kernel; h.clip_iters = f.clip_iters; h.peak_halfwidth = f.peak_halfwidth;
+    h.flux_halfwidth = f.flux_halfwidth; h.monitor_steps = f.monitor_steps; h.backfill_steps = f.backfill_steps;
+    h.qc_warmup = f.qc_warmup; h.pipeline_ingest = f.pipeline_ingest; h.filter_precision = f.filter_precision;
+    h.masked = c->d.masked ? 1 : 0; h.n_regions = n_regions;
+    h.kappa = f.kappa; h.bg_sigma = f.bg_sigma; h.dup_radius = f.dup_radius; h.assoc_radius = f.assoc_radius;
+    h.qc_band_z = f.qc_band_z; h.qc_rms_z = f.qc_rms_z; h.qc_rms_floor = f.qc_rms_floor;
+    h.qc_pixel_zeta = f.qc_pixel_zeta;
+    for (int b = 0; b < kMaxB; ++b) h.grid_rows[b] = b < f.B ? c->grid_rows[b] : 0;
+    h.t_last = c->t_last; h.t_start = c->t_start; h.n_frames = c->n_frames; h.phase = c->phase;
+    return h;
+}
+
+struct Region {
+    void* p;
+    size_t bytes;
+};
+
+// Device state carried from one step to the next (D4-D7 and what a call
+// after the last step may still read): image cache and its stamps, running
+// QC statistics, sky mask, source table, free list, the last step's lists,
+// counters, events and peaks, and the dynamic-spectrum rings.  Per-step
+// scratch (filter planes, partials, candidate lists, catalogue scratch) is
+// not part of it.
+std::vector<Region> state_regions(lpf_ctx* c) {
+    const DevBufs& b = c->buf;
+    const size_t S = (size_t)c->cfg.max_sources, plane = c->d.plane, Tc = (size_t)c->d.Tc;
+    const size_t B = (size_t)c->cfg.B;
+    return {
+        {b.cache, Tc * plane * sizeof(float)},
+        {b.cache_t, Tc * sizeof(int64_t)},
+        {b.cache_rej, Tc * sizeof(uint32_t)},
+        {b.wf_mean, 2 * plane * sizeof(float)},
+        {b.wf_m2, 2 * plane * sizeof(float)},
+        {b.wf_n, kMaxB * sizeof(int32_t)},
+        {b.wf_cur, kMaxB * sizeof(int32_t)},
+        {b.mask, c->d.HW},
+        {b.bandstats, 6 * kMaxB * sizeof(double)},
+        {b.free_list, S * sizeof(int32_t)},
+        {b.src_id, S * sizeof(int32_t)},
+        {b.src_row, S * sizeof(int32_t)},
+        {b.src_col, S * sizeof(int32_t)},
+        {b.src_state, S * sizeof(int32_t)},
+        {b.src_tfirst, S * sizeof(int64_t)},
+        {b.src_tlast, S * sizeof(int64_t)},
+        {b.src_tend, S * sizeof(int64_t)},
+        {b.src_new, S * sizeof(int32_t)},
+        {b.list_measured, S * sizeof(int2)},
+        {b.list_new, S * sizeof(int2)},
+        {b.list_ended, S * sizeof(int32_t)},
+        {b.ring, S * B * kRing * sizeof(float)},
+        {b.ring_t, S * kRing * sizeof(int64_t)},
+        {b.ring_v, S * kRing * sizeof(uint32_t)},
+        {b.status, sizeof(DevStatus)},
+        {b.events, 2 * S * sizeof(lpf_source)},
+        {b.peak_sorted, B * (size_t)c->cfg.peak_cap * sizeof(PeakRec)},
+    };
+}
+
+size_t ckpt_bytes(lpf_ctx* c) {
+    size_t n = sizeof(CkptHeader);
+    for (const Region& r : state_regions(c)) n += sizeof(uint64_t) + r.bytes;
+    return n;
+}
+
+}  // namespace
+
+int lpf_checkpoint_size(lpf_ctx* c, size_t* bytes) {
+    LPF_CHECK_CTX(c);
+    if (!bytes) return fail(c, LPF_EINVAL, "null size");
+    *bytes = ckpt_bytes(c);
+    return LPF_OK;
+}
+
+int lpf_checkpoint_save(lpf_ctx* c, void* host, size_t bytes) {
+    LPF_CHECK_CTX(c);
+    if (!host) return fail(c, LPF_EINVAL, "null buffer");
+    if (c->phase == 1 || c->phase == 2) return fail(c, LPF_ESTATE, "checkpoint between steps only (after extract_flux)");
+    if (bytes < ckpt_bytes(c)) return fail(c, LPF_ENOMEM, "checkpoint buffer too small");
+    if (c->ing_stream) LPF_HIP(c, hipStreamSynchronize(c->ing_stream), "checkpoint sync");
+    LPF_HIP(c, hipStreamSynchronize(c->stream), "checkpoint sync");
+    const std::vector<Region> regs = state_regions(c);
+    const CkptHeader h = ckpt_header(c, (int)regs.size());
+    char* p = static_cast<char*>(host);
+    std::memcpy(p, &h, sizeof(h));
+    p += sizeof(h);
+    for (const Region& r : regs) {
+        const uint64_t n = r.bytes;
+        std::memcpy(p, &n, sizeof(n));
+        p += sizeof(n);
+        LPF_HIP(c, hipMemcpy(p, r.p, r.bytes, hipMemcpyDeviceToHost), "checkpoint D2H");
+        p += r.bytes;
+    }
+    return LPF_OK;
+}
+
+int lpf_checkpoint_load(lpf_ctx* c, const void* host, size_t bytes) {
+    LPF_CHECK_CTX(c);
+    if (!host) return fail(c, LPF_EINVAL, "null buffer");
+    if (c->n_frames != 0 || c->phase != 0) return fail(c, LPF_ESTATE, "load into a context that has taken no step");
+    if (bytes < sizeof(CkptHeader)) return fail(c, LPF_EINVAL, "not a checkpoint");
+    CkptHeader h;
+    std::memcpy(&h, host, sizeof(h));
+    const std::vector<Region> regs = state_regions(c);
+    CkptHeader mine = ckpt_header(c, (int)regs.size());
+    if (std::memcmp(h.magic, kCkptMagic, sizeof(kCkptMagic)) != 0) return fail(c, LPF_EINVAL, "not a checkpoint");
+    // everything but the step bookkeeping must match this context
+    mine.t_last = h.t_last;
+    mine.t_start = h.t_start;
+    mine.n_frames = h.n_frames;
+    mine.phase = h.phase;
+    if (std::memcmp(&h, &mine, sizeof(h)) != 0)
+        return fail(c, LPF_EINVAL, "checkpoint of a different configuration");
+    if (bytes < ckpt_bytes(c)) return fail(c, LPF_EINVAL, "checkpoint truncated");
+    const char* p = static_cast<const char*>(host) + sizeof(h);
+    LPF_HIP(c, hipStreamSynchronize(c->stream), "checkpoint sync");
+    // the sky mask is part of the configuration: it must equal this context's
+    std::vector<uint8_t> cur(c->d.HW);
+    for (const Region& r : regs) {
+        uint64_t n = 0;
+        std::memcpy(&n, p, sizeof(n));
+        p += sizeof(n);
+        if (n != r.bytes) return fail(c, LPF_EINVAL, "checkpoint region size mismatch");
+        if (r.p == c->buf.mask) {
+            LPF_HIP(c, hipMemcpy(cur.data(), r.p, r.bytes, hipMemcpyDeviceToHost), "mask D2H");
+            if (std::memcmp(cur.data(), p, r.bytes) != 0) return fail(c, LPF_EINVAL, "checkpoint of a different sky mask");
+        }
+        p += r.bytes;
+    }
+    p = static_cast<const char*>(host) + sizeof(h);
+    for (const Region& r : regs) {
+        p += sizeof(uint64_t);
+        LPF_HIP(c, hipMemcpy(r.p, p, r.bytes, hipMemcpyHostToDevice), "checkpoint H2D");
+        p += r.bytes;
+    }
+    c->t_last = h.t_last;
+    c->t_start = h.t_start;
+    c->n_frames = h.n_frames;
+    c->phase = h.phase;
+    c->host_n_ended = -1;
+    c->filt_recorded = false;
+    c->qc_pending = false;
+    return LPF_OK;
+}
+
 int lpf_status(lpf_ctx* c, lpf_status_t* out) {
     LPF_CHECK_CTX(c);
     if (!out) return LPF_EINVAL;
@@ -572,6 +978,23 @@ int lpf_debug_read(lpf_ctx* c, int32_t what, void* host, size_t bytes) {
             src = c->buf.clip + (size_t)(c->cfg.clip_iters & 1) * plane; need = plane; break;
         case LPF_DBG_CACHE:
             src = c->buf.cache + (size_t)pmod(c->t_last, c->d.Tc) * plane; need = plane * sizeof(float); break;
+        case LPF_DBG_PREFILTERED:
+            if (!c->buf.pre) return fail(c, LPF_EINVAL, "no PSF pre-filter (psf_sigma = 0)");
+            src = c->buf.pre; need = plane * sizeof(float); break;
+        case LPF_DBG_PEAKS:
+        case LPF_DBG_EVENTS: {
+            DevStatus st;
+            LPF_HIP(c, hipMemcpy(&st, c->buf.status, sizeof(st), hipMemcpyDeviceToHost), "status D2H");
+            if (what == LPF_DBG_PEAKS) {
+                src = c->buf.peak_sorted;
+                need = (size_t)std::max(st.n_peaks, 0) * sizeof(lpf_peak);
+            } else {
+                src = c->buf.events;
+                need = (size_t)std::max(st.n_new + st.n_ended, 0) * sizeof(lpf_source);
+            }
+            if (need == 0 && bytes == 0) return LPF_OK;
+            break;
+        }
         case LPF_DBG_WELFORD_MEAN:
         case LPF_DBG_WELFORD_M2: {
             need = plane * sizeof(float);

@@ -230,7 +230,7 @@ __device__ inline float dist2(int a, int b) {
     return di * di + dj * dj;
 }
 
-__global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
+__device__ __forceinline__ void catalog_body(const CatArgs& a) {
     __shared__ uint64_t s_keys[kCatMaxPeaks];        // 64 KB: sort keys / neighbour lists / live lists
     __shared__ int32_t s_pos[kCatMaxPeaks];          // 32 KB: positions in visiting order
     __shared__ uint8_t s_flag[kCatMaxPeaks];         //  8 KB: kept flags
@@ -824,6 +824,13 @@ __global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
     }
 }
 
+__global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) { catalog_body(a); }
+
+// Grouped: workgroup i runs the catalogue step of context i.
+__global__ __launch_bounds__(kCatThreads) void k_catalog_group(Grouped<CatArgs> g) {
+    catalog_body(g.a[blockIdx.x]);
+}
+
 __global__ void k_table_init(int32_t* src_state, int S, int64_t* cache_t, uint32_t* cache_rej, int Tc,
                              DevStatus* status) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -845,7 +852,7 @@ inline int pmod_host(int64_t a, int m) {
     return (int)(r < 0 ? r + m : r);
 }
 
-hipError_t launch_catalog(lpf_ctx* c, int64_t t) {
+CatArgs catalog_args(lpf_ctx* c, int64_t t) {
     CatArgs a;
     a.B = c->cfg.B;
     a.peak_cap = c->cfg.peak_cap;
@@ -860,11 +867,11 @@ hipError_t launch_catalog(lpf_ctx* c, int64_t t) {
     a.n_changed = (kMaxIters + 1) * c->cfg.B;
     a.peak_sorted = c->buf.peak_sorted;
     // the strip filters of one clip iteration leave the peak test to this kernel
-    const bool deferred = c->d.strip && c->cfg.clip_iters == 1;
+    const bool deferred = (c->d.strip || c->d.disk) && c->cfg.clip_iters == 1;
     a.pk_cand = deferred ? c->buf.cand : nullptr;
     a.pk_cand_cnt = c->buf.cand_cnt;
     a.pk_cap = (int)std::min<size_t>(c->d.plane, (size_t)INT32_MAX);
-    a.X = c->buf.cache + (size_t)pmod_host(t, c->d.Tc) * c->d.plane;
+    a.X = c->d.pre ? c->buf.pre : c->buf.cache + (size_t)pmod_host(t, c->d.Tc) * c->d.plane;
     a.C = c->buf.centre;
     a.M = c->d.masked ? c->buf.mask : nullptr;
     a.H = c->cfg.H;
@@ -890,7 +897,24 @@ hipError_t launch_catalog(lpf_ctx* c, int64_t t) {
     a.ring_t = c->buf.ring_t;
     a.status = c->buf.status;
     a.events = c->buf.events;
-    hipLaunchKernelGGL(k_catalog, dim3(1), dim3(kCatThreads), 0, c->stream, a);
+    return a;
+}
+
+hipError_t launch_catalog(lpf_ctx* c, int64_t t) {
+    hipLaunchKernelGGL(k_catalog, dim3(1), dim3(kCatThreads), 0, c->stream, catalog_args(c, t));
+    return hipGetLastError();
+}
+
+hipError_t launch_catalog_group(lpf_ctx* const* cs, const int64_t* ts, int n, hipStream_t s) {
+    static_assert(sizeof(Grouped<CatArgs>) <= 4096, "grouped kernel arguments exceed 4 KiB");
+    Grouped<CatArgs> g{};
+    g.gi.n = n;
+    for (int i = 0; i < n; ++i) {
+        g.a[i] = catalog_args(cs[i], ts[i]);
+        g.gi.start[i] = i;
+    }
+    g.gi.start[n] = n;
+    hipLaunchKernelGGL(k_catalog_group, dim3(n), dim3(kCatThreads), 0, s, g);
     return hipGetLastError();
 }
 

@@ -27,6 +27,8 @@
 #include <cmath>
 #include <cstdlib>
 
+#include <cstring>
+
 #include "lpf_internal.h"
 
 namespace lpf {
@@ -785,15 +787,14 @@ struct StripGeo {
 };
 constexpr int kStripThreads = 256;
 
+// Workgroup lin of one context's launch (band-major over strips and tiles).
 template <int K, int IN, int OUT>
-__global__ __launch_bounds__(kStripThreads) void k_filter_strip(FiltArgs a, Taps tp) {
+__device__ __forceinline__ void strip_body(const FiltArgs& a, const Taps& tp, int lin, float* lds) {
     typedef StripGeo<K> G;
-    __shared__ __attribute__((aligned(16))) float lds[G::LDS_FLOATS];
     float* stage = lds;
     float* ring = lds + 32 * G::SW;   // [64 columns][RT]
     const int strips_y = (a.H + a.strip_h - 1) / a.strip_h;
     const int per_band = a.tiles_x * strips_y;
-    const int lin = xcd_remap(blockIdx.x, gridDim.x);
     const int b = lin / per_band;
     const int rem = lin % per_band;
     if (a.rej && ((*a.rej >> b) & 1u)) return;
@@ -936,6 +937,22 @@ __global__ __launch_bounds__(kStripThreads) void k_filter_strip(FiltArgs a, Taps
         const int j = bi - (G::NB - 1);
         if (j >= 0) col_pass(j);
     }
+}
+
+template <int K, int IN, int OUT>
+__global__ __launch_bounds__(kStripThreads) void k_filter_strip(FiltArgs a, Taps tp) {
+    __shared__ __attribute__((aligned(16))) float lds[StripGeo<K>::LDS_FLOATS];
+    strip_body<K, IN, OUT>(a, tp, xcd_remap(blockIdx.x, gridDim.x), lds);
+}
+
+// Grouped launch over contexts with the same taps: the XCD-aware order runs
+// over the whole grid, then each workgroup finds its context.
+template <int K, int IN, int OUT>
+__global__ __launch_bounds__(kStripThreads) void k_filter_strip_group(Grouped<FiltArgs> g, Taps tp) {
+    __shared__ __attribute__((aligned(16))) float lds[StripGeo<K>::LDS_FLOATS];
+    const int lin = xcd_remap(blockIdx.x, gridDim.x);
+    const int i = group_of(g.gi, lin);
+    strip_body<K, IN, OUT>(g.a[i], tp, lin - g.gi.start[i], lds);
 }
 
 // 16-bit precision form of the strip kernels (bf16 / fp16 operands, float32
@@ -1163,8 +1180,8 @@ __global__ void k_detect_init(int32_t* peak_cnt, int32_t* cand_cnt, int32_t* cha
 
 // Marks bands active for the next iteration: active = not rejected and changed.
 template <int K, int IN, int OUT>
-hipError_t run_filter(lpf_ctx* c, const FiltArgs& a, int nbands) {
-    const int k = c->d.k;
+hipError_t run_filter_t(lpf_ctx* c, const FiltArgs& a, int nbands, const Taps& tp) {
+    const int k = tp.k;
     const int sw = ((kTileW + 2 * k + 3) & ~3) + 4;
     const size_t lds = sizeof(float) * (64 * sw + (kTileH + 2 * k) * (kTileW + 1));
     const int nblocks = a.tiles_x * a.tiles_y * nbands;
@@ -1172,8 +1189,13 @@ hipError_t run_filter(lpf_ctx* c, const FiltArgs& a, int nbands) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kFiltThreads), lds, c->stream, a, c->taps);
+    hipLaunchKernelGGL(kern, dim3(nblocks), dim3(kFiltThreads), lds, c->stream, a, tp);
     return hipGetLastError();
+}
+
+template <int K, int IN, int OUT>
+hipError_t run_filter(lpf_ctx* c, const FiltArgs& a, int nbands) {
+    return run_filter_t<K, IN, OUT>(c, a, nbands, c->taps);
 }
 
 template <int K, int IN, int OUT>
@@ -1282,7 +1304,8 @@ hipError_t dispatch_k(lpf_ctx* c, const FiltArgs& a, int nbands) {
 
 FiltArgs base_args(lpf_ctx* c, int slot) {
     FiltArgs a{};
-    a.X = c->buf.cache + (size_t)slot * c->d.plane;
+    // detection runs on the PSF-correlated image when the pre-filter is on
+    a.X = c->d.pre ? c->buf.pre : c->buf.cache + (size_t)slot * c->d.plane;
     a.C = c->buf.centre;
     a.M = c->d.masked ? c->buf.mask : nullptr;
     a.Y = c->buf.clip;
@@ -1307,6 +1330,38 @@ FiltArgs base_args(lpf_ctx* c, int slot) {
     return a;
 }
 
+// Grouped strip pass over contexts sharing K and the taps: each context keeps
+// the strip height and workgroup order of its own launch, so its results are
+// bitwise those of the per-context launch.
+template <int K, int IN, int OUT>
+hipError_t run_strip_group(lpf_ctx* const* cs, const FiltArgs* as, int n, hipStream_t s) {
+    static_assert(sizeof(Grouped<FiltArgs>) + sizeof(Taps) <= 4096, "grouped kernel arguments exceed 4 KiB");
+    Grouped<FiltArgs> g{};
+    g.gi.n = n;
+    int total = 0;
+    for (int i = 0; i < n; ++i) {
+        FiltArgs a = as[i];
+        a.tiles_x = (a.W + kTileW - 1) / kTileW;
+        a.strip_h = strip_height(a.H, a.tiles_x, a.B, 1024);
+        g.a[i] = a;
+        g.gi.start[i] = total;
+        total += a.tiles_x * ((a.H + a.strip_h - 1) / a.strip_h) * a.B;
+    }
+    g.gi.start[n] = total;
+    hipLaunchKernelGGL((k_filter_strip_group<K, IN, OUT>), dim3(total), dim3(kStripThreads), 0, s, g, cs[0]->taps);
+    return hipGetLastError();
+}
+
+template <int IN, int OUT>
+hipError_t dispatch_strip_group(lpf_ctx* const* cs, const FiltArgs* as, int n, hipStream_t s) {
+    switch (cs[0]->d.k) {
+        case 15: return run_strip_group<15, IN, OUT>(cs, as, n, s);
+        case 24: return run_strip_group<24, IN, OUT>(cs, as, n, s);
+        case 36: return run_strip_group<36, IN, OUT>(cs, as, n, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_pack_mask(lpf_ctx* c) {
@@ -1323,7 +1378,19 @@ hipError_t launch_inv_den(lpf_ctx* c) {
     a.M = c->d.masked ? c->buf.mask : nullptr;
     a.out = c->buf.inv_den;
     a.rej = nullptr;
-    return dispatch_k<IN_M, OUT_INV_DEN>(c, a, 1);
+    hipError_t e = dispatch_k<IN_M, OUT_INV_DEN>(c, a, 1);
+    if (e != hipSuccess || !c->d.pre) return e;
+    a.out = c->buf.inv_den_psf;
+    return run_filter_t<0, IN_M, OUT_INV_DEN>(c, a, 1, c->taps_psf);
+}
+
+// PSF pre-filter: pre = (G_psf * (M X)) / (G_psf * M) of this step's cube.
+hipError_t launch_prefilter(lpf_ctx* c, int slot) {
+    FiltArgs a = base_args(c, slot);
+    a.X = c->buf.cache + (size_t)slot * c->d.plane;
+    a.out = c->buf.pre;
+    a.inv_den = c->buf.inv_den_psf;
+    return run_filter_t<0, IN_MX, OUT_C_STATIC>(c, a, c->cfg.B, c->taps_psf);
 }
 
 // Clip planes: clip[j] = buf.clip + j * plane, j = 0, 1.  Iteration 1 writes
@@ -1337,6 +1404,16 @@ hipError_t launch_filters(lpf_ctx* c, int slot) {
     uint8_t* clip0 = c->buf.clip;
     uint8_t* clip1 = c->buf.clip ? c->buf.clip + plane : nullptr;
     hipError_t e;
+    if (c->d.pre) {
+        StageTimer tm(c, 2);
+        if ((e = launch_prefilter(c, slot)) != hipSuccess) return e;
+    }
+    if (c->d.disk) {
+        StageTimer tm(c, 3);
+        e = launch_disk_filters(c, base_args(c, slot).X, c->buf.cache_rej + slot, c->stream);
+        if (e == hipSuccess && c->ev_centre) e = hipEventRecord(c->ev_centre, c->stream);
+        return e;
+    }
     FiltArgs a = base_args(c, slot);
     a.out = c->buf.centre;
     a.E_out = c->buf.resid;
@@ -1393,6 +1470,36 @@ hipError_t launch_filters(lpf_ctx* c, int slot) {
     if (gx > 1024) gx = 1024;
     hipLaunchKernelGGL(k_peaks_planes, dim3(gx, B), dim3(256), 0, c->stream, p);
     return hipGetLastError();
+}
+
+// Contexts whose filter passes can share one launch: float32 strip kernels,
+// one clip iteration, the same half-width and taps.
+bool filters_groupable(const lpf_ctx* a, const lpf_ctx* b) {
+    auto ok = [](const lpf_ctx* c) {
+        return c->d.strip && c->cfg.filter_precision == LPF_PREC_FP32 && c->cfg.clip_iters == 1 && !c->ing_stream;
+    };
+    return ok(a) && ok(b) && a->d.k == b->d.k && std::memcmp(a->taps.g, b->taps.g, sizeof(a->taps.g)) == 0;
+}
+
+// The filter passes of launch_filters for n <= kGroupMax groupable contexts
+// (their cubes in cache slots slots[i]) as two grouped launches on stream s.
+hipError_t launch_filters_group(lpf_ctx* const* cs, const int* slots, int n, hipStream_t s) {
+    FiltArgs as[kGroupMax];
+    for (int i = 0; i < n; ++i) {
+        lpf_ctx* c = cs[i];
+        as[i] = base_args(c, slots[i]);
+        as[i].out = c->buf.centre;
+        as[i].E_out = c->buf.resid;
+    }
+    hipError_t e = dispatch_strip_group<IN_MX, OUT_C_E>(cs, as, n, s);
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < n; ++i) {
+        lpf_ctx* c = cs[i];
+        as[i] = base_args(c, slots[i]);
+        as[i].S_out = c->d.dyn ? c->buf.spread : nullptr;
+        as[i].Y_out = c->d.dyn ? c->buf.clip + c->d.plane : nullptr;
+    }
+    return dispatch_strip_group<IN_E, OUT_S_PEAKS>(cs, as, n, s);
 }
 
 }  // namespace lpf

@@ -22,6 +22,7 @@ struct FluxArgs {
     const int64_t* cache_t;   // [Tc]
     const uint32_t* cache_rej;
     int Tc, B, H, W, kf, T_bf;
+    int bgw;                  // > 0: subtract the mean of the annulus this wide around the box
     int64_t t, t_start;
     size_t plane;
     const int2* list;         // measured sources (slot, row << 16 | col)
@@ -80,6 +81,29 @@ __device__ inline float box_max_any(const float* img, int H, int W, int i, int j
     return k == 2 ? box_max_k<2>(img, H, W, i, j) : box_max(img, H, W, i, j, k);
 }
 
+// Flux of one band: the box maximum, or with bgw > 0 the box maximum minus
+// the mean of the pixels at Chebyshev distance k+1 .. k+bgw inside the image
+// (a local background), summed in float64 row by row and rounded once.
+__device__ inline float flux_value(const float* img, int H, int W, int i, int j, int k, int bgw) {
+    const float m = box_max_any(img, H, W, i, j, k);
+    if (bgw <= 0) return m;
+    const int r0 = i - k - bgw < 0 ? 0 : i - k - bgw, r1 = i + k + bgw >= H ? H - 1 : i + k + bgw;
+    const int c0 = j - k - bgw < 0 ? 0 : j - k - bgw, c1 = j + k + bgw >= W ? W - 1 : j + k + bgw;
+    double tot = 0.0;
+    int n = 0;
+    for (int r = r0; r <= r1; ++r) {
+        const int dr = r > i ? r - i : i - r;
+        for (int c = c0; c <= c1; ++c) {
+            const int dc = c > j ? c - j : j - c;
+            if ((dr > dc ? dr : dc) <= k) continue;
+            tot += (double)img[(size_t)r * W + c];
+            ++n;
+        }
+    }
+    const double mean = n > 0 ? tot / (double)n : 0.0;
+    return (float)((double)m - mean);
+}
+
 // Current step: every measured source, every band (blocks [0, flux_blocks)),
 // and the backward fill of the sources opened at this step (the other
 // blocks; their steps precede t by less than the ring length, so the two
@@ -87,9 +111,17 @@ __device__ inline float box_max_any(const float* img, int H, int W, int i, int j
 __device__ void flux_part(const FluxArgs& a, int blk, int nblk);
 __device__ void backfill_part(const FluxArgs& a, int blk, int nblk);
 
-__global__ __launch_bounds__(256) void k_flux(FluxArgs a) {
-    if ((int)blockIdx.x < a.flux_blocks) flux_part(a, blockIdx.x, a.flux_blocks);
-    else backfill_part(a, blockIdx.x - a.flux_blocks, gridDim.x - a.flux_blocks);
+__device__ __forceinline__ void flux_block(const FluxArgs& a, int blk, int nblk) {
+    if (blk < a.flux_blocks) flux_part(a, blk, a.flux_blocks);
+    else backfill_part(a, blk - a.flux_blocks, nblk - a.flux_blocks);
+}
+
+__global__ __launch_bounds__(256) void k_flux(FluxArgs a) { flux_block(a, blockIdx.x, gridDim.x); }
+
+// Grouped: context i owns workgroups [start[i], start[i+1]).
+__global__ __launch_bounds__(256) void k_flux_group(Grouped<FluxArgs> g) {
+    const int i = group_of(g.gi, blockIdx.x);
+    flux_block(g.a[i], blockIdx.x - g.gi.start[i], g.gi.start[i + 1] - g.gi.start[i]);
 }
 
 // The first entry of each lane is read with the count (used only below it),
@@ -109,8 +141,8 @@ __device__ void flux_part(const FluxArgs& a, int blk, int nblk) {
         const int b = (int)(w % a.B);
         const float f = ((rej >> b) & 1u)
                             ? 0.0f
-                            : box_max_any(frame + (size_t)b * a.H * a.W, a.H, a.W, e.y >> 16, e.y & 0xffff,
-                                          a.kf);
+                            : flux_value(frame + (size_t)b * a.H * a.W, a.H, a.W, e.y >> 16, e.y & 0xffff,
+                                         a.kf, a.bgw);
         a.ring[((size_t)s * a.B + b) * kRing + ri] = f;
         if (b == 0) {
             a.ring_t[(size_t)s * kRing + ri] = a.t;
@@ -143,8 +175,8 @@ __device__ void backfill_part(const FluxArgs& a, int blk, int nblk) {
         const float* frame = a.cache + (size_t)cs * a.plane;
         const float f = ((rej >> b) & 1u)
                             ? 0.0f
-                            : box_max_any(frame + (size_t)b * a.H * a.W, a.H, a.W, e.y >> 16, e.y & 0xffff,
-                                          a.kf);
+                            : flux_value(frame + (size_t)b * a.H * a.W, a.H, a.W, e.y >> 16, e.y & 0xffff,
+                                         a.kf, a.bgw);
         const int ri = pmod(tau, kRing);
         a.ring[((size_t)s * a.B + b) * kRing + ri] = f;
         if (b == 0) {
@@ -290,8 +322,7 @@ hipError_t launch_gather_ended(lpf_ctx* c, int ci, int32_t* hdr, float* out, int
     return hipGetLastError();
 }
 
-hipError_t launch_flux(lpf_ctx* c, int slot, int64_t t) {
-    (void)slot;
+FluxArgs flux_args(lpf_ctx* c, int64_t t) {
     FluxArgs a;
     a.cache = c->buf.cache;
     a.cache_t = c->buf.cache_t;
@@ -301,6 +332,7 @@ hipError_t launch_flux(lpf_ctx* c, int slot, int64_t t) {
     a.H = c->cfg.H;
     a.W = c->cfg.W;
     a.kf = c->cfg.flux_halfwidth;
+    a.bgw = c->cfg.flux_bg_width;
     a.T_bf = c->cfg.backfill_steps;
     a.t = t;
     a.t_start = c->t_start;
@@ -314,7 +346,30 @@ hipError_t launch_flux(lpf_ctx* c, int slot, int64_t t) {
     a.count_new = &c->buf.status->n_new;
     a.cap = c->cfg.max_sources;
     a.flux_blocks = 128;
-    hipLaunchKernelGGL(k_flux, dim3(a.T_bf > 0 ? 384 : 128), dim3(256), 0, c->stream, a);
+    return a;
+}
+
+int flux_grid(const FluxArgs& a) { return a.T_bf > 0 ? 384 : 128; }
+
+hipError_t launch_flux(lpf_ctx* c, int slot, int64_t t) {
+    (void)slot;
+    const FluxArgs a = flux_args(c, t);
+    hipLaunchKernelGGL(k_flux, dim3(flux_grid(a)), dim3(256), 0, c->stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_flux_group(lpf_ctx* const* cs, const int64_t* ts, int n, hipStream_t s) {
+    static_assert(sizeof(Grouped<FluxArgs>) <= 4096, "grouped kernel arguments exceed 4 KiB");
+    Grouped<FluxArgs> g{};
+    g.gi.n = n;
+    int total = 0;
+    for (int i = 0; i < n; ++i) {
+        g.a[i] = flux_args(cs[i], ts[i]);
+        g.gi.start[i] = total;
+        total += flux_grid(g.a[i]);
+    }
+    g.gi.start[n] = total;
+    hipLaunchKernelGGL(k_flux_group, dim3(total), dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
@@ -342,6 +397,45 @@ hipError_t launch_windows_gather(lpf_ctx* c, int n, const int32_t* d_slots, cons
 hipError_t launch_ended_ends(lpf_ctx* c, int32_t* slots_out, int64_t* tend_out) {
     hipLaunchKernelGGL(k_ended_ends, dim3(32), dim3(256), 0, c->stream, c->buf.list_ended,
                        &c->buf.status->n_ended, c->buf.src_tend, slots_out, tend_out);
+    return hipGetLastError();
+}
+
+namespace {
+
+// Boxes of the cached quality-controlled images around (row, col) for the
+// steps t_first .. t_first + n - 1: zero outside the image, for a rejected
+// band and for a step the cache no longer holds.
+__global__ __launch_bounds__(256) void k_cutouts(const float* __restrict__ cache, const int64_t* __restrict__ cache_t,
+                                                 const uint32_t* __restrict__ cache_rej, int Tc, int B, int H, int W,
+                                                 size_t plane, int row, int col, int half, int64_t t_first, int n,
+                                                 float* __restrict__ out) {
+    const int side = 2 * half + 1;
+    const int64_t total = (int64_t)n * B * side * side;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int dj = (int)(e % side), di = (int)((e / side) % side);
+        const int b = (int)((e / ((int64_t)side * side)) % B);
+        const int k = (int)(e / ((int64_t)side * side * B));
+        const int64_t tau = t_first + k;
+        int64_t r = tau % Tc;
+        const int slot = (int)(r < 0 ? r + Tc : r);
+        const int i = row + di - half, j = col + dj - half;
+        float v = 0.0f;
+        if (cache_t[slot] == tau && !((cache_rej[slot] >> b) & 1u) && i >= 0 && i < H && j >= 0 && j < W)
+            v = cache[(size_t)slot * plane + ((size_t)b * H + i) * W + j];
+        out[e] = v;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_cutouts(lpf_ctx* c, int row, int col, int half, int64_t t_first, int n_steps) {
+    const int side = 2 * half + 1;
+    const int64_t total = (int64_t)n_steps * c->cfg.B * side * side;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_cutouts, dim3(blocks), dim3(256), 0, c->stream, c->buf.cache, c->buf.cache_t, c->buf.cache_rej,
+                       c->d.Tc, c->cfg.B, c->cfg.H, c->cfg.W, c->d.plane, row, col, half, t_first, n_steps,
+                       c->buf.cutout);
     return hipGetLastError();
 }
 

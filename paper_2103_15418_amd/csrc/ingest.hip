@@ -66,16 +66,40 @@ __device__ inline void pixel_step(float x, float mu, float m2, bool score, float
     m2_out = fmaf(d, x - mu1, m2);
 }
 
-// grid: (nblk, B).  Block (blk, b) handles pixels [blk*chunk, min(HW, (blk+1)*chunk)).
+// Arguments of one context's ingest pass.
+struct IngArgs {
+    const float* src;        // the cube [B][H][W] (device), or the cache slot itself
+    float* cache_slot;       // [B][H][W]
+    const float* wf_mean;    // [2][B][H][W]
+    const float* wf_m2;
+    float* wf_mean_w;
+    float* wf_m2_w;
+    const int32_t* wf_n;     // [B]
+    const int32_t* wf_cur;   // [B]
+    const uint8_t* mask;     // [H][W] or null
+    size_t HW, plane;
+    int64_t chunk;           // pixels per block
+    int warm;
+    int nblk;                // blocks per band
+    BandPartial* partials;   // [B][nblk]
+};
+
+// Block (blk, b) of one context handles pixels [blk*chunk, min(HW, (blk+1)*chunk)) of band b.
 template <bool COPY, bool VEC>
-__global__ __launch_bounds__(kIngThreads) void k_ingest(
-    const float* __restrict__ src, float* __restrict__ cache_slot, const float* __restrict__ wf_mean,
-    const float* __restrict__ wf_m2, float* __restrict__ wf_mean_w, float* __restrict__ wf_m2_w,
-    const int32_t* __restrict__ wf_n, const int32_t* __restrict__ wf_cur,
-    const uint8_t* __restrict__ mask, size_t HW, size_t plane, int64_t chunk, int warm,
-    BandPartial* __restrict__ partials) {
-    const int b = blockIdx.y;
-    const int blk = blockIdx.x;
+__device__ __forceinline__ void ingest_block(const IngArgs& ga, int blk, int b) {
+    const float* __restrict__ src = ga.src;
+    float* __restrict__ cache_slot = ga.cache_slot;
+    const float* __restrict__ wf_mean = ga.wf_mean;
+    const float* __restrict__ wf_m2 = ga.wf_m2;
+    float* __restrict__ wf_mean_w = ga.wf_mean_w;
+    float* __restrict__ wf_m2_w = ga.wf_m2_w;
+    const int32_t* __restrict__ wf_n = ga.wf_n;
+    const int32_t* __restrict__ wf_cur = ga.wf_cur;
+    const uint8_t* __restrict__ mask = ga.mask;
+    const size_t HW = ga.HW, plane = ga.plane;
+    const int64_t chunk = ga.chunk;
+    const int warm = ga.warm;
+    BandPartial* __restrict__ partials = ga.partials;
     const int n = wf_n[b];
     const int cur = wf_cur[b];
     const bool armed = n >= warm && n >= 2;
@@ -146,8 +170,24 @@ __global__ __launch_bounds__(kIngThreads) void k_ingest(
             bp.zmax = fmaxf(bp.zmax, s_z[i]);
         }
         bp.pad[0] = bp.pad[1] = 0;
-        partials[(size_t)b * gridDim.x + blk] = bp;
+        partials[(size_t)b * ga.nblk + blk] = bp;
     }
+}
+
+// grid: (nblk, B), one context.
+template <bool COPY, bool VEC>
+__global__ __launch_bounds__(kIngThreads) void k_ingest(IngArgs a) {
+    ingest_block<COPY, VEC>(a, blockIdx.x, blockIdx.y);
+}
+
+// Grouped launch over several contexts: context i owns the flat blocks
+// [start[i], start[i+1]) = nblk_i x B_i of them, band-major.
+template <bool COPY, bool VEC>
+__global__ __launch_bounds__(kIngThreads) void k_ingest_group(Grouped<IngArgs> g) {
+    const int i = group_of(g.gi, blockIdx.x);
+    const IngArgs& a = g.a[i];
+    const int local = blockIdx.x - g.gi.start[i];
+    ingest_block<COPY, VEC>(a, local % a.nblk, local / a.nblk);
 }
 
 __device__ inline double readlane_d(double v, int j) {
@@ -196,15 +236,21 @@ struct QcParams {
     double npix;
     double band_z, rms_z, rms_floor, zeta;
     int warm;
+    const BandPartial* partials;
+    int32_t* wf_n;
+    int32_t* wf_cur;
+    double* bandstats;
+    int64_t* cache_t;
+    uint32_t* cache_rej;
+    int slot;
+    int64_t t;
+    DevStatus* status;
 };
 
 // One wave per band reduces that band's block partials (lane l sums blocks
 // l, l+64, ... in order, then a fixed butterfly), then lane 0 of the block
-// takes the decision.
-__global__ __launch_bounds__(1024) void k_qc_decide(QcParams q, const BandPartial* __restrict__ partials,
-                                                     int32_t* wf_n, int32_t* wf_cur, double* bandstats,
-                                                     int64_t* cache_t, uint32_t* cache_rej, int slot,
-                                                     int64_t t, DevStatus* status) {
+// takes the decision.  One workgroup of 64 B_max threads per context.
+__device__ __forceinline__ void qc_decide(const QcParams& q) {
     __shared__ double s_mean[kMaxB], s_rms[kMaxB];
     __shared__ int s_nf[kMaxB];
     __shared__ float s_z[kMaxB];
@@ -213,7 +259,7 @@ __global__ __launch_bounds__(1024) void k_qc_decide(QcParams q, const BandPartia
         double sx = 0.0, sxx = 0.0;
         int nf = 0;
         float z = 0.0f;
-        const BandPartial* p = partials + (size_t)b * q.nblk;
+        const BandPartial* p = q.partials + (size_t)b * q.nblk;
         for (int i = lane; i < q.nblk; i += 64) {
             sx += p[i].sx;
             sxx += p[i].sxx;
@@ -240,11 +286,11 @@ __global__ __launch_bounds__(1024) void k_qc_decide(QcParams q, const BandPartia
     const double zr = q.rms_z > 0.0 ? wave_robust_z(in ? s_rms[i] : 0.0, ok, q.B, q.rms_floor) : 0.0;
     bool bad = false;
     if (in) {
-        const int n = wf_n[i];
+        const int n = q.wf_n[i];
         const bool armed = n >= q.warm && n >= 2;
         bad = !ok || fabs(zm) > q.band_z || (q.rms_z > 0.0 && fabs(zr) > q.rms_z) ||
               (armed && (double)s_z[i] > q.zeta);
-        double* bs = bandstats + 6 * i;
+        double* bs = q.bandstats + 6 * i;
         bs[0] = s_mean[i];
         bs[1] = s_rms[i];
         bs[2] = zm;
@@ -252,41 +298,80 @@ __global__ __launch_bounds__(1024) void k_qc_decide(QcParams q, const BandPartia
         bs[4] = armed ? (double)s_z[i] : 0.0;
         bs[5] = (double)s_nf[i];
         if (!bad) {  // commit the speculative Welford update
-            wf_n[i] = n + 1;
-            wf_cur[i] = 1 - wf_cur[i];
+            q.wf_n[i] = n + 1;
+            q.wf_cur[i] = 1 - q.wf_cur[i];
         }
     }
     const uint64_t bal = __ballot(bad);
     const uint32_t rej = (uint32_t)(bal & 0xffffffffull);
     if (i != 0) return;
-    cache_t[slot] = t;
-    cache_rej[slot] = rej;
-    status->rejected = rej;
+    q.cache_t[q.slot] = q.t;
+    q.cache_rej[q.slot] = rej;
+    q.status->rejected = rej;
 }
+
+__global__ __launch_bounds__(1024) void k_qc_decide(QcParams q) { qc_decide(q); }
+
+// Grouped: workgroup i decides for context i.
+__global__ __launch_bounds__(1024) void k_qc_decide_group(Grouped<QcParams> g) { qc_decide(g.a[blockIdx.x]); }
 
 }  // namespace
 
-hipError_t launch_ingest(lpf_ctx* c, const float* src, bool copy, int slot, hipStream_t s) {
+IngArgs ingest_args(lpf_ctx* c, const float* src, int slot) {
     const auto& d = c->d;
-    const int B = c->cfg.B;
-    float* slotp = c->buf.cache + (size_t)slot * d.plane;
-    const int64_t chunk = (int64_t)((d.HW + d.nblk - 1) / d.nblk + 3) / 4 * 4;
-    const bool vec = (d.HW % 4) == 0;
-    dim3 grid(d.nblk, B);
-    const uint8_t* mk = d.masked ? c->buf.mask : nullptr;
-#define LPF_ING(C, V)                                                                        \
-    hipLaunchKernelGGL((k_ingest<C, V>), grid, dim3(kIngThreads), 0, s, src, slotp,           \
-                       c->buf.wf_mean, c->buf.wf_m2, c->buf.wf_mean, c->buf.wf_m2, c->buf.wf_n, \
-                       c->buf.wf_cur, mk, d.HW, d.plane, chunk, c->cfg.qc_warmup, c->buf.partials)
-    if (copy && vec) LPF_ING(true, true);
-    else if (copy) LPF_ING(true, false);
-    else if (vec) LPF_ING(false, true);
-    else LPF_ING(false, false);
-#undef LPF_ING
+    IngArgs a;
+    a.src = src;
+    a.cache_slot = c->buf.cache + (size_t)slot * d.plane;
+    a.wf_mean = c->buf.wf_mean;
+    a.wf_m2 = c->buf.wf_m2;
+    a.wf_mean_w = c->buf.wf_mean;
+    a.wf_m2_w = c->buf.wf_m2;
+    a.wf_n = c->buf.wf_n;
+    a.wf_cur = c->buf.wf_cur;
+    a.mask = d.masked ? c->buf.mask : nullptr;
+    a.HW = d.HW;
+    a.plane = d.plane;
+    a.chunk = (int64_t)((d.HW + d.nblk - 1) / d.nblk + 3) / 4 * 4;
+    a.warm = c->cfg.qc_warmup;
+    a.nblk = d.nblk;
+    a.partials = c->buf.partials;
+    return a;
+}
+
+hipError_t launch_ingest(lpf_ctx* c, const float* src, bool copy, int slot, hipStream_t s) {
+    const IngArgs a = ingest_args(c, src, slot);
+    const bool vec = (c->d.HW % 4) == 0;
+    dim3 grid(c->d.nblk, c->cfg.B);
+    if (copy && vec) hipLaunchKernelGGL((k_ingest<true, true>), grid, dim3(kIngThreads), 0, s, a);
+    else if (copy) hipLaunchKernelGGL((k_ingest<true, false>), grid, dim3(kIngThreads), 0, s, a);
+    else if (vec) hipLaunchKernelGGL((k_ingest<false, true>), grid, dim3(kIngThreads), 0, s, a);
+    else hipLaunchKernelGGL((k_ingest<false, false>), grid, dim3(kIngThreads), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_qc_decide(lpf_ctx* c, int slot, int64_t t, hipStream_t s) {
+// One grouped launch for n <= kGroupMax contexts whose cubes are all on the
+// device (copy) or all already in their cache slots, and whose planes are all
+// float4-aligned or not (vec); srcs[i] and slots[i] as in launch_ingest.
+hipError_t launch_ingest_group(lpf_ctx* const* cs, const float* const* srcs, const int* slots, int n, bool copy,
+                               bool vec, hipStream_t s) {
+    static_assert(sizeof(Grouped<IngArgs>) <= 4096, "grouped kernel arguments exceed 4 KiB");
+    Grouped<IngArgs> g{};
+    g.gi.n = n;
+    int total = 0;
+    for (int i = 0; i < n; ++i) {
+        g.a[i] = ingest_args(cs[i], srcs[i], slots[i]);
+        g.gi.start[i] = total;
+        total += cs[i]->d.nblk * cs[i]->cfg.B;
+    }
+    g.gi.start[n] = total;
+    if (copy && vec) hipLaunchKernelGGL((k_ingest_group<true, true>), dim3(total), dim3(kIngThreads), 0, s, g);
+    else if (copy) hipLaunchKernelGGL((k_ingest_group<true, false>), dim3(total), dim3(kIngThreads), 0, s, g);
+    else if (vec) hipLaunchKernelGGL((k_ingest_group<false, true>), dim3(total), dim3(kIngThreads), 0, s, g);
+    else hipLaunchKernelGGL((k_ingest_group<false, false>), dim3(total), dim3(kIngThreads), 0, s, g);
+    return hipGetLastError();
+}
+
+QcParams qc_params(lpf_ctx* c, int slot, int64_t t) {
     QcParams q;
     q.B = c->cfg.B;
     q.nblk = c->d.nblk;
@@ -296,9 +381,35 @@ hipError_t launch_qc_decide(lpf_ctx* c, int slot, int64_t t, hipStream_t s) {
     q.rms_floor = c->cfg.qc_rms_floor;
     q.zeta = c->cfg.qc_pixel_zeta;
     q.warm = c->cfg.qc_warmup;
-    hipLaunchKernelGGL(k_qc_decide, dim3(1), dim3(64 * c->cfg.B), 0, s, q, c->buf.partials, c->buf.wf_n,
-                       c->buf.wf_cur, c->buf.bandstats, c->buf.cache_t, c->buf.cache_rej, slot, t,
-                       c->buf.status);
+    q.partials = c->buf.partials;
+    q.wf_n = c->buf.wf_n;
+    q.wf_cur = c->buf.wf_cur;
+    q.bandstats = c->buf.bandstats;
+    q.cache_t = c->buf.cache_t;
+    q.cache_rej = c->buf.cache_rej;
+    q.slot = slot;
+    q.t = t;
+    q.status = c->buf.status;
+    return q;
+}
+
+hipError_t launch_qc_decide(lpf_ctx* c, int slot, int64_t t, hipStream_t s) {
+    hipLaunchKernelGGL(k_qc_decide, dim3(1), dim3(64 * c->cfg.B), 0, s, qc_params(c, slot, t));
+    return hipGetLastError();
+}
+
+hipError_t launch_qc_decide_group(lpf_ctx* const* cs, const int* slots, const int64_t* ts, int n, hipStream_t s) {
+    static_assert(sizeof(Grouped<QcParams>) <= 4096, "grouped kernel arguments exceed 4 KiB");
+    Grouped<QcParams> g{};
+    g.gi.n = n;
+    int bmax = 1;
+    for (int i = 0; i < n; ++i) {
+        g.a[i] = qc_params(cs[i], slots[i], ts[i]);
+        g.gi.start[i] = i;
+        if (cs[i]->cfg.B > bmax) bmax = cs[i]->cfg.B;
+    }
+    g.gi.start[n] = n;
+    hipLaunchKernelGGL(k_qc_decide_group, dim3(n), dim3(64 * bmax), 0, s, g);
     return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ constexpr int kMaxIters = 16;      // sigma-clip iterations
 constexpr int kCatMaxPeaks = 8192; // peaks entering association per step
 constexpr int kMaxDim = 4096;      // rows / columns (positions pack into 12 bits)
 constexpr int kMaxSources = 65536;
+constexpr int kMaxCutoutHalf = 32; // image cutouts of candidates: (2 h + 1)^2 pixels, h <= 32
 
 // Background filter tiles: 64 x 64 outputs per 256-thread workgroup.
 constexpr int kTileW = 64;
@@ -116,9 +117,11 @@ struct DevBufs {
     uint32_t* ring_v;      // [S][64]
     DevStatus* status;
     lpf_source* events;    // [2 * max_sources] staging for host copies
-    float* windows;        // unused (network inputs live in the model workspace)
     int32_t* infer_slots;  // [max_sources] slots of an inference batch
     int64_t* infer_tend;   // [max_sources] their window ends
+    float* cutout;         // [Tc][B][2 kMaxCutoutHalf + 1]^2 staging of lpf_read_cutouts
+    float* pre;            // [B][H][W] PSF-correlated detection image (psf_sigma > 0)
+    float* inv_den_psf;    // [H][W] 1 / (G_psf * M) (psf_sigma > 0)
 };
 
 struct Derived {
@@ -131,6 +134,9 @@ struct Derived {
     bool masked;
     bool dyn;      // iterations > 1 or debug planes: materialise S / Y
     bool strip;    // strip kernels (W % 4 == 0, k in {15, 24, 36}): residual plane E
+    bool disk;     // circular uniform kernel (disk.hip)
+    bool pre;      // PSF pre-filter: detection runs on buf.pre
+    int kpsf;      // its half-width
 };
 
 }  // namespace lpf
@@ -140,6 +146,7 @@ struct lpf_ctx {
     int32_t grid_rows[lpf::kMaxB];
     lpf::Derived d;
     lpf::Taps taps;
+    lpf::Taps taps_psf;   // PSF pre-filter taps (psf_sigma > 0)
     lpf::DevBufs buf;
     hipStream_t stream;
     int64_t t_last;
@@ -231,6 +238,26 @@ constexpr int kCand = 8;   // stored association candidates per kept peak
 
 inline int xcd_count() { return 8; }
 
+// Grouped launches (the batch calls): one kernel launch serves up to
+// kGroupMax contexts; context i owns the flat workgroups [start[i],
+// start[i+1]) and its arguments travel in the kernel-argument segment.
+constexpr int kGroupMax = 8;
+struct GroupIndex {
+    int n;
+    int start[kGroupMax + 1];
+};
+template <typename A>
+struct Grouped {
+    GroupIndex gi;
+    A a[kGroupMax];
+};
+// Context of flat workgroup blk (wave-uniform).
+__device__ inline int group_of(const GroupIndex& g, int blk) {
+    int i = 0;
+    while (i + 1 < g.n && blk >= g.start[i + 1]) ++i;
+    return i;
+}
+
 // Local-maximum test of Sec. 2.1.2 at (y, x) of one band plane X: no pixel
 // of the (2 KP + 1)^2 window inside the image and the sky mask M (null = all)
 // exceeds xv, so ties are peaks.  Every window load is issued (from clamped,
@@ -304,5 +331,18 @@ hipError_t launch_pack_mask(lpf_ctx* c);
 hipError_t launch_catalog(lpf_ctx* c, int64_t t);
 hipError_t launch_flux(lpf_ctx* c, int slot, int64_t t);
 hipError_t launch_table_init(lpf_ctx* c);
+hipError_t launch_disk_inv_den(lpf_ctx* c);
+hipError_t launch_disk_filters(lpf_ctx* c, const float* X, const uint32_t* rej, hipStream_t s);
+int disk_max_halfwidth();
+hipError_t launch_prefilter(lpf_ctx* c, int slot);
+hipError_t launch_cutouts(lpf_ctx* c, int row, int col, int half, int64_t t_first, int n_steps);
+// grouped forms (n <= kGroupMax contexts on stream s)
+hipError_t launch_ingest_group(lpf_ctx* const* cs, const float* const* srcs, const int* slots, int n, bool copy,
+                               bool vec, hipStream_t s);
+hipError_t launch_qc_decide_group(lpf_ctx* const* cs, const int* slots, const int64_t* ts, int n, hipStream_t s);
+hipError_t launch_filters_group(lpf_ctx* const* cs, const int* slots, int n, hipStream_t s);
+bool filters_groupable(const lpf_ctx* a, const lpf_ctx* b);
+hipError_t launch_catalog_group(lpf_ctx* const* cs, const int64_t* ts, int n, hipStream_t s);
+hipError_t launch_flux_group(lpf_ctx* const* cs, const int64_t* ts, int n, hipStream_t s);
 
 }  // namespace lpf

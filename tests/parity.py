@@ -30,10 +30,11 @@ PARAM_MAP = dict(kappa="kappa", bg_sigma="s", bg_halfwidth="k_bg", kernel="kerne
                  dup_radius="r_dup", assoc_radius="r_assoc", monitor_steps="n_mon",
                  backfill_steps="t_bf", qc_band_z="qc_band_z", qc_rms_z="qc_rms_z",
                  qc_rms_floor="qc_rms_floor", qc_pixel_zeta="qc_pixel_zeta",
-                 qc_warmup="qc_warmup", max_sources="max_sources", peak_cap="peak_cap")
+                 qc_warmup="qc_warmup", max_sources="max_sources", peak_cap="peak_cap",
+                 psf_sigma="prefilter_sigma", psf_halfwidth="prefilter_k", flux_bg_width="flux_bg_width")
 DEVICE_ONLY = ("debug_planes", "filter_precision")
 FLOAT_PARAMS = ("kappa", "bg_sigma", "dup_radius", "assoc_radius", "qc_band_z", "qc_rms_z", "qc_rms_floor",
-                "qc_pixel_zeta")
+                "qc_pixel_zeta", "psf_sigma")
 
 
 def make_pair(B, H, W, sky_mask=None, grid_rows=None, **params):

@@ -81,7 +81,8 @@ def test_product_path_fails_loudly_without_library(tmp_path, monkeypatch):
 
 def test_pipelined_ingest_holds_one_cube_more():
     """With the pipelined ingest the image cache holds backfill + 2 cubes (the
-    next step is written while this one is measured): exactly one cube more."""
+    next step is written while this one is measured): exactly one cube more,
+    plus one more step of the cutout staging (B x 65^2 floats)."""
     import paper_2103_15418_amd as P
     if not os.path.exists(P.LIB_PATH):
         pytest.skip("library not built")
@@ -89,4 +90,24 @@ def test_pipelined_ingest_holds_one_cube_more():
         seq = P.workspace_size(P.default_config(B, H, W))
         pip = P.workspace_size(P.default_config(B, H, W, pipeline_ingest=1))
         cube = B * H * W * 4
-        assert cube <= pip - seq <= cube + 256
+        assert cube <= pip - seq <= cube + B * 65 * 65 * 4 + 512
+
+
+def test_select_candidates_matches_oracle():
+    """Host-only selection (no device call): DM cut, sigma_DM cut and order
+    against the oracle's selection, with ties and values on both cut edges."""
+    import numpy as np
+    import paper_2103_15418_amd as P
+    from oracle.alert import select
+    rng = np.random.default_rng(5)
+    n = 300
+    mu = rng.uniform(0, 200, (n, 4)).astype(np.float32)
+    L = rng.uniform(-3, 3, (n, 10)).astype(np.float32)
+    L[:, 0] = rng.choice([1.0, 2.5, 50.0, 60.0, 10.0, 49.999996], n).astype(np.float32)
+    mu[::7, 0] = 50.0
+    idx, sg = P.select_candidates(mu, L, 50.0, 50.0)
+    ref, sref = select(mu, L, 50.0, 50.0)
+    assert list(idx) == list(ref)
+    assert np.array_equal(sg.astype(np.float64), sref)
+    idx0, _ = P.select_candidates(mu[:0], L[:0])
+    assert len(idx0) == 0

@@ -1,0 +1,147 @@
+"""Alert and persistence layer on the device: checkpoint / resume of a
+context's state (image cache, QC statistics, source table, rings), image
+cutouts of candidates from the cache (against the oracle, bitwise: pure
+selection), through the C ABI."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.alert import cutouts as oracle_cutouts
+
+from parity import make_pair
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _frames(st, T, hot=None):
+    out = []
+    for t in range(T):
+        f = st.frame(t)
+        if hot is not None and t == hot[0]:
+            f[hot[1]] *= 10.0      # a whole band ten times noisier: QC rejects it
+        out.append(f)
+    return out
+
+
+def _step(ctx, model, t, cube):
+    ctx.ingest(t, cube)
+    ctx.detect(want=False)
+    ctx.extract_flux()
+    return model.infer([ctx])
+
+
+def _same_step(a, b, ra, rb, label):
+    assert a.status() == b.status(), label
+    pa, ea = a.last_lists()
+    pb, eb = b.last_lists()
+    assert pa.tobytes() == pb.tobytes() and ea.tobytes() == eb.tobytes(), label
+    for x, y in zip(ra, rb):
+        assert x.tobytes() == y.tobytes(), label
+    return {int(e["id"]) for e in ea}
+
+
+@pytest.mark.parametrize("pipeline", [0, 1])
+def test_checkpoint_resume_bitwise(pipeline):
+    torch = _torch_cuda()
+    from paper_2103_15418_amd import Context, Model
+    spec = synth.spec_tiny()
+    st = synth.Stream(spec)
+    T, T_save = 16, 9
+    frames = [torch.from_numpy(f).cuda() for f in _frames(st, T, hot=(4, 1))]
+    params = dict(monitor_steps=3, backfill_steps=5, qc_warmup=2, pipeline_ingest=pipeline)
+    model = Model(synth.cnn_weights(seed=3), max_batch=64)
+    a = Context(spec.B, spec.H, spec.W, **params)
+    seen = set()
+    for t in range(T_save):
+        print(f"checkpoint pipeline={pipeline} run t={t}", flush=True)
+        _step(a, model, t, frames[t])
+        seen |= {int(e["id"]) for e in a.last_lists()[1]}
+    buf = a.checkpoint()
+    b = Context(spec.B, spec.H, spec.W, **params)
+    b.restore(buf)
+    assert b.status() == a.status()
+    compared = 0
+    for t in range(T_save, T):
+        print(f"checkpoint pipeline={pipeline} resume t={t}", flush=True)
+        ra = _step(a, model, t, frames[t])
+        rb = _step(b, model, t, frames[t])
+        seen |= _same_step(a, b, ra, rb, (pipeline, t))
+        for sid in sorted(seen):
+            try:
+                sa = a.read_spectrum(sid)
+            except Exception:     # no longer held by the saved context: neither may hold it
+                with pytest.raises(Exception):
+                    b.read_spectrum(sid)
+                continue
+            sb = b.read_spectrum(sid)
+            assert all(np.array_equal(x, y) for x, y in zip(sa, sb)), (pipeline, t, sid)
+            compared += 1
+    assert len(seen) > 0 and compared > 0, (seen, compared)
+
+
+def test_checkpoint_refusals():
+    torch = _torch_cuda()
+    from paper_2103_15418_amd import Context, LpfError
+    a = Context(4, 64, 64, monitor_steps=3, backfill_steps=5)
+    a.ingest(0, torch.zeros((4, 64, 64), device="cuda"))
+    with pytest.raises(LpfError) as err:
+        a.checkpoint()                       # inside a step
+    assert err.value.code == -6
+    a.detect(want=False)
+    a.extract_flux()
+    buf = a.checkpoint()
+    other = Context(4, 64, 64, monitor_steps=4, backfill_steps=5)
+    with pytest.raises(LpfError) as err:
+        other.restore(buf)                   # another configuration
+    assert err.value.code == -1
+    mask = np.ones((64, 64), np.uint8)
+    mask[0, 0] = 0
+    masked = Context(4, 64, 64, sky_mask=mask, monitor_steps=3, backfill_steps=5)
+    with pytest.raises(LpfError) as err:
+        masked.restore(buf)                  # another sky mask
+    assert err.value.code == -1
+    with pytest.raises(LpfError) as err:
+        a.restore(buf)                       # a context that has taken steps
+    assert err.value.code == -6
+
+
+def test_cutouts_match_oracle():
+    torch = _torch_cuda()
+    spec = synth.spec_tiny()
+    st = synth.Stream(spec)
+    T = 12
+    frames = _frames(st, T, hot=(6, 2))
+    ctx, orc = make_pair(spec.B, spec.H, spec.W, backfill_steps=6, qc_warmup=3)
+    c = orc.cfg
+    rng = np.random.default_rng(8)
+    n = 0
+    for t in range(T):
+        print(f"cutouts t={t}", flush=True)
+        ctx.ingest(t, frames[t])
+        rej = orc.ingest(t, frames[t])
+        if t == 6:
+            assert rej >> 2 & 1, rej     # the hot band's zeros reach the cutouts
+        ctx.detect(want=False)
+        orc.detect()
+        ctx.extract_flux()
+        orc.extract_flux()
+        for _ in range(3):
+            row = int(rng.integers(-5, spec.H + 5))
+            col = int(rng.integers(-5, spec.W + 5))
+            half = int(rng.choice([0, 3, 8, 32]))
+            t_first = int(rng.integers(t - 9, t + 1))
+            n_steps = int(rng.integers(1, 8))
+            out, have = ctx.read_cutouts(row, col, half, t_first, n_steps)
+            ref, href = oracle_cutouts(orc.cache, orc.rejected, row, col, half, t_first, n_steps, c.B, c.H, c.W)
+            assert np.array_equal(have, href), (t, row, col, half, t_first)
+            assert out.tobytes() == ref.tobytes(), (t, row, col, half, t_first)
+            n += int(have.sum())
+    assert n > 20

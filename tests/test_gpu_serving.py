@@ -35,14 +35,16 @@ def small_specs(T):
     return out
 
 
+SERVE_PARAMS = dict(monitor_steps=6, backfill_steps=6, kappa=6.0, qc_warmup=3)
+
+
 def run_server(model, streams, frames, record=True, budget=1 << 36):
     from paper_2103_15418_amd import Server
     srv = Server(model, budget, record=record)
     sids = []
     for st in streams:
         s = st.spec
-        sids.append(srv.admit(s.B, s.H, s.W, sky_mask=st.mask, monitor_steps=6, backfill_steps=6,
-                              kappa=6.0, qc_warmup=3))
+        sids.append(srv.admit(s.B, s.H, s.W, sky_mask=st.mask, **SERVE_PARAMS))
     T = len(frames[0])
     stamp = 0
     for t in range(T):                       # interleaved arrivals
@@ -100,22 +102,45 @@ def test_served_peaks_follow_the_oracle():
 
 
 def test_admission_by_hbm_budget():
-    _torch_cuda()
+    """Admission by the HBM budget: a stream that does not fit is refused, or
+    with queue=True waits holding its submitted frames; closing an active
+    stream frees its share and the waiting stream starts; its frames then
+    give the same outputs as the stream served alone."""
+    torch = _torch_cuda()
     from paper_2103_15418_amd import LpfError, Model, Server, default_config, workspace_size
     model = Model(synth.cnn_weights(seed=9), max_batch=8)
-    shapes = [(16, 256, 256), (8, 192, 192), (16, 320, 320)]
-    sizes = [workspace_size(default_config(*sh)) for sh in shapes]
+    specs = small_specs(4)
+    shapes = [(s.B, s.H, s.W) for s in specs]
+    sizes = [workspace_size(default_config(*sh, **SERVE_PARAMS)) for sh in shapes]
     budget = sizes[0] + sizes[1] + sizes[2] - 1   # the third does not fit while both are held
-    srv = Server(model, budget)
-    a = srv.admit(*shapes[0])
-    srv.admit(*shapes[1])
+    streams = [synth.Stream(s) for s in specs]
+    kw = [dict(sky_mask=st.mask, **SERVE_PARAMS) for st in streams]
+    frames = [[torch.from_numpy(st.frame(t)).cuda() for t in range(4)] for st in streams]
+    srv = Server(model, budget, record=True)
+    a = srv.admit(*shapes[0], **kw[0])
+    b = srv.admit(*shapes[1], **kw[1])
     with pytest.raises(LpfError) as err:
-        srv.admit(*shapes[2])
+        srv.admit(*shapes[2], **kw[2])
     assert err.value.code == -2            # LPF_ENOMEM
     used, bud, n = srv.usage()
     assert used == sizes[0] + sizes[1] and n == 2 and bud == budget
-    srv.close(a)                           # memory freed -> the waiting stream fits
-    srv.admit(*shapes[2])
+    c = srv.admit(*shapes[2], queue=True, own_workspace=False, **kw[2])
+    assert srv.admitted_active(a) and not srv.admitted_active(c)
+    for t in range(4):
+        srv.submit(a, t, frames[0][t])
+        srv.submit(c, t, frames[2][t])      # held: the stream is waiting
+    with pytest.raises(LpfError):
+        srv.drain()                         # a's frames finish; c's cannot yet
+    assert srv.usage()[0] == sizes[0] + sizes[1]
+    srv.close(a)                           # memory freed -> the waiting stream starts
+    srv.drain()
     used, _, n = srv.usage()
     assert used == sizes[1] + sizes[2] and n == 2
+    res = srv.poll(cap=64)
+    assert len(res) == 8 and np.all(res["status"] == 0)
+    served = [srv.fetch(c, t) for t in range(4)]
     srv.close_all()
+    alone, _ = run_server(model, [streams[2]], [frames[2]], budget=1 << 36)
+    for t in range(4):
+        for x, y in zip(served[t], alone[(0, t)]):
+            assert x.tobytes() == y.tobytes(), t
