@@ -364,6 +364,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--no-pipeline", action="store_true",
                     help="ingest on the context's stream after the previous step's flux")
+    ap.add_argument("--network-only", action="store_true",
+                    help="only the network on 1024 resident windows per precision (counter runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, copy 1 GiB device-to-device once (reference for HBM counters)")
     args = ap.parse_args()
@@ -379,6 +381,11 @@ def main():
     from paper_2103_15418_amd import Context, Model
 
     torch.cuda.set_device(0)
+    if args.network_only:
+        out = {name: network_batch(Model, synth.cnn_weights(), code) for code, name in ((0, "fp32"), (1, "bf16"),
+                                                                                        (2, "fp16"))}
+        print(json.dumps({"network_batch1024": out}), flush=True)
+        return
     spec = _spec(args.workload)
     st = synth.Stream(spec)
     B, H, W = spec.B, spec.H, spec.W
@@ -556,6 +563,9 @@ def main():
                                            "arrive at a fixed cadence after the timed steps"}
     out["network_batch1024"] = {name: network_batch(Model, synth.cnn_weights(), code)
                                 for code, name in ((0, "fp32"), (1, "bf16"), (2, "fp16"))}
+    # the batch a step of the timed run hands over (about 30 ended episodes)
+    out["network_batch32"] = {name: network_batch(Model, synth.cnn_weights(), code, n=32, reps=50)
+                              for code, name in ((0, "fp32"), (1, "bf16"))}
     # cubes handed over from pinned host memory: the rate including the PCIe copy (not `value`)
     host_pool = [pool[t].cpu().pin_memory() for t in range(4)]
     n_h = min(args.steps, 20)

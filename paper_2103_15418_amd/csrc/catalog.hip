@@ -230,6 +230,101 @@ __device__ inline float dist2(int a, int b) {
     return di * di + dj * dj;
 }
 
+// Deferred local-maximum test (Sec. 2.1.2) of the above-threshold pixels the
+// strip and disk filters listed, over many workgroups: a pixel is a peak if
+// no pixel of its window inside the image and the sky mask exceeds it.
+// Peaks are appended to their band's list (per-band counts in device memory;
+// a band over peak_cap is dropped whole by the catalogue, which also orders
+// the lists).  For the 7 x 7 window eight lanes share a pixel, one window row
+// each, so a wave tests eight pixels with seven loads a lane.
+struct PeakTestArgs {
+    const int2* cand;      // (pixel index | band << 24, S bits)
+    const int32_t* cand_cnt;
+    const float* X;        // detection image [B][H][W]
+    const float* C;        // centre plane
+    const uint8_t* M;
+    int H, W, kp, peak_cap;
+    int32_t* peak_cnt;     // [B]
+    PeakRec* peak_raw;     // [B][peak_cap]
+};
+
+__device__ inline void append_peak(const PeakTestArgs& a, int b, int gy, int gx, float xv, float cv, float sv) {
+    const int idx = atomicAdd(&a.peak_cnt[b], 1);
+    if (idx >= a.peak_cap) return;
+    PeakRec rec;
+    rec.band = b;
+    rec.row = gy;
+    rec.col = gx;
+    rec.x = xv;
+    rec.c = cv;
+    rec.s = sv;
+    rec.sig = (xv - cv) / sqrtf(sv);
+    a.peak_raw[(size_t)b * a.peak_cap + idx] = rec;
+}
+
+__device__ __forceinline__ void peak_test_blocks(const PeakTestArgs& a, int blk, int nblk) {
+    const int ncand = *a.cand_cnt;
+    const size_t HW = (size_t)a.H * a.W;
+    const int tid = threadIdx.x;
+    if (a.kp == 3) {
+        const int g = (blk * (int)blockDim.x + tid) >> 3, r = tid & 7;
+        const int per_round = nblk * (int)blockDim.x / 8;
+        for (int base = 0; base < ncand; base += per_round) {   // uniform trip count
+            const int n = base + g;
+            const bool valid = n < ncand;
+            bool fail = false;
+            int b = 0, gy = 0, gx = 0;
+            float xv = 0.0f, cv = 0.0f, sv = 1.0f;
+            if (valid) {
+                const int2 e = a.cand[n];
+                b = e.x >> 24;
+                const int pix = e.x & 0xffffff;
+                const float* Xb = a.X + (size_t)b * HW;
+                gy = pix / a.W;
+                gx = pix % a.W;
+                sv = __int_as_float(e.y);
+                xv = Xb[pix];
+                if (r == 0) cv = a.C[(size_t)b * HW + pix];
+                const int yy = gy + r - 3;
+                if (r < 7 && yy >= 0 && yy < a.H) {
+                    float v[7];
+                    bool in[7];
+#pragma unroll
+                    for (int dx = 0; dx < 7; ++dx) {
+                        const int xx = gx + dx - 3;
+                        const int xc = xx < 0 ? 0 : (xx >= a.W ? a.W - 1 : xx);
+                        const size_t p = (size_t)yy * a.W + xc;
+                        v[dx] = Xb[p];
+                        in[dx] = xx >= 0 && xx < a.W && (a.M ? a.M[p] != 0 : true);
+                    }
+#pragma unroll
+                    for (int dx = 0; dx < 7; ++dx) fail = fail || (in[dx] && v[dx] > xv);
+                }
+            }
+            const uint64_t bal = __ballot(fail);
+            const bool peak = valid && ((bal >> (tid & 56)) & 0xffull) == 0ull;
+            if (peak && r == 0) append_peak(a, b, gy, gx, xv, cv, sv);
+        }
+    } else {
+        for (int n = blk * (int)blockDim.x + tid; n < ncand; n += nblk * (int)blockDim.x) {
+            const int2 e = a.cand[n];
+            const int b = e.x >> 24, pix = e.x & 0xffffff;
+            const size_t bo = (size_t)b * HW;
+            const int gy = pix / a.W, gx = pix % a.W;
+            const float xv = a.X[bo + pix];
+            if (window_max(a.X + bo, a.M, a.H, a.W, a.kp, gy, gx, xv))
+                append_peak(a, b, gy, gx, xv, a.C[bo + pix], __int_as_float(e.y));
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_peak_test(PeakTestArgs a) { peak_test_blocks(a, blockIdx.x, gridDim.x); }
+
+__global__ __launch_bounds__(256) void k_peak_test_group(Grouped<PeakTestArgs> g) {
+    const int i = group_of(g.gi, blockIdx.x);
+    peak_test_blocks(g.a[i], blockIdx.x - g.gi.start[i], g.gi.start[i + 1] - g.gi.start[i]);
+}
+
 __device__ __forceinline__ void catalog_body(const CatArgs& a) {
     __shared__ uint64_t s_keys[kCatMaxPeaks];        // 64 KB: sort keys / neighbour lists / live lists
     __shared__ int32_t s_pos[kCatMaxPeaks];          // 32 KB: positions in visiting order
@@ -256,88 +351,13 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
     // counters are cleared for the next step's filters.  The candidate count
     // and the first round of candidates are read in the same round trip (the
     // entries are used only below the count).
-    const int g8 = tid >> 3, r8 = tid & 7;
-    const int ncand = a.pk_cand ? a.pk_cand_cnt[0] : 0;
-    int2 e_first = make_int2(0, 0);
-    if (a.pk_cand && g8 < a.pk_cap) e_first = a.pk_cand[g8];
     if (tid < a.B) {
         s_cnt[tid] = a.peak_cnt[tid];
         a.peak_cnt[tid] = 0;
     }
     for (int i = tid; i < a.n_changed; i += kCatThreads) a.changed[i] = 0;
     __syncthreads();   // every lane has read the candidate count
-    if (tid == 0 && a.pk_cand) a.pk_cand_cnt[0] = 0;
-
-    // ---- -1. deferred local-maximum test (Sec. 2.1.2) of the above-threshold
-    // pixels the strip filters listed; peaks are appended to the band lists
-    // (counts in LDS).  For the 7 x 7 window eight lanes share a pixel, one
-    // window row each, so a wave tests eight pixels with seven loads a lane.
-    if (a.pk_cand) {
-        const size_t HW = (size_t)a.H * a.W;
-        auto append = [&](int b, int gy, int gx, float xv, float cv, float sv) {
-            const int idx = atomicAdd(&s_cnt[b], 1);
-            if (idx >= a.peak_cap) return;
-            PeakRec rec;
-            rec.band = b;
-            rec.row = gy;
-            rec.col = gx;
-            rec.x = xv;
-            rec.c = cv;
-            rec.s = sv;
-            rec.sig = (xv - cv) / sqrtf(sv);
-            a.peak_raw[(size_t)b * a.peak_cap + idx] = rec;
-        };
-        if (a.kp == 3) {
-            const int g = g8, r = r8;
-            for (int base = 0; base < ncand; base += kCatThreads / 8) {   // uniform trip count
-                const int n = base + g;
-                const bool valid = n < ncand;
-                bool fail = false;
-                int b = 0, gy = 0, gx = 0;
-                float xv = 0.0f, cv = 0.0f, sv = 1.0f;
-                if (valid) {
-                    const int2 e = base == 0 ? e_first : a.pk_cand[n];
-                    b = e.x >> 24;
-                    const int pix = e.x & 0xffffff;
-                    const float* Xb = a.X + (size_t)b * HW;
-                    gy = pix / a.W;
-                    gx = pix % a.W;
-                    sv = __int_as_float(e.y);
-                    xv = Xb[pix];
-                    if (r == 0) cv = a.C[(size_t)b * HW + pix];
-                    const int yy = gy + r - 3;
-                    if (r < 7 && yy >= 0 && yy < a.H) {
-                        float v[7];
-                        bool in[7];
-#pragma unroll
-                        for (int dx = 0; dx < 7; ++dx) {
-                            const int xx = gx + dx - 3;
-                            const int xc = xx < 0 ? 0 : (xx >= a.W ? a.W - 1 : xx);
-                            const size_t p = (size_t)yy * a.W + xc;
-                            v[dx] = Xb[p];
-                            in[dx] = xx >= 0 && xx < a.W && (a.M ? a.M[p] != 0 : true);
-                        }
-#pragma unroll
-                        for (int dx = 0; dx < 7; ++dx) fail = fail || (in[dx] && v[dx] > xv);
-                    }
-                }
-                const uint64_t bal = __ballot(fail);
-                const bool peak = valid && ((bal >> (tid & 56)) & 0xffull) == 0ull;
-                if (peak && r == 0) append(b, gy, gx, xv, cv, sv);
-            }
-        } else {
-            for (int n = tid; n < ncand; n += kCatThreads) {
-                const int2 e = a.pk_cand[n];
-                const int b = e.x >> 24, pix = e.x & 0xffffff;
-                const size_t bo = (size_t)b * HW;
-                const int gy = pix / a.W, gx = pix % a.W;
-                const float xv = a.X[bo + pix];
-                if (window_max(a.X + bo, a.M, a.H, a.W, a.kp, gy, gx, xv))
-                    append(b, gy, gx, xv, a.C[bo + pix], __int_as_float(e.y));
-            }
-        }
-        __syncthreads();   // the appended records and counts are read below
-    }
+    if (tid == 0 && a.pk_cand_cnt) a.pk_cand_cnt[0] = 0;   // the peak test has read it
 
     if (tid == 0) {
         int off = 0;
@@ -441,31 +461,52 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
             nb[0] = cnt;
         }
         __syncthreads();
-        // A peak without an earlier neighbour is kept whatever the others do: mark
-        // those in parallel; the greedy pass visits only peaks with neighbours.
+        // The greedy order resolved in parallel rounds: a peak without an
+        // earlier neighbour is kept whatever the others do; a peak with a kept
+        // earlier neighbour is dropped; a peak whose earlier neighbours are all
+        // dropped is kept.  Each round decides every peak whose earlier
+        // neighbours are decided, which is the decision of the greedy pass (the
+        // rounds follow its dependency chains, as deep as a cluster of
+        // duplicates is long).  s_flag: 1 kept, 0 dropped, 2 undecided.
         for (int q = tid; q < P; q += kCatThreads) s_flag[q] = nbr[(size_t)q * (kNbr + 1)] == 0 ? 1 : 2;
         __syncthreads();
-        if (tid == 0) {
-            int K = 0;
-            for (int q = 0; q < P; ++q) {
-                if (s_flag[q] == 1) {
-                    ++K;
-                    continue;
-                }
+        for (;;) {
+            int open = 0;
+            for (int q = tid; q < P; q += kCatThreads) {
+                if (s_flag[q] != 2) continue;
                 const int32_t* nb = nbr + (size_t)q * (kNbr + 1);
                 const int cnt = nb[0];
-                bool keep = true;
-                if (cnt > kNbr) {  // long list: test every earlier peak that was kept
-                    for (int r = 0; r < q && keep; ++r)
-                        if (s_flag[r] == 1 && dist2(s_pos[q], s_pos[r]) <= a.r_dup2) keep = false;
+                bool kept_nb = false, pending = false;
+                if (cnt > kNbr) {   // long list: every earlier peak within the radius
+                    for (int r = 0; r < q && !kept_nb; ++r) {
+                        if (dist2(s_pos[q], s_pos[r]) > a.r_dup2) continue;
+                        const int f = s_flag[r];
+                        kept_nb = f == 1;
+                        pending = pending || f == 2;
+                    }
                 } else {
-                    for (int r = 0; r < cnt && keep; ++r)
-                        if (s_flag[nb[1 + r]] == 1) keep = false;
+                    for (int r = 0; r < cnt && !kept_nb; ++r) {
+                        const int f = s_flag[nb[1 + r]];
+                        kept_nb = f == 1;
+                        pending = pending || f == 2;
+                    }
                 }
-                s_flag[q] = keep ? 1 : 0;
-                K += keep;
+                // a flag changes once, from 2 to its final value, so a decision
+                // read in the same round it was written is already the final one
+                if (kept_nb) s_flag[q] = 0;
+                else if (!pending) s_flag[q] = 1;
+                else open = 1;
             }
-            s_K = K;
+            if (!__syncthreads_or(open)) break;
+        }
+        {
+            const int per = (P + kCatThreads - 1) / kCatThreads;
+            const int q0 = tid * per, q1 = min(P, q0 + per);
+            int nk = 0;
+            for (int q = q0; q < q1; ++q) nk += s_flag[q];
+            int tot;
+            (void)block_scan(nk, s_tmp, &tot);
+            if (tid == 0) s_K = tot;
         }
         __syncthreads();
     }
@@ -867,8 +908,7 @@ CatArgs catalog_args(lpf_ctx* c, int64_t t) {
     a.n_changed = (kMaxIters + 1) * c->cfg.B;
     a.peak_sorted = c->buf.peak_sorted;
     // the strip filters of one clip iteration leave the peak test to this kernel
-    const bool deferred = (c->d.strip || c->d.disk) && c->cfg.clip_iters == 1;
-    a.pk_cand = deferred ? c->buf.cand : nullptr;
+    a.pk_cand = nullptr;   // the local-maximum test of deferred candidates runs in k_peak_test
     a.pk_cand_cnt = c->buf.cand_cnt;
     a.pk_cap = (int)std::min<size_t>(c->d.plane, (size_t)INT32_MAX);
     a.X = c->d.pre ? c->buf.pre : c->buf.cache + (size_t)pmod_host(t, c->d.Tc) * c->d.plane;
@@ -900,12 +940,51 @@ CatArgs catalog_args(lpf_ctx* c, int64_t t) {
     return a;
 }
 
+// The filters of one clip iteration on the strip or disk paths leave the
+// local-maximum test to k_peak_test, launched before the catalogue.
+bool peaks_deferred(const lpf_ctx* c) { return (c->d.strip || c->d.disk) && c->cfg.clip_iters == 1; }
+
+constexpr int kPeakTestBlocks = 128;
+
+PeakTestArgs peak_test_args(lpf_ctx* c, int64_t t) {
+    PeakTestArgs a;
+    a.cand = c->buf.cand;
+    a.cand_cnt = c->buf.cand_cnt;
+    a.X = c->d.pre ? c->buf.pre : c->buf.cache + (size_t)pmod_host(t, c->d.Tc) * c->d.plane;
+    a.C = c->buf.centre;
+    a.M = c->d.masked ? c->buf.mask : nullptr;
+    a.H = c->cfg.H;
+    a.W = c->cfg.W;
+    a.kp = c->cfg.peak_halfwidth;
+    a.peak_cap = c->cfg.peak_cap;
+    a.peak_cnt = c->buf.peak_cnt;
+    a.peak_raw = c->buf.peak_raw;
+    return a;
+}
+
 hipError_t launch_catalog(lpf_ctx* c, int64_t t) {
+    if (peaks_deferred(c))
+        hipLaunchKernelGGL(k_peak_test, dim3(kPeakTestBlocks), dim3(256), 0, c->stream, peak_test_args(c, t));
     hipLaunchKernelGGL(k_catalog, dim3(1), dim3(kCatThreads), 0, c->stream, catalog_args(c, t));
     return hipGetLastError();
 }
 
 hipError_t launch_catalog_group(lpf_ctx* const* cs, const int64_t* ts, int n, hipStream_t s) {
+    {
+        static_assert(sizeof(Grouped<PeakTestArgs>) <= 4096, "grouped kernel arguments exceed 4 KiB");
+        Grouped<PeakTestArgs> g{};
+        int m = 0, total = 0;
+        for (int i = 0; i < n; ++i) {
+            if (!peaks_deferred(cs[i])) continue;
+            g.a[m] = peak_test_args(cs[i], ts[i]);
+            g.gi.start[m] = total;
+            total += kPeakTestBlocks;
+            ++m;
+        }
+        g.gi.n = m;
+        g.gi.start[m] = total;
+        if (m > 0) hipLaunchKernelGGL(k_peak_test_group, dim3(total), dim3(256), 0, s, g);
+    }
     static_assert(sizeof(Grouped<CatArgs>) <= 4096, "grouped kernel arguments exceed 4 KiB");
     Grouped<CatArgs> g{};
     g.gi.n = n;

@@ -271,68 +271,141 @@ __global__ __launch_bounds__(256) void k_conv1_16(const float* __restrict__ x, c
         conv1_pixel<T>(x, w, bias, out, p, alpha);
 }
 
-// conv Cin -> Cout on v_mfma_f32_32x32x16_{bf16,f16}: a lane feeds 8 consecutive
-// input channels of one pixel (one 16-byte NHWC load) and 8 consecutive input
-// channels of one output channel's weights ([9][Cout][Cin] layout).
+// conv Cin -> Cout on v_mfma_f32_32x32x16_{bf16,f16} as an implicit GEMM with
+// both operands staged in LDS.  A persistent 256-thread workgroup copies the
+// layer's weights ([9][Cout][Cin], channel rows padded by 8 elements so that
+// the 16-byte reads of 32 lanes spread over all banks) into LDS once, then
+// loops over tiles of four output rows of one window: it stages the tile's
+// six input rows (66 columns with the zero padding, NHWC, padded rows),
+// issuing the next tile's global loads into registers before the products
+// of this one.  Wave w computes output row w of the tile: 64 pixels x Cout
+// channels as 2 x (Cout / 32) accumulators, one k step (16 channels of one
+// kernel tap) reading one 16-byte weight fragment per 32 channels and one
+// input fragment per 32 pixels.  The weights are the A operand (rows =
+// output channels) and the inputs the B operand (columns = pixels), so each
+// lane ends with four consecutive channels of one pixel per group and stores
+// them as one 8-byte vector.
 template <typename T, int CIN, int COUT>
-__global__ __launch_bounds__(256) void k_conv16(const T* __restrict__ in, const T* __restrict__ w,
-                                                const float* __restrict__ bias, T* __restrict__ out,
-                                                const int* __restrict__ n_dev, int n_cap, float alpha) {
+struct Conv16Geo {
+    static constexpr int CINP = CIN + 8;           // LDS channel stride (elements)
+    static constexpr int ROWS = 4;                 // output rows per tile (one per wave)
+    static constexpr int IR = ROWS + 2, IP = kGW + 2;
+    static constexpr int W_ELEMS = 9 * COUT * CINP;
+    static constexpr int I_ELEMS = IR * IP * CINP;
+    static constexpr int CH = CIN / 8;             // 16-byte chunks per pixel
+    static constexpr int IN_CHUNKS = IR * kGW * CH;
+    static constexpr int PF = (IN_CHUNKS + 255) / 256;   // prefetched chunks per thread
+};
+
+template <typename T, int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv16_lds(const T* __restrict__ in, const T* __restrict__ w,
+                                                    const float* __restrict__ bias, T* __restrict__ out,
+                                                    const int* __restrict__ n_dev, int n_cap, float alpha) {
+    typedef Conv16Geo<T, CIN, COUT> G;
     typedef typename V8<T>::type vec;
-    constexpr int ROWS = 64 / COUT;
-    const int nblk = batch_n(n_dev, n_cap) * (kGH / ROWS);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int rloc, px0, co0;
-    if (COUT == 64) {
-        rloc = 0;
-        px0 = (wave & 1) * 32;
-        co0 = (wave >> 1) * 32;
-    } else {
-        rloc = wave >> 1;
-        px0 = (wave & 1) * 32;
-        co0 = 0;
-    }
+    typedef T vec4 __attribute__((ext_vector_type(4)));
+    __shared__ __attribute__((aligned(16))) T s_w[G::W_ELEMS];
+    __shared__ __attribute__((aligned(16))) T s_in[G::I_ELEMS];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int m = lane & 31, kg = lane >> 5;
-    for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
-        const int n = blk / (kGH / ROWS);
-        const int h0 = (blk % (kGH / ROWS)) * ROWS;
-        const int row = h0 + rloc;
-        floatx16 acc = {};
-        vec zero = {};
-#pragma unroll 1
+    const int ntiles = batch_n(n_dev, n_cap) * (kGH / G::ROWS);
+    if ((int)blockIdx.x >= ntiles) return;
+    const vec zero = {};
+
+    // weights, once per workgroup
+    for (int c = tid; c < 9 * COUT * G::CH; c += 256) {
+        const int row = c / G::CH, q = c % G::CH;   // row = kk * COUT + co
+        *reinterpret_cast<vec*>(s_w + row * G::CINP + 8 * q) = *reinterpret_cast<const vec*>(w + (size_t)row * CIN + 8 * q);
+    }
+    // zero padding columns (pixel -1 and 64) of every staged row, never overwritten
+    for (int c = tid; c < G::IR * 2 * G::CH; c += 256) {
+        const int r = c / (2 * G::CH), side = (c / G::CH) & 1, q = c % G::CH;
+        *reinterpret_cast<vec*>(s_in + (r * G::IP + (side ? G::IP - 1 : 0)) * G::CINP + 8 * q) = zero;
+    }
+
+    vec pf[G::PF];
+    auto load_tile = [&](int tile) {
+        const int n = tile / (kGH / G::ROWS);
+        const int h0 = (tile % (kGH / G::ROWS)) * G::ROWS;
+#pragma unroll
+        for (int i = 0; i < G::PF; ++i) {
+            const int c = tid + 256 * i;
+            pf[i] = zero;
+            if (c < G::IN_CHUNKS) {
+                const int r = c / (kGW * G::CH), px = (c / G::CH) % kGW, q = c % G::CH;
+                const int row = h0 - 1 + r;
+                if (row >= 0 && row < kGH)
+                    pf[i] = *reinterpret_cast<const vec*>(in + (((size_t)n * kGH + row) * kGW + px) * CIN + 8 * q);
+            }
+        }
+    };
+    auto store_tile = [&]() {
+#pragma unroll
+        for (int i = 0; i < G::PF; ++i) {
+            const int c = tid + 256 * i;
+            if (c < G::IN_CHUNKS) {
+                const int r = c / (kGW * G::CH), px = (c / G::CH) % kGW, q = c % G::CH;
+                *reinterpret_cast<vec*>(s_in + (r * G::IP + px + 1) * G::CINP + 8 * q) = pf[i];
+            }
+        }
+    };
+
+    constexpr int NCO = COUT / 32;
+    int tile = blockIdx.x;
+    load_tile(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+        __syncthreads();   // the previous tile's products are done with s_in
+        store_tile();
+        __syncthreads();
+        if (tile + (int)gridDim.x < ntiles) load_tile(tile + gridDim.x);   // in flight during the products
+        floatx16 acc[NCO][2];
+#pragma unroll
+        for (int a = 0; a < NCO; ++a) acc[a][0] = acc[a][1] = floatx16{};
+#pragma unroll
         for (int kh = 0; kh < 3; ++kh) {
-            const int r = row + kh - 1;
-            const bool rv = r >= 0 && r < kGH;
-            // the kernel row's 3 x CIN / 16 operand pairs are loaded before the products
-            constexpr int NC = CIN / 16;
-            vec avs[3 * NC], bvs[3 * NC];
 #pragma unroll
             for (int kw = 0; kw < 3; ++kw) {
-                const int col = px0 + m + kw - 1;
-                const bool valid = rv && col >= 0 && col < kGW;
-                const T* ap = in + (((size_t)n * kGH + (rv ? r : 0)) * kGW + (valid ? col : 0)) * CIN + kg * 8;
-                const T* bp = w + ((size_t)(kh * 3 + kw) * COUT + co0 + m) * CIN + kg * 8;
+                const T* ip = s_in + ((wave + kh) * G::IP + m + kw) * G::CINP + 8 * kg;
+                const T* wp = s_w + ((kh * 3 + kw) * COUT + m) * G::CINP + 8 * kg;
 #pragma unroll
-                for (int q = 0; q < NC; ++q) {
-                    avs[kw * NC + q] = valid ? *reinterpret_cast<const vec*>(ap + 16 * q) : zero;
-                    bvs[kw * NC + q] = *reinterpret_cast<const vec*>(bp + 16 * q);
+                for (int cb = 0; cb < CIN / 16; ++cb) {
+                    vec bv[2], av[NCO];
+#pragma unroll
+                    for (int ph = 0; ph < 2; ++ph) bv[ph] = *reinterpret_cast<const vec*>(ip + ph * 32 * G::CINP + 16 * cb);
+#pragma unroll
+                    for (int a = 0; a < NCO; ++a) av[a] = *reinterpret_cast<const vec*>(wp + a * 32 * G::CINP + 16 * cb);
+#pragma unroll
+                    for (int a = 0; a < NCO; ++a)
+#pragma unroll
+                        for (int ph = 0; ph < 2; ++ph) acc[a][ph] = mfma32<T>(av[a], bv[ph], acc[a][ph]);
                 }
             }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int q = 0; q < 3 * NC; ++q) acc = mfma32<T>(avs[q], bvs[q], acc);
         }
+        // lane: pixel ph * 32 + m; channels a * 32 + 8 g + 4 kg + (0..3)
+        const int n = tile / (kGH / G::ROWS);
+        const int row = (tile % (kGH / G::ROWS)) * G::ROWS + wave;
         T* dst = out + ((size_t)n * kGH + row) * kGW * COUT;
-        const float bj = bias[co0 + m];
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int px = px0 + 8 * (v / 4) + 4 * kg + (v % 4);
-            dst[(size_t)px * COUT + co0 + m] = (T)act_fn(acc[v] + bj, alpha);
+        for (int a = 0; a < NCO; ++a) {
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int co = a * 32 + 8 * g + 4 * kg;
+                const float4 bb = *reinterpret_cast<const float4*>(bias + co);
+#pragma unroll
+                for (int ph = 0; ph < 2; ++ph) {
+                    vec4 o;
+                    o[0] = (T)act_fn(acc[a][ph][4 * g + 0] + bb.x, alpha);
+                    o[1] = (T)act_fn(acc[a][ph][4 * g + 1] + bb.y, alpha);
+                    o[2] = (T)act_fn(acc[a][ph][4 * g + 2] + bb.z, alpha);
+                    o[3] = (T)act_fn(acc[a][ph][4 * g + 3] + bb.w, alpha);
+                    *reinterpret_cast<vec4*>(dst + (size_t)(ph * 32 + m) * COUT + co) = o;
+                }
+            }
         }
     }
 }
 
-// fc1 split-K on 16-bit operands: A = act [n][65536] (NHWC flatten), B = W1 [128][65536].
+// fc1 split-K on 16-bit operands// fc1 split-K on 16-bit operands: A = act [n][65536] (NHWC flatten), B = W1 [128][65536].
 template <typename T>
 __global__ __launch_bounds__(256) void k_fc1_16(const T* __restrict__ a, const T* __restrict__ w,
                                                 float* __restrict__ part, const int* __restrict__ n_dev,
@@ -545,13 +618,17 @@ hipError_t forward16(const lpf_model* m, const NetBufs& nb, const float* windows
     const GridCaps gc(n_dev);
     hipLaunchKernelGGL((k_conv1_16<T>), dim3(grid_cap(((int64_t)n_cap * kGH * kGW + 255) / 256, gc.conv1)),
                        dim3(256), 0, s, windows, W + lay.w1, W + lay.b1, a, n_dev, n_cap, m->alpha);
-    hipLaunchKernelGGL((k_conv16<T, 32, 32>), dim3(grid_cap((int64_t)n_cap * (kGH / 2), gc.conv)), dim3(256), 0, s,
-                       a, w16 + kW16o2, W + lay.b2, b, n_dev, n_cap, m->alpha);
-    hipLaunchKernelGGL((k_conv16<T, 32, 64>), dim3(grid_cap((int64_t)n_cap * kGH, gc.conv)), dim3(256), 0, s, b,
-                       w16 + kW16o3, W + lay.b3, a, n_dev, n_cap, m->alpha);
-    hipLaunchKernelGGL((k_conv16<T, 64, 64>), dim3(grid_cap((int64_t)n_cap * kGH, gc.conv)), dim3(256), 0, s, a,
-                       w16 + kW16o4, W + lay.b4, b, n_dev, n_cap, m->alpha);
-    hipLaunchKernelGGL((k_fc1_16<T>), dim3(kNSplit, grid_cap((n_cap + 31) / 32, gc.fc1_rows)), dim3(256), 0, s, b,
+    // persistent implicit GEMMs: a workgroup per CU (Cin = 64: 137 KB of LDS) or two
+    const int64_t tiles = (int64_t)n_cap * (kGH / 4);
+    hipLaunchKernelGGL((k_conv16_lds<T, 32, 32>), dim3(grid_cap(tiles, 512)), dim3(256), 0, s, a, w16 + kW16o2,
+                       W + lay.b2, b, n_dev, n_cap, m->alpha);
+    hipLaunchKernelGGL((k_conv16_lds<T, 32, 64>), dim3(grid_cap(tiles, 512)), dim3(256), 0, s, b, w16 + kW16o3,
+                       W + lay.b3, a, n_dev, n_cap, m->alpha);
+    hipLaunchKernelGGL((k_conv16_lds<T, 64, 64>), dim3(grid_cap(tiles, 256)), dim3(256), 0, s, a, w16 + kW16o4,
+                       W + lay.b4, b, n_dev, n_cap, m->alpha);
+    // fc1: no LDS, so a host-sized batch gets a workgroup per (K chunk, 32 windows) to keep
+    // enough loads in flight to stream the activations
+    hipLaunchKernelGGL((k_fc1_16<T>), dim3(kNSplit, grid_cap((n_cap + 31) / 32, n_dev ? gc.fc1_rows : 32)), dim3(256), 0, s, b,
                        w16 + kW16of1, nb.part, n_dev, n_cap, nb.ldp);
     return hipGetLastError();
 }

@@ -23,6 +23,7 @@ import argparse
 import json
 import os
 import sys
+import time
 from typing import Dict, List, Sequence
 
 import numpy as np
@@ -88,6 +89,7 @@ def run(images: int = 32, kappa: float = 2.0, iters: Sequence[int] = (1, 2, 3, 4
         n_sources: int = 500, seed: int = 2103_15418 + 7, r_match: float = 3.0):
     """The sweep on the device (one context per iteration count, B = 1; the
     pixel test is kept unarmed because the images are unrelated skies)."""
+    import torch
     import synth.skymap as sm
     from . import Context
     imgs = [sm.sky_image(seed, k, D, n_sources) for k in range(images)]
@@ -97,13 +99,24 @@ def run(images: int = 32, kappa: float = 2.0, iters: Sequence[int] = (1, 2, 3, 4
         ctx = Context(1, D, D, sky_mask=mask, kappa=kappa, clip_iters=n_it, qc_warmup=1 << 30,
                       peak_cap=8192)
         counts: Dict[str, np.ndarray] = {}
+        dev = [torch.from_numpy(img[None]).cuda() for img, _, _ in imgs]
         for t, (img, truth, _) in enumerate(imgs):
-            ctx.ingest(t, img[None])
+            ctx.ingest(t, dev[t])
             pd, ev, rc = ctx.detect()
             ctx.extract_flux()
             got, taken = match(pd["row"], pd["col"], truth.rows, truth.cols, truth.flux, r_match)
             accumulate(counts, got, taken, truth.flux, pd["sig"])
         out[f"iters_{n_it}"] = scores(counts)
+        # device time of a step (ingest + detect + flux, nothing read back) at this setting
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t, x in enumerate(dev):
+            ctx.ingest(len(imgs) + t, x)
+            ctx.detect(want=False)
+            ctx.extract_flux()
+        ctx.sync()
+        out[f"iters_{n_it}"]["ms_per_image"] = (time.perf_counter() - t0) / len(dev) * 1e3
+        out[f"iters_{n_it}"]["peaks_per_image"] = float(counts["n_det"].sum()) / len(imgs)
         del ctx
     return out
 
