@@ -366,6 +366,7 @@ def main():
                     help="ingest on the context's stream after the previous step's flux")
     ap.add_argument("--network-only", action="store_true",
                     help="only the network on 1024 resident windows per precision (counter runs)")
+    ap.add_argument("--network-batch", type=int, default=1024, help="windows per call with --network-only")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, copy 1 GiB device-to-device once (reference for HBM counters)")
     args = ap.parse_args()
@@ -382,9 +383,10 @@ def main():
 
     torch.cuda.set_device(0)
     if args.network_only:
-        out = {name: network_batch(Model, synth.cnn_weights(), code) for code, name in ((0, "fp32"), (1, "bf16"),
-                                                                                        (2, "fp16"))}
-        print(json.dumps({"network_batch1024": out}), flush=True)
+        n = args.network_batch
+        out = {name: network_batch(Model, synth.cnn_weights(), code, n=n) for code, name in ((0, "fp32"), (1, "bf16"),
+                                                                                             (2, "fp16"))}
+        print(json.dumps({f"network_batch{n}": out}), flush=True)
         return
     spec = _spec(args.workload)
     st = synth.Stream(spec)

@@ -267,8 +267,8 @@ int lpf_infer_windows(const lpf_model* model, const float* windows, int32_t n, f
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the network
  * on n <= LPF_STATIC_MAX_WINDOWS device windows, as lpf_infer_windows
- * computes it, with its intermediate buffers (activations, fc1 partials,
- * hidden layer) in a file-scope device array of the library (about 18 MiB,
+ * computes it, with its intermediate buffers (activations and fc1 partials)
+ * in a file-scope device array of the library (about 18 MiB,
  * one copy per GPU, held until the process ends) instead of the model's
  * workspace.  Launches directly on hip_stream; allocates nothing and makes
  * no allocating call.  The model still supplies the weights; windows, mu_out

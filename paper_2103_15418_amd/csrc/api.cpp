@@ -156,6 +156,16 @@ size_t carve(const lpf_config* c, const Derived& d, char* base, DevBufs* b) {
     b->cat_kept = cv.take<int32_t>(kCatMaxPeaks);
     b->cat_nbr = cv.take<int32_t>((size_t)kCatMaxPeaks * (kNbr + 1));
     b->cat_cand = cv.take<int32_t>((size_t)kCatMaxPeaks * (kCand + 1));
+    b->cat_gkeys = cv.take<uint64_t>(kCatMaxPeaks);
+    b->cat_gpos = cv.take<int32_t>(kCatMaxPeaks);
+    b->cat_gflag = cv.take<uint8_t>(kCatMaxPeaks);
+    b->cat_live = cv.take<int32_t>(S);
+    b->cat_lpos = cv.take<int32_t>(S);
+    b->cat_taken = cv.take<uint32_t>((S + 31) / 32);
+    b->cat_seen = cv.take<uint32_t>((S + 31) / 32);
+    b->cat_rowoff = cv.take<int32_t>((size_t)c->H + 1);
+    b->cat_rowcur = cv.take<int32_t>((size_t)c->H);
+    b->cat_rowidx = cv.take<int32_t>(kCatMaxPeaks);
     b->free_list = cv.take<int32_t>(S);
     b->src_id = cv.take<int32_t>(S);
     b->src_row = cv.take<int32_t>(S);
@@ -209,6 +219,13 @@ int dev_fail(lpf_ctx* c, hipError_t e, const char* where) {
 int pmod(int64_t a, int m) {
     int64_t r = a % m;
     return (int)(r < 0 ? r + m : r);
+}
+
+// Waits for every stream of a context (before host reads of its state).
+hipError_t sync_all(lpf_ctx* c) {
+    hipError_t e;
+    if (c->ing_stream && (e = hipStreamSynchronize(c->ing_stream)) != hipSuccess) return e;
+    return hipStreamSynchronize(c->stream);
 }
 
 
@@ -425,10 +442,7 @@ void lpf_destroy(lpf_ctx* c) {
         c->pend_model->pend_ctx[c->pend_slot] = nullptr;
         c->pend_model = nullptr;
     }
-    if (!c->poisoned) {
-        (void)hipStreamSynchronize(c->stream);
-        if (c->ing_stream) (void)hipStreamSynchronize(c->ing_stream);
-    }
+    if (!c->poisoned) (void)sync_all(c);
     for (auto& e : c->prof_pool) (void)hipEventDestroy(e);
     if (c->ev_ready) (void)hipEventDestroy(c->ev_ready);
     if (c->ev_filt) (void)hipEventDestroy(c->ev_filt);
@@ -446,11 +460,15 @@ int lpf_ingest_frame(lpf_ctx* c, int64_t t, const float* cube, int32_t on_device
     const int slot = pmod(t, c->d.Tc);
     float* dst = c->buf.cache + (size_t)slot * c->d.plane;
     // pipelined: the context's own ingest stream, ordered after the previous
-    // step's filters (which follow the flux that last read this cache slot),
-    // or after everything on the context's stream before the first detect
+    // step's filters (which follow the flux that last read this cache slot:
+    // the cache holds backfill_steps + 2 steps and a flux reads back
+    // backfill_steps), or after everything on the context's stream before
+    // the first detect or when t skips a step (then the flux just enqueued
+    // may read the slot this frame overwrites)
     hipStream_t s = c->ing_stream ? c->ing_stream : c->stream;
     if (c->ing_stream) {
-        if (!c->filt_recorded) LPF_HIP(c, hipEventRecord(c->ev_filt, c->stream), "event record");
+        if (!c->filt_recorded || (c->n_frames > 0 && t - c->t_last >= 2))
+            LPF_HIP(c, hipEventRecord(c->ev_filt, c->stream), "event record");
         LPF_HIP(c, hipStreamWaitEvent(s, c->ev_filt, 0), "event wait");
     }
     if (on_device) {
@@ -712,7 +730,7 @@ int lpf_read_cutouts(lpf_ctx* c, int32_t row, int32_t col, int32_t half, int64_t
     LPF_CHECK_CTX(c);
     if (!out || half < 0 || half > kMaxCutoutHalf || n_steps < 1 || n_steps > c->d.Tc)
         return fail(c, LPF_EINVAL, "cutout: half in 0..32, 1 <= n_steps <= cache depth, out non-null");
-    if (c->ing_stream) LPF_HIP(c, hipStreamSynchronize(c->ing_stream), "cutout sync");
+    LPF_HIP(c, sync_all(c), "cutout sync");
     LPF_HIP(c, launch_cutouts(c, row, col, half, t_first, n_steps), "cutout");
     const size_t side = (size_t)(2 * half + 1);
     const size_t nval = (size_t)n_steps * c->cfg.B * side * side;
@@ -831,8 +849,7 @@ int lpf_checkpoint_save(lpf_ctx* c, void* host, size_t bytes) {
     if (!host) return fail(c, LPF_EINVAL, "null buffer");
     if (c->phase == 1 || c->phase == 2) return fail(c, LPF_ESTATE, "checkpoint between steps only (after extract_flux)");
     if (bytes < ckpt_bytes(c)) return fail(c, LPF_ENOMEM, "checkpoint buffer too small");
-    if (c->ing_stream) LPF_HIP(c, hipStreamSynchronize(c->ing_stream), "checkpoint sync");
-    LPF_HIP(c, hipStreamSynchronize(c->stream), "checkpoint sync");
+    LPF_HIP(c, sync_all(c), "checkpoint sync");
     const std::vector<Region> regs = state_regions(c);
     const CkptHeader h = ckpt_header(c, (int)regs.size());
     char* p = static_cast<char*>(host);
@@ -867,7 +884,7 @@ int lpf_checkpoint_load(lpf_ctx* c, const void* host, size_t bytes) {
         return fail(c, LPF_EINVAL, "checkpoint of a different configuration");
     if (bytes < ckpt_bytes(c)) return fail(c, LPF_EINVAL, "checkpoint truncated");
     const char* p = static_cast<const char*>(host) + sizeof(h);
-    LPF_HIP(c, hipStreamSynchronize(c->stream), "checkpoint sync");
+    LPF_HIP(c, sync_all(c), "checkpoint sync");
     // the sky mask is part of the configuration: it must equal this context's
     std::vector<uint8_t> cur(c->d.HW);
     for (const Region& r : regs) {
@@ -901,7 +918,7 @@ int lpf_status(lpf_ctx* c, lpf_status_t* out) {
     LPF_CHECK_CTX(c);
     if (!out) return LPF_EINVAL;
     DevStatus st;
-    if (c->ing_stream) LPF_HIP(c, hipStreamSynchronize(c->ing_stream), "status sync");
+    LPF_HIP(c, sync_all(c), "status sync");
     LPF_HIP(c, hipMemcpyAsync(&st, c->buf.status, sizeof(st), hipMemcpyDeviceToHost, c->stream), "status D2H");
     LPF_HIP(c, hipStreamSynchronize(c->stream), "status sync");
     out->t = c->t_last;
@@ -922,7 +939,7 @@ int lpf_read_spectrum(lpf_ctx* c, int32_t id, float* out, uint8_t* valid, int64_
     if (!out) return LPF_EINVAL;
     const int S = c->cfg.max_sources, B = c->cfg.B;
     std::vector<int32_t> ids(S), state(S);
-    LPF_HIP(c, hipStreamSynchronize(c->stream), "spectrum sync");
+    LPF_HIP(c, sync_all(c), "spectrum sync");
     LPF_HIP(c, hipMemcpy(ids.data(), c->buf.src_id, S * sizeof(int32_t), hipMemcpyDeviceToHost), "ids D2H");
     LPF_HIP(c, hipMemcpy(state.data(), c->buf.src_state, S * sizeof(int32_t), hipMemcpyDeviceToHost), "state D2H");
     int slot = -1;
@@ -964,8 +981,7 @@ int lpf_debug_read(lpf_ctx* c, int32_t what, void* host, size_t bytes) {
     const void* src = nullptr;
     size_t need = 0;
     std::vector<int32_t> cur(kMaxB);
-    if (c->ing_stream) LPF_HIP(c, hipStreamSynchronize(c->ing_stream), "debug sync");
-    LPF_HIP(c, hipStreamSynchronize(c->stream), "debug sync");
+    LPF_HIP(c, sync_all(c), "debug sync");
     switch (what) {
         case LPF_DBG_BANDSTATS: src = c->buf.bandstats; need = (size_t)c->cfg.B * 6 * sizeof(double); break;
         case LPF_DBG_WELFORD_N: src = c->buf.wf_n; need = (size_t)c->cfg.B * sizeof(int32_t); break;
@@ -1028,8 +1044,7 @@ int lpf_profile_enable(lpf_ctx* c, int32_t stages) {
 
 int lpf_profile_read(lpf_ctx* c, double* ms, int64_t* counts) {
     LPF_CHECK_CTX(c);
-    if (c->ing_stream) LPF_HIP(c, hipStreamSynchronize(c->ing_stream), "profile sync");
-    LPF_HIP(c, hipStreamSynchronize(c->stream), "profile sync");
+    LPF_HIP(c, sync_all(c), "profile sync");
     for (int i = 0; i < LPF_STAGE_COUNT; ++i) {
         if (ms) ms[i] = 0.0;
         if (counts) counts[i] = 0;
@@ -1047,8 +1062,7 @@ int lpf_profile_read(lpf_ctx* c, double* ms, int64_t* counts) {
 
 int lpf_sync(lpf_ctx* c) {
     LPF_CHECK_CTX(c);
-    if (c->ing_stream) LPF_HIP(c, hipStreamSynchronize(c->ing_stream), "sync");
-    LPF_HIP(c, hipStreamSynchronize(c->stream), "sync");
+    LPF_HIP(c, sync_all(c), "sync");
     return LPF_OK;
 }
 
@@ -1242,7 +1256,7 @@ int lpf_infer(lpf_ctx* const* ctxs, int32_t n_ctx, const lpf_model* m, const int
             const int S = c->cfg.max_sources;
             std::vector<int32_t> idv(S), state(S);
             std::vector<int64_t> tend(S);
-            LPF_HIP(c, hipStreamSynchronize(c->stream), "infer sync");
+            LPF_HIP(c, sync_all(c), "infer sync");
             LPF_HIP(c, hipMemcpy(idv.data(), c->buf.src_id, S * sizeof(int32_t), hipMemcpyDeviceToHost), "ids");
             LPF_HIP(c, hipMemcpy(state.data(), c->buf.src_state, S * sizeof(int32_t), hipMemcpyDeviceToHost), "state");
             LPF_HIP(c, hipMemcpy(tend.data(), c->buf.src_tend, S * sizeof(int64_t), hipMemcpyDeviceToHost), "tend");

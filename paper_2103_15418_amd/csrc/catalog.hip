@@ -26,8 +26,16 @@ namespace lpf {
 namespace {
 
 constexpr int kCatThreads = 1024;
-constexpr int kLdsPeaks = (kCatMaxPeaks * 2) / (kNbr + 1);  // neighbour lists that fit the key area
-constexpr int kLdsKept = 512;                                // kept peaks with LDS candidate lists
+// LDS capacities of the catalogue workgroup (about 42 KB in all, so that it
+// can start on a CU that other kernels' workgroups already occupy); larger
+// steps use the global scratch of the context (mostly L2-resident).
+constexpr int kLdsKeys = 2048;                                 // sort keys (16 KB)
+constexpr int kLdsPeaks = (kLdsKeys * 2) / (kNbr + 1);          // neighbour lists that fit the key area
+constexpr int kLdsLive = kLdsKeys;                              // live (slot, position) pairs in the key area
+constexpr int kLdsPos = 2048;                                   // positions and flags of listed peaks
+constexpr int kLdsSrc = 16384;                                  // table slots of the taken / seen bitmaps
+constexpr int kLdsKept = 256;                                   // kept peaks with LDS candidate lists
+constexpr int kRowIndexMin = 512;   // above this many peaks the duplicate search buckets them by row
 
 struct CatArgs {
     int B, peak_cap, max_sources, n_mon;
@@ -37,20 +45,24 @@ struct CatArgs {
     PeakRec* peak_raw;
     int32_t* changed;        // per-iteration changed flags, cleared for the next step
     int n_changed;
-    // deferred local-maximum test (strip filters): above-threshold pixels per band
-    const int2* pk_cand;         // [cap] (pixel index | band << 24, S bits), null if peaks are already listed
-    int32_t* pk_cand_cnt;        // [1]
-    int pk_cap;                  // entries the list can hold
-    const float* X;           // this step's cube [B][H][W]
-    const float* C;           // centre plane [B][H][W]
-    const uint8_t* M;         // sky mask [H][W] or null
-    int H, W, kp;
+    int32_t* cand_cnt;        // [1] above-threshold pixel count of the peak test, cleared for the next step
+    int H;                    // image rows (row buckets of the duplicate search)
     PeakRec* peak_sorted;
     int32_t* order;     // [kCatMaxPeaks] bij-rank by visiting position
     int32_t* nbr;       // [kCatMaxPeaks][kNbr + 1]
     int32_t* cand;      // [kCatMaxPeaks][kCand + 1]
     int32_t* kept;      // [kCatMaxPeaks] kept peaks (visiting positions) in visiting order
     int32_t* dec;       // [kCatMaxPeaks] association decisions (large steps)
+    uint64_t* g_keys;   // [kCatMaxPeaks] sort keys (steps with more than kLdsKeys peaks)
+    int32_t* g_pos;     // [kCatMaxPeaks] positions in visiting order (large steps)
+    uint8_t* g_flag;    // [kCatMaxPeaks] duplicate-removal flags (large steps)
+    int32_t* g_live;    // [max_sources] live slots of this step
+    int32_t* g_lpos;    // [max_sources] their positions
+    uint32_t* g_taken;  // [max_sources / 32] bitmaps (tables beyond kLdsSrc slots)
+    uint32_t* g_seen;
+    int32_t* g_rowoff;  // [H + 1] row buckets of the duplicate search (many peaks)
+    int32_t* g_rowcur;  // [H]
+    int32_t* g_rowidx;  // [kCatMaxPeaks]
     int32_t* free_list; // [max_sources]
     int32_t* src_id;
     int32_t* src_row;
@@ -326,13 +338,13 @@ __global__ __launch_bounds__(256) void k_peak_test_group(Grouped<PeakTestArgs> g
 }
 
 __device__ __forceinline__ void catalog_body(const CatArgs& a) {
-    __shared__ uint64_t s_keys[kCatMaxPeaks];        // 64 KB: sort keys / neighbour lists / live lists
-    __shared__ int32_t s_pos[kCatMaxPeaks];          // 32 KB: positions in visiting order
-    __shared__ uint8_t s_flag[kCatMaxPeaks];         //  8 KB: kept flags
-    __shared__ uint32_t s_taken[kMaxSources / 32];   //  8 KB: taken bitmap
-    __shared__ uint32_t s_seen[kMaxSources / 32];    //  8 KB: slots named by some candidate list
-    __shared__ int32_t s_cand[kLdsKept * (kCand + 1)];  // 18 KB: candidate lists
-    __shared__ int32_t s_dec[kLdsKept];              //  2 KB: association decisions
+    __shared__ uint64_t s_keys[kLdsKeys];            // 16 KB: sort keys / neighbour lists / live lists
+    __shared__ int32_t s_posl[kLdsPos];              //  8 KB: positions in visiting order
+    __shared__ uint8_t s_flagl[kLdsPos];             //  2 KB: kept flags
+    __shared__ uint32_t s_takenl[kLdsSrc / 32];      //  2 KB: taken bitmap
+    __shared__ uint32_t s_seenl[kLdsSrc / 32];       //  2 KB: slots named by some candidate list
+    __shared__ int32_t s_cand[kLdsKept * (kCand + 1)];  //  9 KB: candidate lists
+    __shared__ int32_t s_dec[kLdsKept];              //  1 KB: association decisions
     __shared__ uint64_t s_wkey[(kCatThreads / 64) * kCand];  // per-wave candidate keys
     __shared__ int32_t s_wslot[(kCatThreads / 64) * kCand];
     __shared__ int s_off[kMaxB + 1];
@@ -347,17 +359,16 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
     const int64_t t = a.t;
 
     // per-band peak counts, read in parallel (one dependent read per band
-    // would serialise as many memory latencies), then the step's detection
-    // counters are cleared for the next step's filters.  The candidate count
-    // and the first round of candidates are read in the same round trip (the
-    // entries are used only below the count).
+    // would serialise as many memory latencies); the step's detection
+    // counters are cleared for the next step's filters (the peak test,
+    // earlier on this stream, has read the candidate count)
     if (tid < a.B) {
         s_cnt[tid] = a.peak_cnt[tid];
         a.peak_cnt[tid] = 0;
     }
     for (int i = tid; i < a.n_changed; i += kCatThreads) a.changed[i] = 0;
-    __syncthreads();   // every lane has read the candidate count
-    if (tid == 0 && a.pk_cand_cnt) a.pk_cand_cnt[0] = 0;   // the peak test has read it
+    if (tid == 0) a.cand_cnt[0] = 0;
+    __syncthreads();
 
     if (tid == 0) {
         int off = 0;
@@ -379,7 +390,12 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
     // ---- 1. (band, row, col) order
     int Ppad = 1;
     while (Ppad < P) Ppad <<= 1;
-    for (int n = tid; n < Ppad; n += kCatThreads) s_keys[n] = ~0ull;
+    uint64_t* keys = Ppad <= kLdsKeys ? s_keys : a.g_keys;
+    int32_t* s_pos = P <= kLdsPos ? s_posl : a.g_pos;
+    uint8_t* s_flag = P <= kLdsPos ? s_flagl : a.g_flag;
+    uint32_t* s_taken = S <= kLdsSrc ? s_takenl : a.g_taken;
+    uint32_t* s_seen = S <= kLdsSrc ? s_seenl : a.g_seen;
+    for (int n = tid; n < Ppad; n += kCatThreads) keys[n] = ~0ull;
     __syncthreads();
     // one pass over all listed peaks (overflowed bands have empty ranges)
     for (int n = tid; n < P; n += kCatThreads) {
@@ -388,10 +404,10 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
         const int q = n - s_off[b];
         const PeakRec& r = a.peak_raw[(size_t)b * a.peak_cap + q];
         const uint32_t key = ((uint32_t)r.band << 24) | ((uint32_t)r.row << 12) | (uint32_t)r.col;
-        s_keys[n] = ((uint64_t)key << 32) | (uint32_t)(b * a.peak_cap + q);
+        keys[n] = ((uint64_t)key << 32) | (uint32_t)(b * a.peak_cap + q);
     }
     __syncthreads();
-    if (P > 1) sort_keys(s_keys, Ppad);
+    if (P > 1) sort_keys(keys, Ppad);
     // copy in (band, row, col) order; the same lane writes the visiting-order
     // key of position n (x descending, then rank n); padding keys stay ~0.
     // Positions also go to LDS (the candidate-list area, free until phase 4b)
@@ -399,18 +415,18 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
     int32_t* s_npos = s_cand;
     const bool pos_lds = P <= kLdsKept * (kCand + 1);
     for (int n = tid; n < P; n += kCatThreads) {
-        const uint32_t ref = (uint32_t)(s_keys[n] & 0xffffffffu);
+        const uint32_t ref = (uint32_t)(keys[n] & 0xffffffffu);
         const PeakRec rec = a.peak_raw[ref];
         a.peak_sorted[n] = rec;
-        s_keys[n] = ((uint64_t)(~ordered(rec.x)) << 32) | (uint32_t)n;
+        keys[n] = ((uint64_t)(~ordered(rec.x)) << 32) | (uint32_t)n;
         if (pos_lds) s_npos[n] = pack_pos(rec.row, rec.col);
     }
     __syncthreads();
 
     // ---- 2. visiting order: x descending, then (band, row, col) = rank
-    if (P > 1) sort_keys(s_keys, Ppad);
+    if (P > 1) sort_keys(keys, Ppad);
     for (int q = tid; q < P; q += kCatThreads) {
-        const int n = (int)(s_keys[q] & 0xffffffffu);
+        const int n = (int)(keys[q] & 0xffffffffu);
         a.order[q] = n;
         s_pos[q] = pos_lds ? s_npos[n] : pack_pos(a.peak_sorted[n].row, a.peak_sorted[n].col);
     }
@@ -448,17 +464,65 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
         // nbr[q] = {count, up to kNbr earlier-visited peaks within dup_radius};
         // held in LDS (the sort-key area) for steps with at most kLdsPeaks peaks.
         int32_t* nbr = P <= kLdsPeaks ? reinterpret_cast<int32_t*>(s_keys) : a.nbr;
-        for (int q = tid; q < P; q += kCatThreads) {
-            const int pq = s_pos[q];
-            int32_t* nb = nbr + (size_t)q * (kNbr + 1);
-            int cnt = 0;
-            for (int r = 0; r < q; ++r) {
-                if (dist2(pq, s_pos[r]) <= a.r_dup2) {
-                    if (cnt < kNbr) nb[1 + cnt] = r;
-                    ++cnt;
+        if (P <= kRowIndexMin) {
+            for (int q = tid; q < P; q += kCatThreads) {
+                const int pq = s_pos[q];
+                int32_t* nb = nbr + (size_t)q * (kNbr + 1);
+                int cnt = 0;
+                for (int r = 0; r < q; ++r) {
+                    if (dist2(pq, s_pos[r]) <= a.r_dup2) {
+                        if (cnt < kNbr) nb[1 + cnt] = r;
+                        ++cnt;
+                    }
                 }
+                nb[0] = cnt;
             }
-            nb[0] = cnt;
+        } else {
+            // many peaks: bucket them by image row (counting sort of the
+            // visiting indices), then each peak looks only at the rows within
+            // dup_radius of its own
+            int32_t* rowoff = a.g_rowoff;   // [H + 1] bucket starts
+            int32_t* rowcur = a.g_rowcur;   // [H] fill cursors
+            const int H = a.H;
+            for (int r = tid; r <= H; r += kCatThreads) rowoff[r] = 0;
+            __syncthreads();
+            for (int q = tid; q < P; q += kCatThreads) atomicAdd(&rowoff[pos_i(s_pos[q])], 1);
+            __syncthreads();
+            {
+                const int per = (H + kCatThreads - 1) / kCatThreads;
+                const int r0 = tid * per, r1 = min(H, r0 + per);
+                int sum = 0;
+                for (int r = r0; r < r1; ++r) sum += rowoff[r];
+                int tot;
+                int acc = block_scan(sum, s_tmp, &tot);
+                for (int r = r0; r < r1; ++r) {
+                    const int c = rowoff[r];
+                    rowoff[r] = acc;
+                    rowcur[r] = acc;
+                    acc += c;
+                }
+                if (tid == 0) rowoff[H] = tot;
+            }
+            __syncthreads();
+            for (int q = tid; q < P; q += kCatThreads) a.g_rowidx[atomicAdd(&rowcur[pos_i(s_pos[q])], 1)] = q;
+            __syncthreads();
+            const int R = (int)floorf(sqrtf(a.r_dup2));
+            for (int q = tid; q < P; q += kCatThreads) {
+                const int pq = s_pos[q];
+                const int i = pos_i(pq);
+                int32_t* nb = nbr + (size_t)q * (kNbr + 1);
+                int cnt = 0;
+                for (int rr = max(0, i - R); rr <= min(H - 1, i + R); ++rr) {
+                    for (int e = rowoff[rr]; e < rowoff[rr + 1]; ++e) {
+                        const int r = a.g_rowidx[e];
+                        if (r < q && dist2(pq, s_pos[r]) <= a.r_dup2) {
+                            if (cnt < kNbr) nb[1 + cnt] = r;
+                            ++cnt;
+                        }
+                    }
+                }
+                nb[0] = cnt;
+            }
         }
         __syncthreads();
         // The greedy order resolved in parallel rounds: a peak without an
@@ -530,8 +594,10 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
         s_taken[w] = 0u;
         s_seen[w] = 0u;
     }
-    int32_t* s_live = reinterpret_cast<int32_t*>(s_keys);        // [S <= 8192 fast path]
-    int32_t* s_lpos = s_live + kCatMaxPeaks;
+    // live (slot, position) pairs go to the global scratch; the key area holds
+    // a copy when they fit
+    int32_t* s_live = reinterpret_cast<int32_t*>(s_keys);
+    int32_t* s_lpos = s_live + kLdsLive;
     {
         // rounds of 8 consecutive slots per thread: the loads (state, last
         // detection, position) are issued together and the scan keeps slot order
@@ -572,10 +638,8 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
             for (int i = 0; i < 8; ++i) {
                 const int sl = s0 + i;
                 if (st[i] == kSrcLive) {
-                    if (ol < kCatMaxPeaks) {
-                        s_live[ol] = sl;
-                        s_lpos[ol] = pack_pos(row[i], col[i]);
-                    }
+                    a.g_live[ol] = sl;
+                    a.g_lpos[ol] = pack_pos(row[i], col[i]);
                     ++ol;
                 } else if (st[i] == kSrcFree) {
                     a.free_list[of++] = sl;
@@ -593,7 +657,16 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
     }
     __syncthreads();
     const int L = s_nlive;
-    const bool live_in_lds = L <= kCatMaxPeaks;
+    const bool live_in_lds = L <= kLdsLive;
+    if (live_in_lds) {
+        for (int l = tid; l < L; l += kCatThreads) {
+            s_live[l] = a.g_live[l];
+            s_lpos[l] = a.g_lpos[l];
+        }
+        __syncthreads();
+    }
+    const int32_t* live = live_in_lds ? s_live : a.g_live;
+    const int32_t* lpos = live_in_lds ? s_lpos : a.g_lpos;
 
     // ---- 4b. association candidates of each kept peak, sorted by (d^2, id).
     // cand[kq] = {count or -1 (too many / table not staged), up to kCand slots}.
@@ -606,15 +679,12 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
         int32_t* wslot = s_wslot + wave * kCand;
         for (int kq = wave; kq < K; kq += kCatThreads / 64) {
             int32_t* out = cand + (size_t)kq * (kCand + 1);
-            if (!live_in_lds) {
-                if (lane == 0) out[0] = -1;
-                continue;
-            }
             const int pq = s_pos[a.kept[kq]];
             int cnt = 0;
             for (int l0 = 0; l0 < L && cnt <= kCand; l0 += 64) {
                 const int l = l0 + lane;
-                const bool hit = l < L && dist2(pq, s_lpos[l]) <= a.r_assoc2;
+                const int lp = l < L ? lpos[l] : 0;
+                const bool hit = l < L && dist2(pq, lp) <= a.r_assoc2;
                 const uint64_t bal = __ballot(hit);
                 const int nh = __popcll(bal);
                 if (cnt + nh > kCand) {
@@ -623,8 +693,8 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
                 }
                 if (hit) {
                     const int at = cnt + __popcll(bal & ((1ull << lane) - 1ull));
-                    const int s = s_live[l];
-                    const uint32_t d2 = (uint32_t)dist2(pq, s_lpos[l]);
+                    const int s = live[l];
+                    const uint32_t d2 = (uint32_t)dist2(pq, lp);
                     wkey[at] = ((uint64_t)d2 << 32) | (uint32_t)a.src_id[s];
                     wslot[at] = s;
                 }
@@ -907,21 +977,23 @@ CatArgs catalog_args(lpf_ctx* c, int64_t t) {
     a.changed = c->buf.changed;
     a.n_changed = (kMaxIters + 1) * c->cfg.B;
     a.peak_sorted = c->buf.peak_sorted;
-    // the strip filters of one clip iteration leave the peak test to this kernel
-    a.pk_cand = nullptr;   // the local-maximum test of deferred candidates runs in k_peak_test
-    a.pk_cand_cnt = c->buf.cand_cnt;
-    a.pk_cap = (int)std::min<size_t>(c->d.plane, (size_t)INT32_MAX);
-    a.X = c->d.pre ? c->buf.pre : c->buf.cache + (size_t)pmod_host(t, c->d.Tc) * c->d.plane;
-    a.C = c->buf.centre;
-    a.M = c->d.masked ? c->buf.mask : nullptr;
+    a.cand_cnt = c->buf.cand_cnt;
     a.H = c->cfg.H;
-    a.W = c->cfg.W;
-    a.kp = c->cfg.peak_halfwidth;
     a.order = c->buf.cat_order;
     a.nbr = c->buf.cat_nbr;
     a.cand = c->buf.cat_cand;
     a.kept = c->buf.cat_kept;
     a.dec = c->buf.cat_dec;
+    a.g_keys = c->buf.cat_gkeys;
+    a.g_pos = c->buf.cat_gpos;
+    a.g_flag = c->buf.cat_gflag;
+    a.g_live = c->buf.cat_live;
+    a.g_lpos = c->buf.cat_lpos;
+    a.g_taken = c->buf.cat_taken;
+    a.g_seen = c->buf.cat_seen;
+    a.g_rowoff = c->buf.cat_rowoff;
+    a.g_rowcur = c->buf.cat_rowcur;
+    a.g_rowidx = c->buf.cat_rowidx;
     a.free_list = c->buf.free_list;
     a.src_id = c->buf.src_id;
     a.src_row = c->buf.src_row;

@@ -65,6 +65,15 @@ ModelLayout make_layout() {
 
 __device__ inline float act_fn(float v, float alpha) { return v >= 0.0f ? v : alpha * v; }
 
+// Device layout of the float32 fc1 weights W1[k][j] (k < 65536, j < 128):
+// groups of eight k, and inside a group (k & 1, (k & 7) >> 1), so that lane
+// (m, kk) of a 32x32x2 product reads the B operands of four consecutive
+// products, W1[8 g + 2 q + kk][j] for q = 0..3, as one 16-byte load, and the
+// 64 lanes of a wave read 1 KB contiguous.
+__host__ __device__ inline size_t f1_index(size_t k, int j) {
+    return ((k >> 3) * kHidden + (size_t)j) * 8 + (k & 1) * 4 + ((k & 7) >> 1);
+}
+
 // Number of windows of a launch: *n_dev (clamped to n_cap) when the count is
 // held on the device, else n_cap.  Grids are sized for n_cap and loop.
 __device__ inline int batch_n(const int* n_dev, int n_cap) {
@@ -175,22 +184,31 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ in,
         }
         const int m = lane & 31, kk = lane >> 5;
         floatx16 acc = {};
-#pragma unroll 1
-        for (int kh = 0; kh < 3; ++kh) {
-#pragma unroll 1
-            for (int kw = 0; kw < 3; ++kw) {
-                const float* arow = s_in + ((rloc + kh) * CIN) * PADW + px0 + m + kw;
-                const float* wrow = w + (size_t)((kh * 3 + kw) * CIN) * COUT + co0 + m;
-                // all CIN / 2 weight loads of this tap in flight before the products
-                float bvs[CIN / 2];
+        // the weights of tap q + 1 (from L2) are loaded before the products of
+        // tap q, so their latency hides behind those products
+        float bA[CIN / 2], bB[CIN / 2];
+        auto load_tap = [&](float* bv, int q) {
+            const float* wrow = w + (size_t)(q * CIN) * COUT + co0 + m;
 #pragma unroll
-                for (int c = 0; c < CIN; c += 2) bvs[c / 2] = wrow[(size_t)(c + kk) * COUT];
-                __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the products
+            for (int c = 0; c < CIN; c += 2) bv[c / 2] = wrow[(size_t)(c + kk) * COUT];
+        };
+        auto products = [&](const float* bv, int q) {
+            const float* arow = s_in + ((rloc + q / 3) * CIN) * PADW + px0 + m + q % 3;
 #pragma unroll
-                for (int c = 0; c < CIN; c += 2)
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[(c + kk) * PADW], bvs[c / 2], acc, 0, 0, 0);
-            }
+            for (int c = 0; c < CIN; c += 2)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[(c + kk) * PADW], bv[c / 2], acc, 0, 0, 0);
+        };
+        load_tap(bA, 0);
+#pragma unroll 1
+        for (int q = 0; q < 8; q += 2) {
+            load_tap(bB, q + 1);
+            __builtin_amdgcn_sched_barrier(0);
+            products(bA, q);
+            load_tap(bA, q + 2);
+            __builtin_amdgcn_sched_barrier(0);
+            products(bB, q + 1);
         }
+        products(bA, 8);
         // D[i][j]: j = lane % 32 (output channel), i = 8 (v / 4) + 4 (lane / 32) + v % 4 (pixel)
         const int row = h0 + rloc;
         float* dst = out + ((size_t)n * kGH + row) * kGW * COUT;
@@ -217,6 +235,7 @@ __global__ __launch_bounds__(256) void k_fc1_mfma(const float* __restrict__ a, c
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m = lane & 31, kk = lane >> 5;
     const int co0 = wave * 32;
+    const float4* wp = reinterpret_cast<const float4*>(w) + ((size_t)(k0 >> 3) * kHidden + co0 + m) * 2 + kk;
     for (int mb = blockIdx.y; mb * 32 < n_total; mb += gridDim.y) {
         for (int i = threadIdx.x; i < 32 * kSplitK; i += 256) {
             const int r = i / kSplitK, k = i % kSplitK;
@@ -225,16 +244,20 @@ __global__ __launch_bounds__(256) void k_fc1_mfma(const float* __restrict__ a, c
         }
         __syncthreads();
         floatx16 acc = {};
-        const float* wp = w + (size_t)k0 * kHidden + co0 + m;
 #pragma unroll 1
-        for (int kb = 0; kb < kSplitK; kb += 64) {   // 32 weight loads in flight per group
-            float bvs[32];
+        for (int g0 = 0; g0 < kSplitK / 8; g0 += 16) {   // 16 KB of weights in flight per wave
+            float4 bvs[16];
 #pragma unroll
-            for (int q = 0; q < 32; ++q) bvs[q] = wp[(size_t)(kb + 2 * q + kk) * kHidden];
+            for (int g = 0; g < 16; ++g) bvs[g] = wp[(size_t)(g0 + g) * kHidden * 2];
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int q = 0; q < 32; ++q)
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(s_a[m * LDA + kb + 2 * q + kk], bvs[q], acc, 0, 0, 0);
+            for (int g = 0; g < 16; ++g) {
+                const float* ar = s_a + m * LDA + 8 * (g0 + g) + kk;
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[0], bvs[g].x, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[2], bvs[g].y, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[4], bvs[g].z, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[6], bvs[g].w, acc, 0, 0, 0);
+            }
         }
         float* dst = part + (size_t)ks * ld_part * kHidden;
 #pragma unroll
@@ -243,6 +266,69 @@ __global__ __launch_bounds__(256) void k_fc1_mfma(const float* __restrict__ a, c
             dst[(size_t)r * kHidden + co0 + m] = acc[v];
         }
         __syncthreads();   // s_a is restaged by the next row block
+    }
+}
+
+// fc1 for a batch whose count is held on the device (typically a few tens of
+// windows) or of at most 64 windows: grid (kNSplit, 2), a workgroup per (K chunk, half of the 128
+// outputs), so that twice as many workgroups stream the weights as with
+// all 128 outputs per workgroup; wave (column block cb, K half kh) and the
+// two K halves added in LDS in a fixed order.  Row blocks of 32 in a loop.
+__global__ __launch_bounds__(256) void k_fc1_small(const float* __restrict__ a, const float* __restrict__ w,
+                                                   float* __restrict__ part, const int* __restrict__ n_dev,
+                                                   int n_cap, int ld_part) {
+    constexpr int LDA = kSplitK + 1;
+    constexpr int KH = kSplitK / 2;
+    __shared__ float s_a[32 * LDA];
+    __shared__ float s_red[2 * 16 * 64];
+    const int n_total = batch_n(n_dev, n_cap);
+    const int ks = blockIdx.x;
+    const int k0 = ks * kSplitK;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m = lane & 31, kk = lane >> 5;
+    const int cb = wave & 1, kh = wave >> 1;
+    const int co0 = blockIdx.y * 64 + cb * 32;
+    const float4* wp = reinterpret_cast<const float4*>(w) + ((size_t)((k0 + kh * KH) >> 3) * kHidden + co0 + m) * 2 + kk;
+    for (int mb = 0; mb * 32 < n_total; ++mb) {
+        for (int i = threadIdx.x; i < 32 * (kSplitK / 4); i += 256) {
+            const int r = i / (kSplitK / 4), k4 = i % (kSplitK / 4);
+            const int n = mb * 32 + r;
+            float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (n < n_total) v = *reinterpret_cast<const float4*>(a + (size_t)n * kFlat + k0 + 4 * k4);
+            float* d = s_a + r * LDA + 4 * k4;
+            d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+        }
+        __syncthreads();
+        floatx16 acc = {};
+#pragma unroll 1
+        for (int g0 = 0; g0 < KH / 8; g0 += 16) {
+            float4 bvs[16];
+#pragma unroll
+            for (int g = 0; g < 16; ++g) bvs[g] = wp[(size_t)(g0 + g) * kHidden * 2];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int g = 0; g < 16; ++g) {
+                const float* ar = s_a + m * LDA + kh * KH + 8 * (g0 + g) + kk;
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[0], bvs[g].x, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[2], bvs[g].y, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[4], bvs[g].z, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[6], bvs[g].w, acc, 0, 0, 0);
+            }
+        }
+        if (kh == 1) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) s_red[(cb * 16 + v) * 64 + lane] = acc[v];
+        }
+        __syncthreads();
+        if (kh == 0) {
+            float* dst = part + (size_t)ks * ld_part * kHidden;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int r = mb * 32 + 8 * (v / 4) + 4 * kk + (v % 4);
+                dst[(size_t)r * kHidden + co0 + m] = acc[v] + s_red[(cb * 16 + v) * 64 + lane];
+            }
+        }
+        __syncthreads();   // s_a and s_red are rewritten by the next row block
     }
 }
 
@@ -464,44 +550,63 @@ __global__ void k_to16(const float* __restrict__ W, T* __restrict__ w16, ModelLa
     conv(lay.w3, o3, 32, 64);
     conv(lay.w4, o4, 64, 64);
     for (size_t i = tid; i < (size_t)kFlat * kHidden; i += nth) {
-        const size_t k = i / kHidden, j = i % kHidden;
-        w16[of1 + j * kFlat + k] = (T)W[lay.f1 + i];
-    }
-}
-
-// hidden[n][j] = phi(sum_ks part[ks][n][j] + b[j]) in a fixed order.
-__global__ void k_fc1_reduce(const float* __restrict__ part, const float* __restrict__ bias,
-                             float* __restrict__ hidden, const int* __restrict__ n_dev, int n_cap, int ld_part,
-                             float alpha) {
-    const int total = batch_n(n_dev, n_cap) * kHidden;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-        const int n = i / kHidden, j = i % kHidden;
-        float acc = 0.0f;
-        for (int ks = 0; ks < kNSplit; ++ks) acc += part[((size_t)ks * ld_part + n) * kHidden + j];
-        hidden[i] = act_fn(acc + bias[j], alpha);
+        const size_t k = i / kHidden;
+        const int j = (int)(i % kHidden);
+        w16[of1 + (size_t)j * kFlat + k] = (T)W[lay.f1 + f1_index(k, j)];
     }
 }
 
 __device__ inline float softplus(float z) { return fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))); }
 
-// fc2 + head: one lane per (sample, output).
-__global__ void k_fc2_head(const float* __restrict__ hidden, const float* __restrict__ w,  // [14][128]
-                           const float* __restrict__ bias, float* __restrict__ mu, float* __restrict__ L,
-                           const int* __restrict__ n_dev, int n_cap) {
-    const int total = batch_n(n_dev, n_cap) * kOut;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-        const int n = i / kOut, o = i % kOut;
-        const float* h = hidden + (size_t)n * kHidden;
-        const float* wr = w + (size_t)o * kHidden;
-        float acc = bias[o];
-        for (int j = 0; j < kHidden; ++j) acc = fmaf(wr[j], h[j], acc);
-        if (o < 4) {
-            mu[n * 4 + o] = acc;
-        } else {
-            const int p = o - 4;
-            const bool diag = p == 0 || p == 2 || p == 5 || p == 9;
-            L[n * 10 + p] = diag ? softplus(acc) : acc;
+// fc1's reduction, fc2 and the head, one sample per 1024-thread workgroup
+// (samples in a loop): thread (g, j) sums the partials ks = g, g + 8, ...
+// of hidden unit j in order, the eight group sums are added in order (then
+// the bias and phi), and wave o < 14 forms output o from the 128 hidden
+// values (two per lane, lanes combined by a fixed butterfly), so the result
+// does not depend on the launch.  mu = out[0:4]; L = out[4:14] with
+// softplus on the diagonal entries (packed positions 0, 2, 5, 9).
+__global__ __launch_bounds__(1024) void k_fc1_head(const float* __restrict__ part, const float* __restrict__ b1,
+                                                   const float* __restrict__ w2,   // [14][128]
+                                                   const float* __restrict__ b2, float* __restrict__ mu,
+                                                   float* __restrict__ L, const int* __restrict__ n_dev, int n_cap,
+                                                   int ld_part, float alpha) {
+    constexpr int G = 8;
+    __shared__ float s_p[G * kHidden];
+    __shared__ float s_h[kHidden];
+    const int tid = threadIdx.x;
+    const int j = tid & (kHidden - 1), g = tid >> 7;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int n_total = batch_n(n_dev, n_cap);
+    for (int n = blockIdx.x; n < n_total; n += gridDim.x) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int ks = g; ks < kNSplit; ks += G) acc += part[((size_t)ks * ld_part + n) * kHidden + j];
+        s_p[g * kHidden + j] = acc;
+        __syncthreads();
+        if (tid < kHidden) {
+            float h = 0.0f;
+#pragma unroll
+            for (int q = 0; q < G; ++q) h += s_p[q * kHidden + tid];
+            s_h[tid] = act_fn(h + b1[tid], alpha);
         }
+        __syncthreads();
+        if (wave < kOut) {
+            const float* wr = w2 + (size_t)wave * kHidden;
+            float v = fmaf(wr[lane], s_h[lane], wr[lane + 64] * s_h[lane + 64]);
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) {
+                v += b2[wave];
+                if (wave < 4) {
+                    mu[(size_t)n * 4 + wave] = v;
+                } else {
+                    const int p = wave - 4;
+                    const bool diag = p == 0 || p == 2 || p == 5 || p == 9;
+                    L[(size_t)n * 10 + p] = diag ? softplus(v) : v;
+                }
+            }
+        }
+        __syncthreads();   // s_p and s_h are rewritten for the next sample
     }
 }
 
@@ -540,7 +645,7 @@ __global__ void k_relayout(const float* __restrict__ blob, float* __restrict__ d
         const int j = (int)(i / kFlat);
         const int kt = (int)(i % kFlat);
         const int c = kt / (kGH * kGW), hw = kt % (kGH * kGW);
-        dst[lay.f1 + ((size_t)hw * 64 + c) * kHidden + j] = blob[o_f1 + i];
+        dst[lay.f1 + f1_index((size_t)hw * 64 + c, j)] = blob[o_f1 + i];
     }
     for (size_t i = tid; i < kHidden; i += nthreads) dst[lay.fb1 + i] = blob[o_fb1 + i];
     for (size_t i = tid; i < (size_t)kOut * kHidden; i += nthreads) dst[lay.f2 + i] = blob[o_f2 + i];
@@ -564,7 +669,6 @@ size_t work_bytes(int precision, int maxb) {
     b += 2 * align64(act);
     if (precision != LPF_PREC_FP32) b += align64(kW16total * 2);
     b += align64((size_t)kNSplit * pad32(maxb) * kHidden * sizeof(float));
-    b += align64((size_t)maxb * kHidden * sizeof(float));
     b += (1 + kInflight) * align64((size_t)maxb * kGH * kGW * sizeof(float));
     b += (1 + kInflight) * align64(out_block_bytes(maxb));
     return b;
@@ -579,20 +683,19 @@ inline int grid_cap(int64_t want, int cap) { return (int)(want < 1 ? 1 : (want >
 // would exit at once (and hold LDS while being dispatched), so those launches
 // use about two workgroups per CU and loop.
 struct GridCaps {
-    int conv1, conv, fc1_rows, small;
+    int conv1, conv, fc1_rows, head;
     explicit GridCaps(const int* n_dev)
-        : conv1(n_dev ? 1024 : 4096), conv(n_dev ? 512 : 2048), fc1_rows(n_dev ? 2 : 4), small(n_dev ? 128 : 1024) {}
+        : conv1(n_dev ? 1024 : 4096), conv(n_dev ? 512 : 2048), fc1_rows(n_dev ? 2 : 4), head(n_dev ? 256 : 1024) {}
 };
 
 // Device buffers one forward pass writes besides its outputs: two activation
-// planes, the fc1 split-K partials (leading dimension ldp rows) and the
-// hidden layer.  A model's own workspace provides them, or the library's
-// static scratch array (lpf_infer_windows_static).
+// planes and the fc1 split-K partials (leading dimension ldp rows).  A
+// model's own workspace provides them, or the library's static scratch
+// array (lpf_infer_windows_static).
 struct NetBufs {
     void* act_a;
     void* act_b;
     float* part;
-    float* hidden;
     int ldp;
 };
 
@@ -602,7 +705,6 @@ NetBufs model_bufs(const lpf_model* m) {
     nb.act_a = m->precision == LPF_PREC_FP32 ? static_cast<void*>(w.act_a) : w.act16_a;
     nb.act_b = m->precision == LPF_PREC_FP32 ? static_cast<void*>(w.act_b) : w.act16_b;
     nb.part = w.part;
-    nb.hidden = w.hidden;
     nb.ldp = pad32(m->max_batch);
     return nb;
 }
@@ -657,15 +759,17 @@ hipError_t forward_on(const lpf_model* m, const NetBufs& nb, const float* window
                            b, W + lay.w3, W + lay.b3, a, n_dev, n_cap, m->alpha);
         hipLaunchKernelGGL((k_conv_mfma<64, 64>), dim3(grid_cap((int64_t)n_cap * kGH, gc.conv)), dim3(256), 0, s,
                            a, W + lay.w4, W + lay.b4, b, n_dev, n_cap, m->alpha);
-        hipLaunchKernelGGL(k_fc1_mfma, dim3(kNSplit, grid_cap((n_cap + 31) / 32, gc.fc1_rows)), dim3(256), 0, s, b,
-                           W + lay.f1, nb.part, n_dev, n_cap, nb.ldp);
+        if (n_dev || n_cap <= 64)
+            hipLaunchKernelGGL(k_fc1_small, dim3(kNSplit, 2), dim3(256), 0, s, b, W + lay.f1, nb.part, n_dev, n_cap,
+                               nb.ldp);
+        else
+            hipLaunchKernelGGL(k_fc1_mfma, dim3(kNSplit, grid_cap((n_cap + 31) / 32, gc.fc1_rows)), dim3(256), 0, s,
+                               b, W + lay.f1, nb.part, n_dev, n_cap, nb.ldp);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fc1_reduce, dim3(grid_cap(((int64_t)n_cap * kHidden + 255) / 256, gc.small)), dim3(256), 0,
-                       s, nb.part, W + lay.fb1, nb.hidden, n_dev, n_cap, nb.ldp, m->alpha);
-    hipLaunchKernelGGL(k_fc2_head, dim3(grid_cap(((int64_t)n_cap * kOut + 255) / 256, gc.small)), dim3(256), 0, s,
-                       nb.hidden, W + lay.f2, W + lay.fb2, mu, L, n_dev, n_cap);
+    hipLaunchKernelGGL(k_fc1_head, dim3(grid_cap(n_cap, gc.head)), dim3(1024), 0, s, nb.part, W + lay.fb1,
+                       W + lay.f2, W + lay.fb2, mu, L, n_dev, n_cap, nb.ldp, m->alpha);
     return hipGetLastError();
 }
 
@@ -676,14 +780,12 @@ hipError_t cnn_forward(const lpf_model* m, const float* windows, const int* n_de
 
 // ---- allocation-free inference: a file-scope device scratch array --------
 // Holds the buffers of one forward pass of up to kStaticWindows windows:
-// two float32 activation planes, the fc1 partials (32 rows) and the hidden
-// layer.  Each device has its own copy; host code reaches it only through
+// two float32 activation planes and the fc1 partials (32 rows).  Each device has its own copy; host code reaches it only through
 // the address hipGetSymbolAddress returns on that device.
 constexpr int kStaticWindows = 32;
 constexpr size_t kStaticAct = (size_t)kStaticWindows * kGH * kGW * 64 * sizeof(float);   // 8 MiB
 constexpr size_t kStaticPart = (size_t)kNSplit * kStaticWindows * kHidden * sizeof(float);  // 2 MiB
-constexpr size_t kStaticHidden = (size_t)kStaticWindows * kHidden * sizeof(float);
-constexpr size_t kStaticBytes = 2 * kStaticAct + kStaticPart + kStaticHidden;
+constexpr size_t kStaticBytes = 2 * kStaticAct + kStaticPart;
 static_assert(kStaticAct % 256 == 0 && kStaticPart % 256 == 0, "scratch sub-buffer alignment");
 
 __device__ __align__(256) char scratch[kStaticBytes];
@@ -724,7 +826,6 @@ hipError_t cnn_forward_static(const lpf_model* m, const float* windows, int n, f
     nb.act_a = base;
     nb.act_b = base + kStaticAct;
     nb.part = reinterpret_cast<float*>(base + 2 * kStaticAct);
-    nb.hidden = reinterpret_cast<float*>(base + 2 * kStaticAct + kStaticPart);
     nb.ldp = kStaticWindows;
     return forward_on(m, nb, windows, nullptr, n, mu, L, s);
 }
@@ -798,7 +899,6 @@ int model_create(const void* weights, size_t bytes, int precision, int maxb, voi
     }
     m->work.part = reinterpret_cast<float*>(p);
     p += align64((size_t)kNSplit * pad32(maxb) * kHidden * sizeof(float));
-    m->work.hidden = reinterpret_cast<float*>(p); p += align64((size_t)maxb * kHidden * sizeof(float));
     m->work.windows = reinterpret_cast<float*>(p); p += align64((size_t)maxb * kGH * kGW * sizeof(float));
     m->work.hdr = reinterpret_cast<int32_t*>(p);
     m->work.rows = m->work.hdr + 4;

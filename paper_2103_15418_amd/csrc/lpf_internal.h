@@ -98,6 +98,16 @@ struct DevBufs {
     int32_t* cat_kept;     // [kCatMaxPeaks]
     int32_t* cat_nbr;      // [kCatMaxPeaks][kNbr]
     int32_t* cat_cand;     // [kCatMaxPeaks][kCand]
+    uint64_t* cat_gkeys;   // [kCatMaxPeaks] sort keys beyond the workgroup's LDS
+    int32_t* cat_gpos;     // [kCatMaxPeaks]
+    uint8_t* cat_gflag;    // [kCatMaxPeaks]
+    int32_t* cat_live;     // [max_sources] live slots of the step
+    int32_t* cat_lpos;     // [max_sources] their positions
+    uint32_t* cat_taken;   // [max_sources / 32] bitmaps beyond the LDS ones
+    uint32_t* cat_seen;
+    int32_t* cat_rowoff;   // [H + 1] row buckets of the duplicate search
+    int32_t* cat_rowcur;   // [H]
+    int32_t* cat_rowidx;   // [kCatMaxPeaks]
     int32_t* free_list;    // [max_sources]
     // source table
     int32_t* src_id;
@@ -193,7 +203,6 @@ struct CnnWork {
     void* act16_b;
     void* w16;        // 16-bit weights: conv2..4 [9][Cout][Cin], fc1 [128][65536]
     float* part;      // [128][maxb_pad][128] fc1 split-K partials
-    float* hidden;    // [maxb][128]
     float* windows;   // [maxb][16][64]
     // result block, one contiguous device range (copied to the host in one piece):
     int32_t* hdr;     // [4]: windows taken, ended episodes seen

@@ -3,9 +3,9 @@ and the dispersion-measure accuracy table (Sec. 2.3.3, Sec. 3.2, Table 1).
 
     python -m paper_2103_15418_amd.train [--samples 32768] [--out weights.npz] [--table table.json]
 
-Training is an offline step: it uses PyTorch's autograd on the GPU (Adam with
-default settings, mini-batches, early stopping on the likelihood of a held-
-out tenth) for the network the library's kernels evaluate (four 3 x 3
+Training is an offline step: it uses PyTorch's autograd on the GPU (Adam,
+the step size halved when the held-out likelihood stalls, mini-batches,
+early stopping on the likelihood of a held-out tenth) for the network the library's kernels evaluate (four 3 x 3
 convolutions 1->32->32->64->64 with leaky rectifiers, dense 65536->128->14;
 mu = out[0:4] = (DM, width, amplitude, arrival), L packed row by row with a
 softplus diagonal, Sigma = L L^T).  The loss per sample is the Gaussian
@@ -47,13 +47,19 @@ def build_net(alpha: float):
             self.fc1 = nn.Linear(64 * 16 * 64, 128)
             self.fc2 = nn.Linear(128, 14)
             self.alpha = alpha
+            # fixed per-output scale after fc2 (folded into fc2 at export, so
+            # the exported network is the plain one): Adam's steps are of the
+            # same size in every parameter, and without it an output in the
+            # units of a wide parameter (DM spans hundreds) would move by
+            # only a few units over a whole training run
+            self.register_buffer("oscale", torch.ones(14))
 
         def forward(self, x):
             a = x[:, None]
             for c in self.conv:
                 a = torch.nn.functional.leaky_relu(c(a), self.alpha)
             h = torch.nn.functional.leaky_relu(self.fc1(a.flatten(1)), self.alpha)
-            return self.fc2(h)
+            return self.fc2(h) * self.oscale
 
     return Net()
 
@@ -88,16 +94,17 @@ def export(net) -> dict:
     for l, c in enumerate(net.conv, start=1):
         w[f"conv{l}.w"] = c.weight.detach().float().cpu().numpy().copy()
         w[f"conv{l}.b"] = c.bias.detach().float().cpu().numpy().copy()
-    for name in ("fc1", "fc2"):
-        m = getattr(net, name)
-        w[f"{name}.w"] = m.weight.detach().float().cpu().numpy().copy()
-        w[f"{name}.b"] = m.bias.detach().float().cpu().numpy().copy()
+    w["fc1.w"] = net.fc1.weight.detach().float().cpu().numpy().copy()
+    w["fc1.b"] = net.fc1.bias.detach().float().cpu().numpy().copy()
+    sc = net.oscale.detach().float().cpu()
+    w["fc2.w"] = (net.fc2.weight.detach().float().cpu() * sc[:, None]).numpy().copy()
+    w["fc2.b"] = (net.fc2.bias.detach().float().cpu() * sc).numpy().copy()
     w["alpha"] = float(net.alpha)
     return w
 
 
-def train(samples=32768, seed=2103_15418 + 11, batch=256, patience=5, max_epochs=100, alpha=0.01,
-          log=print, device="cuda"):
+def train(samples=32768, seed=2103_15418 + 11, batch=256, patience=20, max_epochs=400, alpha=0.01,
+          log=print, device="cuda", lr=3e-4, clip=5.0):
     import torch
     from synth.pulses import RANGES, simulate
     torch.manual_seed(seed)
@@ -108,16 +115,22 @@ def train(samples=32768, seed=2103_15418 + 11, batch=256, patience=5, max_epochs
     xv, tv = torch.from_numpy(x[:nv]).to(dev), torch.from_numpy(th[:nv]).to(dev)
     net = build_net(alpha).to(dev)
     with torch.no_grad():
-        # start at the prior: mean and spread of the uniform parameter ranges
+        # start at the prior: mean and spread of the uniform parameter ranges;
+        # output i (mu_i, or an entry of row i of L) is scaled by the prior
+        # spread of parameter i
         lo = np.array([RANGES[k][0] for k in ("dm", "width", "amp", "t0")])
         hi = np.array([RANGES[k][1] for k in ("dm", "width", "amp", "t0")])
+        sd = (hi - lo) / np.sqrt(12.0)
+        row = [0, 1, 2, 3] + [i for i in range(4) for _ in range(i + 1)]
+        net.oscale.copy_(torch.tensor(sd[row], dtype=torch.float32))
         net.fc2.weight.mul_(0.01)
         net.fc2.bias.zero_()
-        net.fc2.bias[:4] = torch.tensor((lo + hi) / 2, dtype=torch.float32)
-        sd = (hi - lo) / np.sqrt(12.0)
+        net.fc2.bias[:4] = torch.tensor((lo + hi) / 2 / sd, dtype=torch.float32)
         for i, p in enumerate(DIAG):
-            net.fc2.bias[4 + p] = float(np.log(np.expm1(sd[i])))
-    opt = torch.optim.Adam(net.parameters())
+            net.fc2.bias[4 + p] = float(np.log(np.expm1(sd[i])) / sd[i])
+    opt = torch.optim.Adam(net.parameters(), lr=lr)
+    # the validation likelihood is noisy: halve the step size when it stalls
+    sched = torch.optim.lr_scheduler.ReduceLROnPlateau(opt, factor=0.5, patience=6)
     best, best_state, bad, hist = np.inf, None, 0, []
     g = torch.Generator(device="cpu")
     g.manual_seed(seed)
@@ -130,12 +143,16 @@ def train(samples=32768, seed=2103_15418 + 11, batch=256, patience=5, max_epochs
             loss = nll(net(xt[idx]), tt[idx])
             opt.zero_grad()
             loss.backward()
+            # the likelihood is steep where a predicted spread is small: clip
+            # the step's gradient so that one bad batch cannot wreck the features
+            torch.nn.utils.clip_grad_norm_(net.parameters(), clip)
             opt.step()
             tot += float(loss.detach()) * len(idx)
         net.eval()
         with torch.no_grad():
             vl = float(sum(nll(net(xv[i:i + 1024]), tv[i:i + 1024]) * len(xv[i:i + 1024])
                            for i in range(0, nv, 1024)) / nv)
+        sched.step(vl)
         hist.append((ep, tot / xt.shape[0], vl))
         log(f"[train] epoch {ep} train nll {tot / xt.shape[0]:.4f} val nll {vl:.4f}")
         if vl < best - 1e-4:
@@ -185,7 +202,7 @@ def evaluate(weights: dict, n=8192, seed=2103_15418 + 12, precision=0):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--samples", type=int, default=32768)
-    ap.add_argument("--epochs", type=int, default=100)
+    ap.add_argument("--epochs", type=int, default=400)
     ap.add_argument("--out", default=None, help="write the trained weights (npz)")
     ap.add_argument("--table", default=None, help="write the DM table (json)")
     args = ap.parse_args(argv)

@@ -77,18 +77,21 @@ def test_streaming_workload_2048_with_rfi():
     assert n_rfi >= 5
 
 
-def test_many_peaks_catalogue_global_lists():
-    """More than 512 kept peaks and more than 963 peaks in one step (4 x
+@pytest.mark.parametrize("max_sources", [8192, 20000])
+def test_many_peaks_catalogue_global_lists(max_sources):
+    """More than 256 kept peaks and more than 240 peaks in one step (4 x
     1024^2 at kappa = 3.4, peak_cap 2048): the catalogue's candidate and
-    neighbour lists leave the LDS for global memory; events and spectra as
-    the oracle's."""
+    neighbour lists leave the LDS for global memory, and with a table of
+    20000 slots its taken / seen bitmaps too; events and spectra as the
+    oracle's.  (More than 2048 peaks, which moves the sort keys, positions
+    and flags to global memory, is the sweep test's kappa = 2 case.)"""
     _torch_cuda()
     rng = np.random.default_rng(44)
     B, H, W = 4, 1024, 1024
-    ctx, orc = make_pair(B, H, W, kappa=3.4, peak_cap=2048, pipeline_ingest=1)
+    ctx, orc = make_pair(B, H, W, kappa=3.4, peak_cap=2048, pipeline_ingest=1, max_sources=max_sources)
 
     def frame(t):
         return rng.standard_normal((B, H, W)).astype(np.float32)
-    res = run_steps_sampled(ctx, orc, frame, [0, 1, 2], label="many-peaks", tiles=1)
+    res = run_steps_sampled(ctx, orc, frame, [0, 1, 2], label=f"many-peaks-S{max_sources}", tiles=1)
     assert res["peaks"] / 3 > 1000, res
     assert ctx.status()["n_kept"] > 512
