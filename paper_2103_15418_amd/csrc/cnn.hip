@@ -184,31 +184,22 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ in,
         }
         const int m = lane & 31, kk = lane >> 5;
         floatx16 acc = {};
-        // the weights of tap q + 1 (from L2) are loaded before the products of
-        // tap q, so their latency hides behind those products
-        float bA[CIN / 2], bB[CIN / 2];
-        auto load_tap = [&](float* bv, int q) {
-            const float* wrow = w + (size_t)(q * CIN) * COUT + co0 + m;
-#pragma unroll
-            for (int c = 0; c < CIN; c += 2) bv[c / 2] = wrow[(size_t)(c + kk) * COUT];
-        };
-        auto products = [&](const float* bv, int q) {
-            const float* arow = s_in + ((rloc + q / 3) * CIN) * PADW + px0 + m + q % 3;
-#pragma unroll
-            for (int c = 0; c < CIN; c += 2)
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[(c + kk) * PADW], bv[c / 2], acc, 0, 0, 0);
-        };
-        load_tap(bA, 0);
 #pragma unroll 1
-        for (int q = 0; q < 8; q += 2) {
-            load_tap(bB, q + 1);
-            __builtin_amdgcn_sched_barrier(0);
-            products(bA, q);
-            load_tap(bA, q + 2);
-            __builtin_amdgcn_sched_barrier(0);
-            products(bB, q + 1);
+        for (int kh = 0; kh < 3; ++kh) {
+#pragma unroll 1
+            for (int kw = 0; kw < 3; ++kw) {
+                const float* arow = s_in + ((rloc + kh) * CIN) * PADW + px0 + m + kw;
+                const float* wrow = w + (size_t)((kh * 3 + kw) * CIN) * COUT + co0 + m;
+                // all CIN / 2 weight loads of this tap in flight before the products
+                float bvs[CIN / 2];
+#pragma unroll
+                for (int c = 0; c < CIN; c += 2) bvs[c / 2] = wrow[(size_t)(c + kk) * COUT];
+                __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the products
+#pragma unroll
+                for (int c = 0; c < CIN; c += 2)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[(c + kk) * PADW], bvs[c / 2], acc, 0, 0, 0);
+            }
         }
-        products(bA, 8);
         // D[i][j]: j = lane % 32 (output channel), i = 8 (v / 4) + 4 (lane / 32) + v % 4 (pixel)
         const int row = h0 + rloc;
         float* dst = out + ((size_t)n * kGH + row) * kGW * COUT;
@@ -531,6 +522,56 @@ __global__ __launch_bounds__(256) void k_fc1_16(const T* __restrict__ a, const T
     }
 }
 
+// fc1 on 16-bit operands for host-sized batches of at least 128 windows: a
+// workgroup per (K chunk of kWideK, 128 windows), wave w owning windows
+// 32 w .. 32 w + 31 and all 128 outputs (four accumulators), so each
+// activation is read once from HBM and the weight fragments, common to the
+// four waves, come from cache.  Workgroups of one K chunk are kSplitWide
+// apart in launch order, which puts them on the same XCD (and L2).
+constexpr int kWideK = 2048;
+constexpr int kSplitWide = kFlat / kWideK;   // 32
+template <typename T>
+__global__ __launch_bounds__(256) void k_fc1_16w(const T* __restrict__ a, const T* __restrict__ w,
+                                                 float* __restrict__ part, int n, int ld_part) {
+    typedef typename V8<T>::type vec;
+    constexpr int U = 4;   // k steps of 16 in flight
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m = lane & 31, kg = lane >> 5;
+    const int ks = blockIdx.x, k0 = ks * kWideK;
+    const int row = blockIdx.y * 128 + wave * 32 + m;
+    const bool valid = row < n;
+    const T* ap = a + (size_t)(valid ? row : 0) * kFlat + k0 + kg * 8;
+    const T* bp = w + (size_t)m * kFlat + k0 + kg * 8;
+    const vec zero = {};
+    floatx16 acc[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = floatx16{};
+#pragma unroll 1
+    for (int k = 0; k < kWideK; k += 16 * U) {
+        vec av[U], bv[U][4];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            av[u] = valid ? *reinterpret_cast<const vec*>(ap + k + 16 * u) : zero;
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+                bv[u][cb] = *reinterpret_cast<const vec*>(bp + (size_t)cb * 32 * kFlat + k + 16 * u);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) acc[cb] = mfma32<T>(av[u], bv[u][cb], acc[cb]);
+    }
+    float* dst = part + (size_t)ks * ld_part * kHidden;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int r = blockIdx.y * 128 + wave * 32 + 8 * (v / 4) + 4 * kg + (v % 4);
+        if (r >= n) continue;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) dst[(size_t)r * kHidden + cb * 32 + m] = acc[cb][v];
+    }
+}
+
 // float32 device layouts -> 16-bit copies: conv [(kh*3+kw)*Cin+cin][Cout] -> [kh*3+kw][Cout][Cin],
 // fc1 [k][128] -> [128][k].
 template <typename T>
@@ -560,6 +601,7 @@ __device__ inline float softplus(float z) { return fmaxf(z, 0.0f) + log1pf(expf(
 
 // fc1's reduction, fc2 and the head, one sample per 1024-thread workgroup
 // (samples in a loop): thread (g, j) sums the partials ks = g, g + 8, ...
+// (nsplit K chunks, a multiple of 8)
 // of hidden unit j in order, the eight group sums are added in order (then
 // the bias and phi), and wave o < 14 forms output o from the 128 hidden
 // values (two per lane, lanes combined by a fixed butterfly), so the result
@@ -569,7 +611,7 @@ __global__ __launch_bounds__(1024) void k_fc1_head(const float* __restrict__ par
                                                    const float* __restrict__ w2,   // [14][128]
                                                    const float* __restrict__ b2, float* __restrict__ mu,
                                                    float* __restrict__ L, const int* __restrict__ n_dev, int n_cap,
-                                                   int ld_part, float alpha) {
+                                                   int ld_part, int nsplit, float alpha) {
     constexpr int G = 8;
     __shared__ float s_p[G * kHidden];
     __shared__ float s_h[kHidden];
@@ -580,7 +622,7 @@ __global__ __launch_bounds__(1024) void k_fc1_head(const float* __restrict__ par
     for (int n = blockIdx.x; n < n_total; n += gridDim.x) {
         float acc = 0.0f;
 #pragma unroll
-        for (int ks = g; ks < kNSplit; ks += G) acc += part[((size_t)ks * ld_part + n) * kHidden + j];
+        for (int ks = g; ks < nsplit; ks += G) acc += part[((size_t)ks * ld_part + n) * kHidden + j];
         s_p[g * kHidden + j] = acc;
         __syncthreads();
         if (tid < kHidden) {
@@ -711,7 +753,7 @@ NetBufs model_bufs(const lpf_model* m) {
 
 template <typename T>
 hipError_t forward16(const lpf_model* m, const NetBufs& nb, const float* windows, const int* n_dev, int n_cap,
-                     hipStream_t s) {
+                     hipStream_t s, int* nsplit) {
     const ModelLayout& lay = m->lay;
     const float* W = m->wts;
     const T* w16 = static_cast<const T*>(m->work.w16);
@@ -730,8 +772,15 @@ hipError_t forward16(const lpf_model* m, const NetBufs& nb, const float* windows
                        W + lay.b4, b, n_dev, n_cap, m->alpha);
     // fc1: no LDS, so a host-sized batch gets a workgroup per (K chunk, 32 windows) to keep
     // enough loads in flight to stream the activations
-    hipLaunchKernelGGL((k_fc1_16<T>), dim3(kNSplit, grid_cap((n_cap + 31) / 32, n_dev ? gc.fc1_rows : 32)), dim3(256), 0, s, b,
-                       w16 + kW16of1, nb.part, n_dev, n_cap, nb.ldp);
+    if (!n_dev && n_cap >= 128) {
+        hipLaunchKernelGGL((k_fc1_16w<T>), dim3(kSplitWide, (n_cap + 127) / 128), dim3(256), 0, s, b, w16 + kW16of1,
+                           nb.part, n_cap, nb.ldp);
+        *nsplit = kSplitWide;
+    } else {
+        hipLaunchKernelGGL((k_fc1_16<T>), dim3(kNSplit, grid_cap((n_cap + 31) / 32, n_dev ? gc.fc1_rows : 32)),
+                           dim3(256), 0, s, b, w16 + kW16of1, nb.part, n_dev, n_cap, nb.ldp);
+        *nsplit = kNSplit;
+    }
     return hipGetLastError();
 }
 
@@ -744,10 +793,11 @@ hipError_t forward_on(const lpf_model* m, const NetBufs& nb, const float* window
     const float* W = m->wts;
     const GridCaps gc(n_dev);
     hipError_t e = hipSuccess;
+    int nsplit = kNSplit;
     if (m->precision == LPF_PREC_BF16) {
-        e = forward16<__bf16>(m, nb, windows, n_dev, n_cap, s);
+        e = forward16<__bf16>(m, nb, windows, n_dev, n_cap, s, &nsplit);
     } else if (m->precision == LPF_PREC_FP16) {
-        e = forward16<_Float16>(m, nb, windows, n_dev, n_cap, s);
+        e = forward16<_Float16>(m, nb, windows, n_dev, n_cap, s, &nsplit);
     } else {
         float* a = static_cast<float*>(nb.act_a);
         float* b = static_cast<float*>(nb.act_b);
@@ -769,7 +819,7 @@ hipError_t forward_on(const lpf_model* m, const NetBufs& nb, const float* window
     }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fc1_head, dim3(grid_cap(n_cap, gc.head)), dim3(1024), 0, s, nb.part, W + lay.fb1,
-                       W + lay.f2, W + lay.fb2, mu, L, n_dev, n_cap, nb.ldp, m->alpha);
+                       W + lay.f2, W + lay.fb2, mu, L, n_dev, n_cap, nb.ldp, nsplit, m->alpha);
     return hipGetLastError();
 }
 

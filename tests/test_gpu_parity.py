@@ -257,16 +257,19 @@ def test_association_conflicts_and_duplicates():
     assert res["steps"] == len(ts) and res["events"] >= 5 and res["resyncs"] == 0
 
 
-def test_network_fp32_parity_ragged_batch():
-    """infer_windows on 37 seeded windows (a ragged multiple of 32) against the
-    FP64 oracle network, per output within 1e-5 of the condition scale."""
+@pytest.mark.parametrize("n,maxb", [(37, 64), (100, 128)])
+def test_network_fp32_parity_ragged_batch(n, maxb):
+    """infer_windows on 37 and 100 seeded windows (ragged multiples of 32;
+    up to 64 windows fc1 splits the outputs over two workgroups per K chunk,
+    above it runs a workgroup per 32 windows) against the FP64 oracle
+    network, per output within 1e-5 of the condition scale."""
     torch = _torch_cuda()
     from paper_2103_15418_amd import Model
     wts = synth.cnn_weights(seed=11, leaky_alpha=0.1)
     rng = np.random.default_rng(4)
-    x = (rng.standard_normal((37, 16, 64)) * 2.0).astype(np.float32)
+    x = (rng.standard_normal((n, 16, 64)) * 2.0).astype(np.float32)
     x[::3, 5, 20:30] += 6.0
-    m = Model(wts, max_batch=64)
+    m = Model(wts, max_batch=maxb)
     mu_d, L_d = m.infer_windows(torch.from_numpy(x).cuda())
     torch.cuda.synchronize()
     raw = ocnn.forward_raw(x.astype(np.float64), wts)

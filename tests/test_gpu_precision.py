@@ -116,14 +116,18 @@ def test_candidates_16bit_vs_fp32(prec):
 
 
 @pytest.mark.parametrize("prec", [1, 2])
-def test_network_16bit_error(prec):
+@pytest.mark.parametrize("n,maxb", [(70, 64), (300, 512)])
+def test_network_16bit_error(prec, n, maxb):
+    """70 windows through a model of batch 64 (two chunks, the per-32-window
+    fc1), 300 through one of batch 512 (one call: the fc1 over 128-window
+    blocks, the last one ragged)."""
     torch = _torch_cuda()
     from paper_2103_15418_amd import Model
     wts = synth.cnn_weights(seed=11)
     rng = np.random.default_rng(4)
-    x = (rng.standard_normal((70, 16, 64)) * 2.0).astype(np.float32)
+    x = (rng.standard_normal((n, 16, 64)) * 2.0).astype(np.float32)
     x[::3, 5, 20:30] += 6.0
-    m = Model(wts, precision=prec, max_batch=64)   # 70 > 64: two chunks
+    m = Model(wts, precision=prec, max_batch=maxb)
     mu_d, L_d = m.infer_windows(torch.from_numpy(x).cuda())
     torch.cuda.synchronize()
     raw = ocnn.forward_raw(x.astype(np.float64), wts)
