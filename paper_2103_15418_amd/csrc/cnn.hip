@@ -152,22 +152,43 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ in,
                                                    float* __restrict__ out, const int* __restrict__ n_dev,
                                                    int n_cap, float alpha) {
     constexpr int ROWS = 64 / COUT;
-    constexpr int PADW = kGW + 2;  // 66
+    constexpr int PADW = kGW + 3;  // a zero column either side, odd stride
+    constexpr int C4 = CIN / 4;
+    constexpr int NCH = (ROWS + 2) * kGW * C4;   // 16-byte input chunks per block
+    constexpr int PF = (NCH + 255) / 256;
     __shared__ float s_in[(ROWS + 2) * CIN * PADW];
     const int nblk = batch_n(n_dev, n_cap) * (kGH / ROWS);
     for (int blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         const int n = blk / (kGH / ROWS);
         const int h0 = (blk % (kGH / ROWS)) * ROWS;
         const float* src = in + (size_t)n * kGH * kGW * CIN;
-        // stage rows h0-1 .. h0+ROWS, channel-major with a zero column either side
-        for (int i = threadIdx.x; i < (ROWS + 2) * PADW * CIN; i += 256) {
-            const int cin = i % CIN;
-            const int col = (i / CIN) % PADW;
-            const int r = i / (CIN * PADW);
-            const int gr = h0 - 1 + r, gc = col - 1;
-            float v = 0.0f;
-            if (gr >= 0 && gr < kGH && gc >= 0 && gc < kGW) v = src[((size_t)gr * kGW + gc) * CIN + cin];
-            s_in[(r * CIN + cin) * PADW + col] = v;
+        // stage rows h0-1 .. h0+ROWS channel-major: every 16-byte load of the
+        // block in flight at once, then the LDS stores
+        float4 pf[PF];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int c = threadIdx.x + 256 * q;
+            pf[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (c < NCH) {
+                const int r = c / (kGW * C4), col = (c / C4) % kGW, c4 = c % C4;
+                const int gr = h0 - 1 + r;
+                if (gr >= 0 && gr < kGH)
+                    pf[q] = *reinterpret_cast<const float4*>(src + ((size_t)gr * kGW + col) * CIN + 4 * c4);
+            }
+        }
+        for (int i = threadIdx.x; i < (ROWS + 2) * CIN * 2; i += 256)
+            s_in[(i >> 1) * PADW + ((i & 1) ? kGW + 1 : 0)] = 0.0f;
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int c = threadIdx.x + 256 * q;
+            if (c < NCH) {
+                const int r = c / (kGW * C4), col = (c / C4) % kGW, c4 = c % C4;
+                float* d = s_in + (r * CIN + 4 * c4) * PADW + col + 1;
+                d[0] = pf[q].x;
+                d[PADW] = pf[q].y;
+                d[2 * PADW] = pf[q].z;
+                d[3 * PADW] = pf[q].w;
+            }
         }
         __syncthreads();
         const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -213,6 +234,33 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ in,
     }
 }
 
+// Stages A[n0 .. n0 + 31][k0 .. k0 + kSplitK) (zero rows past n_total) into
+// LDS rows of kSplitK + 1 floats (odd: the products' column reads are free of
+// bank conflicts): all of the workgroup's 16-byte loads in flight, then the
+// stores.
+__device__ __forceinline__ void stage_rows(float* s_a, const float* __restrict__ a, int n0, int n_total, int k0) {
+    constexpr int LDA = kSplitK + 1;
+    constexpr int K4 = kSplitK / 4;
+    constexpr int PF = 32 * K4 / 256;
+    float4 pf[PF];
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        const int n = n0 + i / K4;
+        pf[q] = n < n_total ? *reinterpret_cast<const float4*>(a + (size_t)n * kFlat + k0 + 4 * (i % K4))
+                            : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        float* d = s_a + (i / K4) * LDA + 4 * (i % K4);
+        d[0] = pf[q].x;
+        d[1] = pf[q].y;
+        d[2] = pf[q].z;
+        d[3] = pf[q].w;
+    }
+}
+
 // fc1 split-K: part[ks][row][128] = A[rows][kchunk] * W1[kchunk][128]
 // grid (kNSplit, ceil(n / 32)); A = act (NHWC flatten, k = (h*64 + w)*64 + c).
 __global__ __launch_bounds__(256) void k_fc1_mfma(const float* __restrict__ a, const float* __restrict__ w,
@@ -228,11 +276,7 @@ __global__ __launch_bounds__(256) void k_fc1_mfma(const float* __restrict__ a, c
     const int co0 = wave * 32;
     const float4* wp = reinterpret_cast<const float4*>(w) + ((size_t)(k0 >> 3) * kHidden + co0 + m) * 2 + kk;
     for (int mb = blockIdx.y; mb * 32 < n_total; mb += gridDim.y) {
-        for (int i = threadIdx.x; i < 32 * kSplitK; i += 256) {
-            const int r = i / kSplitK, k = i % kSplitK;
-            const int n = mb * 32 + r;
-            s_a[r * LDA + k] = n < n_total ? a[(size_t)n * kFlat + k0 + k] : 0.0f;
-        }
+        stage_rows(s_a, a, mb * 32, n_total, k0);
         __syncthreads();
         floatx16 acc = {};
 #pragma unroll 1
@@ -281,14 +325,7 @@ __global__ __launch_bounds__(256) void k_fc1_small(const float* __restrict__ a, 
     const int co0 = blockIdx.y * 64 + cb * 32;
     const float4* wp = reinterpret_cast<const float4*>(w) + ((size_t)((k0 + kh * KH) >> 3) * kHidden + co0 + m) * 2 + kk;
     for (int mb = 0; mb * 32 < n_total; ++mb) {
-        for (int i = threadIdx.x; i < 32 * (kSplitK / 4); i += 256) {
-            const int r = i / (kSplitK / 4), k4 = i % (kSplitK / 4);
-            const int n = mb * 32 + r;
-            float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (n < n_total) v = *reinterpret_cast<const float4*>(a + (size_t)n * kFlat + k0 + 4 * k4);
-            float* d = s_a + r * LDA + 4 * k4;
-            d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
-        }
+        stage_rows(s_a, a, mb * 32, n_total, k0);
         __syncthreads();
         floatx16 acc = {};
 #pragma unroll 1
