@@ -345,6 +345,8 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
     __shared__ uint32_t s_seenl[kLdsSrc / 32];       //  2 KB: slots named by some candidate list
     __shared__ int32_t s_cand[kLdsKept * (kCand + 1)];  //  9 KB: candidate lists
     __shared__ int32_t s_dec[kLdsKept];              //  1 KB: association decisions
+    __shared__ int32_t s_kept[kLdsKept];             //  1 KB: kept peaks (visiting positions)
+    __shared__ int32_t s_freel[kLdsKept];            //  1 KB: first free slots of the table
     __shared__ uint64_t s_wkey[(kCatThreads / 64) * kCand];  // per-wave candidate keys
     __shared__ int32_t s_wslot[(kCatThreads / 64) * kCand];
     __shared__ int s_off[kMaxB + 1];
@@ -368,6 +370,7 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
     }
     for (int i = tid; i < a.n_changed; i += kCatThreads) a.changed[i] = 0;
     if (tid == 0) a.cand_cnt[0] = 0;
+    if (tid == kCatThreads - 1) s_next = a.status->next_id;   // in the same round trip
     __syncthreads();
 
     if (tid == 0) {
@@ -382,7 +385,6 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
         s_off[a.B] = off;
         s_P = off;
         s_overflow = ovf;
-        s_next = a.status->next_id;
     }
     __syncthreads();
     const int P = s_P;
@@ -397,31 +399,57 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
     uint32_t* s_seen = S <= kLdsSrc ? s_seenl : a.g_seen;
     for (int n = tid; n < Ppad; n += kCatThreads) keys[n] = ~0ull;
     __syncthreads();
-    // one pass over all listed peaks (overflowed bands have empty ranges)
-    for (int n = tid; n < P; n += kCatThreads) {
-        int b = 0;
-        while (n >= s_off[b + 1]) ++b;
-        const int q = n - s_off[b];
-        const PeakRec& r = a.peak_raw[(size_t)b * a.peak_cap + q];
-        const uint32_t key = ((uint32_t)r.band << 24) | ((uint32_t)r.row << 12) | (uint32_t)r.col;
-        keys[n] = ((uint64_t)key << 32) | (uint32_t)(b * a.peak_cap + q);
-    }
-    __syncthreads();
-    if (P > 1) sort_keys(keys, Ppad);
-    // copy in (band, row, col) order; the same lane writes the visiting-order
-    // key of position n (x descending, then rank n); padding keys stay ~0.
-    // Positions also go to LDS (the candidate-list area, free until phase 4b)
-    // when they fit, so the visiting order needs no read of the copy.
     int32_t* s_npos = s_cand;
     const bool pos_lds = P <= kLdsKept * (kCand + 1);
-    for (int n = tid; n < P; n += kCatThreads) {
-        const uint32_t ref = (uint32_t)(keys[n] & 0xffffffffu);
-        const PeakRec rec = a.peak_raw[ref];
-        a.peak_sorted[n] = rec;
-        keys[n] = ((uint64_t)(~ordered(rec.x)) << 32) | (uint32_t)n;
-        if (pos_lds) s_npos[n] = pack_pos(rec.row, rec.col);
+    if (P <= kCatThreads) {
+        // one peak per lane, held in registers: the sorted copy and the
+        // visiting-order keys are written from them through the rank of each
+        // lane's peak (LDS), with no second read of the raw records
+        PeakRec rec{};
+        if (tid < P) {
+            int b = 0;
+            while (tid >= s_off[b + 1]) ++b;
+            rec = a.peak_raw[(size_t)b * a.peak_cap + (tid - s_off[b])];
+            const uint32_t key = ((uint32_t)rec.band << 24) | ((uint32_t)rec.row << 12) | (uint32_t)rec.col;
+            keys[tid] = ((uint64_t)key << 32) | (uint32_t)tid;
+        }
+        __syncthreads();
+        if (P > 1) sort_keys(keys, Ppad);
+        int32_t* s_rank = s_posl;   // free until the visiting order is written
+        if (tid < P) s_rank[(int)(keys[tid] & 0xffffffffu)] = tid;
+        __syncthreads();
+        if (tid < P) {
+            const int n = s_rank[tid];
+            a.peak_sorted[n] = rec;
+            keys[n] = ((uint64_t)(~ordered(rec.x)) << 32) | (uint32_t)n;
+            if (pos_lds) s_npos[n] = pack_pos(rec.row, rec.col);
+        }
+        __syncthreads();
+    } else {
+        // one pass over all listed peaks (overflowed bands have empty ranges)
+        for (int n = tid; n < P; n += kCatThreads) {
+            int b = 0;
+            while (n >= s_off[b + 1]) ++b;
+            const int q = n - s_off[b];
+            const PeakRec& r = a.peak_raw[(size_t)b * a.peak_cap + q];
+            const uint32_t key = ((uint32_t)r.band << 24) | ((uint32_t)r.row << 12) | (uint32_t)r.col;
+            keys[n] = ((uint64_t)key << 32) | (uint32_t)(b * a.peak_cap + q);
+        }
+        __syncthreads();
+        if (P > 1) sort_keys(keys, Ppad);
+        // copy in (band, row, col) order; the same lane writes the visiting-order
+        // key of position n (x descending, then rank n); padding keys stay ~0.
+        // Positions also go to LDS (the candidate-list area, free until phase 4b)
+        // when they fit, so the visiting order needs no read of the copy.
+        for (int n = tid; n < P; n += kCatThreads) {
+            const uint32_t ref = (uint32_t)(keys[n] & 0xffffffffu);
+            const PeakRec rec = a.peak_raw[ref];
+            a.peak_sorted[n] = rec;
+            keys[n] = ((uint64_t)(~ordered(rec.x)) << 32) | (uint32_t)n;
+            if (pos_lds) s_npos[n] = pack_pos(rec.row, rec.col);
+        }
+        __syncthreads();
     }
-    __syncthreads();
 
     // ---- 2. visiting order: x descending, then (band, row, col) = rank
     if (P > 1) sort_keys(keys, Ppad);
@@ -455,8 +483,11 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
                 if ((m & kept) == 0ull) kept |= 1ull << j;
             }
             if (q < P) s_flag[q] = (uint8_t)((kept >> q) & 1ull);
-            if (q < P && ((kept >> q) & 1ull))   // kept list in visiting order
-                a.kept[__popcll(kept & ((1ull << q) - 1ull))] = q;
+            if (q < P && ((kept >> q) & 1ull)) {   // kept list in visiting order
+                const int k = __popcll(kept & ((1ull << q) - 1ull));
+                a.kept[k] = q;
+                s_kept[k] = q;   // P <= 64 <= kLdsKept
+            }
             if (q == 0) s_K = __popcll(kept);
         }
         __syncthreads();
@@ -583,7 +614,11 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
         int tot;
         int ok = block_scan(nk, s_tmp, &tot);
         for (int q = q0; q < q1; ++q)
-            if (s_flag[q]) a.kept[ok++] = q;
+            if (s_flag[q]) {
+                a.kept[ok] = q;
+                if (ok < kLdsKept) s_kept[ok] = q;
+                ++ok;
+            }
     }
     __syncthreads();
 
@@ -634,15 +669,24 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
             const int tl = tot3[0], tf = tot3[1], th = tot3[2];
             int ol = base_l + pre[0];
             int of = base_f + pre[1];
+            // a table of one round whose live list fits the LDS writes it there only
+            const bool to_lds = S <= 8 * kCatThreads && tl <= kLdsLive;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int sl = s0 + i;
                 if (st[i] == kSrcLive) {
-                    a.g_live[ol] = sl;
-                    a.g_lpos[ol] = pack_pos(row[i], col[i]);
+                    if (to_lds) {
+                        s_live[ol] = sl;
+                        s_lpos[ol] = pack_pos(row[i], col[i]);
+                    } else {
+                        a.g_live[ol] = sl;
+                        a.g_lpos[ol] = pack_pos(row[i], col[i]);
+                    }
                     ++ol;
                 } else if (st[i] == kSrcFree) {
-                    a.free_list[of++] = sl;
+                    a.free_list[of] = sl;
+                    if (of < kLdsKept) s_freel[of] = sl;
+                    ++of;
                 }
             }
             base_l += tl;
@@ -658,7 +702,7 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
     __syncthreads();
     const int L = s_nlive;
     const bool live_in_lds = L <= kLdsLive;
-    if (live_in_lds) {
+    if (live_in_lds && S > 8 * kCatThreads) {   // several rounds: copy from the global list
         for (int l = tid; l < L; l += kCatThreads) {
             s_live[l] = a.g_live[l];
             s_lpos[l] = a.g_lpos[l];
@@ -679,7 +723,7 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
         int32_t* wslot = s_wslot + wave * kCand;
         for (int kq = wave; kq < K; kq += kCatThreads / 64) {
             int32_t* out = cand + (size_t)kq * (kCand + 1);
-            const int pq = s_pos[a.kept[kq]];
+            const int pq = s_pos[K <= kLdsKept ? s_kept[kq] : a.kept[kq]];
             int cnt = 0;
             for (int l0 = 0; l0 < L && cnt <= kCand; l0 += 64) {
                 const int l = l0 + lane;
@@ -824,11 +868,11 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
             a.src_tlast[dq] = t;
         } else if (dq != INT32_MIN) {
             const int r = -1 - dq;
-            const int s = a.free_list[r];
-            const int n = a.order[a.kept[kq]];
+            const int s = r < kLdsKept ? s_freel[r] : a.free_list[r];
+            const int pos = s_pos[K <= kLdsKept ? s_kept[kq] : a.kept[kq]];   // (row << 16) | col
             a.src_id[s] = s_next + r;
-            a.src_row[s] = a.peak_sorted[n].row;
-            a.src_col[s] = a.peak_sorted[n].col;
+            a.src_row[s] = pos >> 16;
+            a.src_col[s] = pos & 0xffff;
             a.src_state[s] = kSrcLive;
             a.src_tfirst[s] = t;
             a.src_tlast[s] = t;
