@@ -793,10 +793,11 @@ __device__ __forceinline__ void strip_body(const FiltArgs& a, const Taps& tp, in
     typedef StripGeo<K> G;
     float* stage = lds;
     float* ring = lds + 32 * G::SW;   // [64 columns][RT]
-    const int strips_y = (a.H + a.strip_h - 1) / a.strip_h;
-    const int per_band = a.tiles_x * strips_y;
-    const int b = lin / per_band;
-    const int rem = lin % per_band;
+    // band-minor order: an XCD's contiguous range of lin (xcd_remap) covers one
+    // region of the image in every band, so the planes all bands read
+    // (1/(G*M), the mask bits) come from that XCD's L2 after the first band
+    const int b = lin % a.B;
+    const int rem = lin / a.B;
     if (a.rej && ((*a.rej >> b) & 1u)) return;
     const int sy = rem / a.tiles_x, tx = rem % a.tiles_x;
     const int x0 = tx * kTileW;
@@ -982,11 +983,9 @@ __global__ __launch_bounds__(kStripThreads) void k_filter_strip16(FiltArgs a, Ta
     constexpr bool SCALE = !__is_same(T, __bf16) && IN == IN_E;
     __shared__ __attribute__((aligned(16))) T stage[32 * G::SW];
     __shared__ __attribute__((aligned(16))) T ring[kTileW * G::RT];
-    const int strips_y = (a.H + a.strip_h - 1) / a.strip_h;
-    const int per_band = a.tiles_x * strips_y;
     const int lin = xcd_remap(blockIdx.x, gridDim.x);
-    const int b = lin / per_band;
-    const int rem = lin % per_band;
+    const int b = lin % a.B;   // band-minor, as in strip_body
+    const int rem = lin / a.B;
     if (a.rej && ((*a.rej >> b) & 1u)) return;
     const int sy = rem / a.tiles_x, tx = rem % a.tiles_x;
     const int x0 = tx * kTileW;
