@@ -166,6 +166,7 @@ size_t carve(const lpf_config* c, const Derived& d, char* base, DevBufs* b) {
     b->cat_rowoff = cv.take<int32_t>((size_t)c->H + 1);
     b->cat_rowcur = cv.take<int32_t>((size_t)c->H);
     b->cat_rowidx = cv.take<int32_t>(kCatMaxPeaks);
+    b->cat_lrowidx = cv.take<int32_t>(S);
     b->free_list = cv.take<int32_t>(S);
     b->src_id = cv.take<int32_t>(S);
     b->src_row = cv.take<int32_t>(S);

@@ -63,6 +63,7 @@ struct CatArgs {
     int32_t* g_rowoff;  // [H + 1] row buckets of the duplicate search (many peaks)
     int32_t* g_rowcur;  // [H]
     int32_t* g_rowidx;  // [kCatMaxPeaks]
+    int32_t* g_lrowidx; // [max_sources] live entries by row (association search, many sources)
     int32_t* free_list; // [max_sources]
     int32_t* src_id;
     int32_t* src_row;
@@ -337,6 +338,37 @@ __global__ __launch_bounds__(256) void k_peak_test_group(Grouped<PeakTestArgs> g
     peak_test_blocks(g.a[i], blockIdx.x - g.gi.start[i], g.gi.start[i + 1] - g.gi.start[i]);
 }
 
+// Counting sort of n items by the image row of their packed positions:
+// rowoff[r] .. rowoff[r + 1] index the items of row r in idx (the order
+// inside a row is that of the atomic cursor, which no result depends on).
+// All threads of the workgroup call it; it ends with a barrier.
+__device__ void bucket_rows(int n, const int32_t* pos, int32_t* rowoff, int32_t* rowcur, int32_t* idx, int H,
+                            int* s_tmp) {
+    const int tid = threadIdx.x;
+    for (int r = tid; r <= H; r += kCatThreads) rowoff[r] = 0;
+    __syncthreads();
+    for (int q = tid; q < n; q += kCatThreads) atomicAdd(&rowoff[pos_i(pos[q])], 1);
+    __syncthreads();
+    {
+        const int per = (H + kCatThreads - 1) / kCatThreads;
+        const int r0 = tid * per, r1 = min(H, r0 + per);
+        int sum = 0;
+        for (int r = r0; r < r1; ++r) sum += rowoff[r];
+        int tot;
+        int acc = block_scan(sum, s_tmp, &tot);
+        for (int r = r0; r < r1; ++r) {
+            const int c = rowoff[r];
+            rowoff[r] = acc;
+            rowcur[r] = acc;
+            acc += c;
+        }
+        if (tid == 0) rowoff[H] = tot;
+    }
+    __syncthreads();
+    for (int q = tid; q < n; q += kCatThreads) idx[atomicAdd(&rowcur[pos_i(pos[q])], 1)] = q;
+    __syncthreads();
+}
+
 __device__ __forceinline__ void catalog_body(const CatArgs& a) {
     __shared__ uint64_t s_keys[kLdsKeys];            // 16 KB: sort keys / neighbour lists / live lists
     __shared__ int32_t s_posl[kLdsPos];              //  8 KB: positions in visiting order
@@ -513,30 +545,8 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
             // visiting indices), then each peak looks only at the rows within
             // dup_radius of its own
             int32_t* rowoff = a.g_rowoff;   // [H + 1] bucket starts
-            int32_t* rowcur = a.g_rowcur;   // [H] fill cursors
             const int H = a.H;
-            for (int r = tid; r <= H; r += kCatThreads) rowoff[r] = 0;
-            __syncthreads();
-            for (int q = tid; q < P; q += kCatThreads) atomicAdd(&rowoff[pos_i(s_pos[q])], 1);
-            __syncthreads();
-            {
-                const int per = (H + kCatThreads - 1) / kCatThreads;
-                const int r0 = tid * per, r1 = min(H, r0 + per);
-                int sum = 0;
-                for (int r = r0; r < r1; ++r) sum += rowoff[r];
-                int tot;
-                int acc = block_scan(sum, s_tmp, &tot);
-                for (int r = r0; r < r1; ++r) {
-                    const int c = rowoff[r];
-                    rowoff[r] = acc;
-                    rowcur[r] = acc;
-                    acc += c;
-                }
-                if (tid == 0) rowoff[H] = tot;
-            }
-            __syncthreads();
-            for (int q = tid; q < P; q += kCatThreads) a.g_rowidx[atomicAdd(&rowcur[pos_i(s_pos[q])], 1)] = q;
-            __syncthreads();
+            bucket_rows(P, s_pos, rowoff, a.g_rowcur, a.g_rowidx, H, s_tmp);
             const int R = (int)floorf(sqrtf(a.r_dup2));
             for (int q = tid; q < P; q += kCatThreads) {
                 const int pq = s_pos[q];
@@ -717,32 +727,44 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
     // One wave per kept peak scans the live list 64 sources at a time.
     int32_t* cand = K <= kLdsKept ? s_cand : a.cand;
     int32_t* dec = K <= kLdsKept ? s_dec : a.dec;
+    // many live sources and kept peaks: bucket the live list by row, so each
+    // peak looks only at the rows within assoc_radius of its own
+    const bool lbucket = L > kRowIndexMin && K > 64;
+    if (lbucket) bucket_rows(L, lpos, a.g_rowoff, a.g_rowcur, a.g_lrowidx, a.H, s_tmp);
     {
         const int wave = tid >> 6, lane = tid & 63;
         uint64_t* wkey = s_wkey + wave * kCand;
         int32_t* wslot = s_wslot + wave * kCand;
+        const int R = (int)floorf(sqrtf(a.r_assoc2));
         for (int kq = wave; kq < K; kq += kCatThreads / 64) {
             int32_t* out = cand + (size_t)kq * (kCand + 1);
             const int pq = s_pos[K <= kLdsKept ? s_kept[kq] : a.kept[kq]];
+            // the live entries to test: all of them, or the rows i - R .. i + R
+            const int pi = pos_i(pq);
+            const int rr0 = lbucket ? max(0, pi - R) : 0, rr1 = lbucket ? min(a.H - 1, pi + R) : 0;
             int cnt = 0;
-            for (int l0 = 0; l0 < L && cnt <= kCand; l0 += 64) {
-                const int l = l0 + lane;
-                const int lp = l < L ? lpos[l] : 0;
-                const bool hit = l < L && dist2(pq, lp) <= a.r_assoc2;
-                const uint64_t bal = __ballot(hit);
-                const int nh = __popcll(bal);
-                if (cnt + nh > kCand) {
-                    cnt = kCand + 1;
-                    break;
+            for (int rr = rr0; rr <= rr1 && cnt <= kCand; ++rr) {
+                const int e0 = lbucket ? a.g_rowoff[rr] : 0, e1 = lbucket ? a.g_rowoff[rr + 1] : L;
+                for (int l0 = e0; l0 < e1 && cnt <= kCand; l0 += 64) {
+                    const int e = l0 + lane;
+                    const int l = e < e1 ? (lbucket ? a.g_lrowidx[e] : e) : 0;
+                    const int lp = e < e1 ? lpos[l] : 0;
+                    const bool hit = e < e1 && dist2(pq, lp) <= a.r_assoc2;
+                    const uint64_t bal = __ballot(hit);
+                    const int nh = __popcll(bal);
+                    if (cnt + nh > kCand) {
+                        cnt = kCand + 1;
+                        break;
+                    }
+                    if (hit) {
+                        const int at = cnt + __popcll(bal & ((1ull << lane) - 1ull));
+                        const int s = live[l];
+                        const uint32_t d2 = (uint32_t)dist2(pq, lp);
+                        wkey[at] = ((uint64_t)d2 << 32) | (uint32_t)a.src_id[s];
+                        wslot[at] = s;
+                    }
+                    cnt += nh;
                 }
-                if (hit) {
-                    const int at = cnt + __popcll(bal & ((1ull << lane) - 1ull));
-                    const int s = live[l];
-                    const uint32_t d2 = (uint32_t)dist2(pq, lp);
-                    wkey[at] = ((uint64_t)d2 << 32) | (uint32_t)a.src_id[s];
-                    wslot[at] = s;
-                }
-                cnt += nh;
             }
             __builtin_amdgcn_wave_barrier();
             if (lane == 0) {
@@ -1038,6 +1060,7 @@ CatArgs catalog_args(lpf_ctx* c, int64_t t) {
     a.g_rowoff = c->buf.cat_rowoff;
     a.g_rowcur = c->buf.cat_rowcur;
     a.g_rowidx = c->buf.cat_rowidx;
+    a.g_lrowidx = c->buf.cat_lrowidx;
     a.free_list = c->buf.free_list;
     a.src_id = c->buf.src_id;
     a.src_row = c->buf.src_row;

@@ -108,6 +108,7 @@ struct DevBufs {
     int32_t* cat_rowoff;   // [H + 1] row buckets of the duplicate search
     int32_t* cat_rowcur;   // [H]
     int32_t* cat_rowidx;   // [kCatMaxPeaks]
+    int32_t* cat_lrowidx;  // [max_sources] live sources by row
     int32_t* free_list;    // [max_sources]
     // source table
     int32_t* src_id;

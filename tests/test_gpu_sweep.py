@@ -1,7 +1,8 @@
 """The accuracy sweep's detection on the device against the oracle at the
 sweep's setting (kappa = 2, one and three clip iterations, 512^2 all-sky
 images with exponential fluxes and side-lobe PSFs): the same peaks up to the
-excused near-threshold pixels, hence the same scores."""
+excused near-threshold pixels, hence the same scores, and the events of the
+oracle's catalogue fed the device's peaks."""
 
 import numpy as np
 import pytest
@@ -11,7 +12,7 @@ from oracle.config import OracleConfig
 from oracle.pipeline import OracleStream
 from paper_2103_15418_amd.sweep import accumulate, match, scores
 
-from parity import check_peaks_bracket, check_peaks_iters, clip_reference
+from parity import check_peaks_bracket, check_peaks_iters, clip_reference, compare_events, dev_peaks_as_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -44,7 +45,10 @@ def test_sweep_detection_matches_oracle(n_iter):
         ctx.extract_flux()
         orc.ingest(t, img[None])
         own, overflow = orc.find_peaks()
-        orc.associate(own, overflow)
+        # association from the device's validated list: on the second image thousands of
+        # kept peaks meet thousands of live sources (the row-bucketed candidate search)
+        _, new_o, ended_o = orc.associate(dev_peaks_as_oracle(pd), 0)
+        compare_events(ev, orc, new_o, ended_o, f"sweep t={t}")
         orc.extract_flux()
         assert overflow == 0 and ctx.status()["overflow_bands"] == 0
         assert len(pd) > 1000
