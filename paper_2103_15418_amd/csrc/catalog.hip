@@ -639,8 +639,9 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
         s_taken[w] = 0u;
         s_seen[w] = 0u;
     }
-    // live (slot, position) pairs go to the global scratch; the key area holds
-    // a copy when they fit
+    // live (slot, position) pairs go to the key area in LDS when the table is
+    // scanned in one round and they fit, else to the global scratch (copied
+    // to the key area afterwards when they fit)
     int32_t* s_live = reinterpret_cast<int32_t*>(s_keys);
     int32_t* s_lpos = s_live + kLdsLive;
     {
