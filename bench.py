@@ -563,6 +563,18 @@ def main():
                              "definition": "completion of extract_flux (event on the context stream seen "
                                            "done by the host) minus the frame's arrival time; frames "
                                            "arrive at a fixed cadence after the timed steps"}
+    # precision forms: bf16 / fp16 operands on MFMA (filters and network), float32 accumulation;
+    # timed right after the float32 steps, under the same conditions
+    if not args.no_precision_forms:
+        forms = {}
+        for code, name in ((1, "bf16"), (2, "fp16")):
+            print(f"[bench] {name}: timing {args.steps} steps", file=sys.stderr, flush=True)
+            el, hs, pr, _, nw, _, _ = run(code, args.steps)
+            forms[name] = {"value": args.steps * px_step / el, "ms_per_step": el / args.steps * 1e3,
+                           "stage_avg_ms": {k: round(v[0] / v[1], 5) for k, v in pr.items() if v[1]},
+                           "windows_inferred": nw}
+            forms[name]["error_vs_fp64"] = precision_errors(code, st, pool, Context, Model, synth)
+        out["precision_forms"] = forms
     out["network_batch1024"] = {name: network_batch(Model, synth.cnn_weights(), code)
                                 for code, name in ((0, "fp32"), (1, "bf16"), (2, "fp16"))}
     # the batch a step of the timed run hands over (about 30 ended episodes)
@@ -576,17 +588,6 @@ def main():
                              "ms_per_step": el_h / n_h * 1e3,
                              "note": "cubes copied host->device each step from pinned memory (4 cubes cycled)"}
     del host_pool
-    # precision forms: bf16 / fp16 operands on MFMA (filters and network), float32 accumulation
-    if not args.no_precision_forms:
-        forms = {}
-        for code, name in ((1, "bf16"), (2, "fp16")):
-            print(f"[bench] {name}: timing {args.steps} steps", file=sys.stderr, flush=True)
-            el, hs, pr, _, nw, _, _ = run(code, args.steps)
-            forms[name] = {"value": args.steps * px_step / el, "ms_per_step": el / args.steps * 1e3,
-                           "stage_avg_ms": {k: round(v[0] / v[1], 5) for k, v in pr.items() if v[1]},
-                           "windows_inferred": nw}
-            forms[name]["error_vs_fp64"] = precision_errors(code, st, pool, Context, Model, synth)
-        out["precision_forms"] = forms
     if not args.no_serving:
         del pool
         torch.cuda.empty_cache()
