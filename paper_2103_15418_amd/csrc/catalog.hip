@@ -1002,7 +1002,12 @@ __device__ __forceinline__ void catalog_body(const CatArgs& a) {
     }
 }
 
-__global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) { catalog_body(a); }
+__global__ __launch_bounds__(kCatThreads) void k_catalog(CatArgs a) {
+    // the catalogue's chain of short phases is the step's critical path: its
+    // waves take issue priority over other kernels' waves sharing the CU
+    __builtin_amdgcn_s_setprio(3);
+    catalog_body(a);
+}
 
 // Grouped: workgroup i runs the catalogue step of context i.
 __global__ __launch_bounds__(kCatThreads) void k_catalog_group(Grouped<CatArgs> g) {
