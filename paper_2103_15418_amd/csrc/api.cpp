@@ -256,7 +256,10 @@ int launch_ticket(lpf_model* m, int slot, hipEvent_t after, lpf_ctx* c0) {
     return LPF_OK;
 }
 
-// Issues a context's deferred launch: after `after`, or after its own gather.
+// Issues a context's deferred launch: after `after`, or after all the work on
+// the context's stream so far (its gather included).  The gather itself
+// records no event: the detect that usually issues the launch passes one it
+// records anyway, and an event record costs the stream a few microseconds.
 int flush_pending(lpf_ctx* c, hipEvent_t after) {
     lpf_model* m = c->pend_model;
     if (!m) return LPF_OK;
@@ -264,7 +267,11 @@ int flush_pending(lpf_ctx* c, hipEvent_t after) {
     c->pend_model = nullptr;
     c->pend_slot = -1;
     m->pend_ctx[slot] = nullptr;
-    return launch_ticket(m, slot, after ? after : m->ev_gath[slot], c);
+    if (!after) {
+        LPF_HIP(c, hipEventRecord(m->ev_gath[slot], c->stream), "event record");
+        after = m->ev_gath[slot];
+    }
+    return launch_ticket(m, slot, after, c);
 }
 
 }  // namespace
@@ -1133,18 +1140,19 @@ int lpf_infer_async(lpf_ctx* const* ctxs, int32_t n_ctx, lpf_model* m, int64_t* 
     if (n_ctx == 1) {
         // one context: its stream gathers into this ticket's buffers and goes
         // on; only the network waits (on the model's stream).  A pipelined
-        // context defers the launch to after its next step's filters, so the
-        // network runs beside that step's catalogue rather than its filters.
+        // context defers the launch to after its next step's centre pass, so
+        // the network runs beside that step's spread pass and catalogue.
         lpf_ctx* c = c0;
-        LPF_HIP(c, launch_gather_ended(c, 0, hdr, win, rows, m->max_batch, c->stream, true), "gather");
-        LPF_HIP(c, hipEventRecord(m->ev_gath[slot], c->stream), "event record");
         if (c->ing_stream) {
             const int rc = flush_pending(c, nullptr);   // a ticket gathered earlier, no detect since
             if (rc != LPF_OK) return rc;
+            LPF_HIP(c, launch_gather_ended(c, 0, hdr, win, rows, m->max_batch, c->stream, true), "gather");
             c->pend_model = m;
             c->pend_slot = slot;
             m->pend_ctx[slot] = c;
         } else {
+            LPF_HIP(c, launch_gather_ended(c, 0, hdr, win, rows, m->max_batch, c->stream, true), "gather");
+            LPF_HIP(c, hipEventRecord(m->ev_gath[slot], c->stream), "event record");
             const int rc = launch_ticket(m, slot, m->ev_gath[slot], c);
             if (rc != LPF_OK) return rc;
         }

@@ -519,7 +519,7 @@ __global__ __launch_bounds__(256) void k_conv16_lds(const T* __restrict__ in, co
     }
 }
 
-// fc1 split-K on 16-bit operands// fc1 split-K on 16-bit operands: A = act [n][65536] (NHWC flatten), B = W1 [128][65536].
+// fc1 split-K on 16-bit operands: A = act [n][65536] (NHWC flatten), B = W1 [128][65536].
 template <typename T>
 __global__ __launch_bounds__(256) void k_fc1_16(const T* __restrict__ a, const T* __restrict__ w,
                                                 float* __restrict__ part, const int* __restrict__ n_dev,
@@ -1040,7 +1040,7 @@ void model_destroy(lpf_model* m) {
     for (int i = 0; i < kInflight; ++i) {
         if (m->pend_ctx[i]) {   // a deferred launch that will not happen: its ticket dies with the model
             // its gather (on the context's stream) still writes this model's buffers
-            if (m->ev_gath[i]) (void)hipEventSynchronize(m->ev_gath[i]);
+            (void)hipStreamSynchronize(m->pend_ctx[i]->stream);
             m->pend_ctx[i]->pend_model = nullptr;
             m->pend_ctx[i]->pend_slot = -1;
         }
