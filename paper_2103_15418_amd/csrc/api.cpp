@@ -227,6 +227,11 @@ int pmod(int64_t a, int m) {
     return (int)(r < 0 ? r + m : r);
 }
 
+// Events that order one device's streams only (never waited on by the host):
+// no timing and no system-scope fence, so a record costs no cache write-back
+// for host visibility.
+constexpr unsigned kDevEvent = hipEventDisableTiming | hipEventDisableSystemFence;
+
 // Waits for every stream of a context (before host reads of its state).
 hipError_t sync_all(lpf_ctx* c) {
     hipError_t e;
@@ -430,9 +435,9 @@ int lpf_create(const lpf_config* cfg, void* ws, size_t bytes, void* stream, lpf_
     if (e == hipSuccess) e = d.disk ? launch_disk_inv_den(c) : launch_inv_den(c);
     if (e == hipSuccess && cfg->pipeline_ingest) {
         e = hipStreamCreateWithFlags(&c->ing_stream, hipStreamNonBlocking);   // default priority
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_filt, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_qc, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_centre, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_filt, kDevEvent);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_qc, kDevEvent);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_centre, kDevEvent);
     }
     if (e == hipSuccess && (d.masked || cfg->pipeline_ingest)) {
         // mask copy is from pageable host memory, and a pipelined ingest is
@@ -1162,7 +1167,7 @@ int lpf_infer_async(lpf_ctx* const* ctxs, int32_t n_ctx, lpf_model* m, int64_t* 
         // order; each may go on as soon as its rings have been read
         for (int i = 0; i < n_ctx; ++i) {
             lpf_ctx* c = ctxs[i];
-            if (!c->ev_ready) LPF_HIP(c, hipEventCreateWithFlags(&c->ev_ready, hipEventDisableTiming), "event");
+            if (!c->ev_ready) LPF_HIP(c, hipEventCreateWithFlags(&c->ev_ready, kDevEvent), "event");
             LPF_HIP(c, hipEventRecord(c->ev_ready, c->stream), "event record");
             LPF_HIP(c0, hipStreamWaitEvent(s, c->ev_ready, 0), "event wait");
         }
@@ -1319,7 +1324,7 @@ int lpf_infer(lpf_ctx* const* ctxs, int32_t n_ctx, const lpf_model* m, const int
     // the contexts' streams hand their lists and rings over to the model's stream
     for (const auto& r : runs) {
         lpf_ctx* c = ctxs[r.ctx];
-        if (!c->ev_ready) LPF_HIP(c, hipEventCreateWithFlags(&c->ev_ready, hipEventDisableTiming), "event");
+        if (!c->ev_ready) LPF_HIP(c, hipEventCreateWithFlags(&c->ev_ready, kDevEvent), "event");
         LPF_HIP(c, hipEventRecord(c->ev_ready, c->stream), "event record");
         LPF_HIP(c0, hipStreamWaitEvent(s, c->ev_ready, 0), "event wait");
     }

@@ -1015,14 +1015,17 @@ int model_create(const void* weights, size_t bytes, int precision, int maxb, voi
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    // inference stream (default priority), events and pinned result blocks
+    // inference stream (default priority), events and pinned result blocks;
+    // the events that only order device streams skip the system-scope fence
+    // (the host waits on ev_done alone)
+    constexpr unsigned kDevEvent = hipEventDisableTiming | hipEventDisableSystemFence;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&m->istream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_gathered, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_in, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_out, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_gathered, kDevEvent);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_in, kDevEvent);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_out, kDevEvent);
     for (int i = 0; i < kInflight && e == hipSuccess; ++i) {
         e = hipEventCreateWithFlags(&m->ev_done[i], hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_gath[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_gath[i], kDevEvent);
         if (e == hipSuccess)
             e = hipHostMalloc(reinterpret_cast<void**>(&m->h_res[i]), m->work.out_bytes, hipHostMallocDefault);
     }
