@@ -1054,7 +1054,8 @@ int lpf_profile_enable(lpf_ctx* c, int32_t stages) {
     if (stages < 0 || stages > LPF_PROFILE_ALL) return fail(c, LPF_EINVAL, "stage mask");
     if (stages && c->prof_pool.empty()) {
         c->prof_pool.resize(1 << 14);
-        for (auto& e : c->prof_pool) LPF_HIP(c, hipEventCreate(&e), "event create");
+        for (auto& e : c->prof_pool)   // timing only: no system-scope fence around the kernels timed
+            LPF_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "event create");
     }
     c->prof_mask = (uint32_t)stages;
     return LPF_OK;
