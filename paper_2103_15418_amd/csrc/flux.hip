@@ -77,8 +77,41 @@ __device__ inline float box_max_k(const float* img, int H, int W, int i, int j) 
     return m;
 }
 
+// Half-width 2 on rows of whole float4 (W % 4 == 0, W >= 8): two aligned
+// 16-byte loads per row, starting at the multiple of 4 at or below j - 2
+// (clamped to [0, W - 8]), hold the box's five columns; the maximum runs over
+// the loaded pixels inside the box and the image, in the same row-major order
+// as box_max_k<2>.
+__device__ inline float box_max_2v(const float* img, int H, int W, int i, int j) {
+    int a0 = (j - 2) & ~3;
+    a0 = a0 < 0 ? 0 : (a0 > W - 8 ? W - 8 : a0);
+    float v[5][8];
+    bool rok[5];
+#pragma unroll
+    for (int dr = 0; dr < 5; ++dr) {
+        const int r = i + dr - 2;
+        const int rc = r < 0 ? 0 : (r >= H ? H - 1 : r);
+        rok[dr] = r >= 0 && r < H;
+        const float4* p = reinterpret_cast<const float4*>(img + (size_t)rc * W + a0);
+        const float4 lo = p[0], hi = p[1];
+        v[dr][0] = lo.x; v[dr][1] = lo.y; v[dr][2] = lo.z; v[dr][3] = lo.w;
+        v[dr][4] = hi.x; v[dr][5] = hi.y; v[dr][6] = hi.z; v[dr][7] = hi.w;
+    }
+    float m = -INFINITY;
+#pragma unroll
+    for (int dr = 0; dr < 5; ++dr) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int c = a0 + e;
+            if (rok[dr] && c >= j - 2 && c <= j + 2) m = fmaxf(m, v[dr][e]);
+        }
+    }
+    return m;
+}
+
 __device__ inline float box_max_any(const float* img, int H, int W, int i, int j, int k) {
-    return k == 2 ? box_max_k<2>(img, H, W, i, j) : box_max(img, H, W, i, j, k);
+    if (k == 2) return (W & 3) == 0 && W >= 8 ? box_max_2v(img, H, W, i, j) : box_max_k<2>(img, H, W, i, j);
+    return box_max(img, H, W, i, j, k);
 }
 
 // Flux of one band: the box maximum, or with bgw > 0 the box maximum minus
@@ -159,19 +192,26 @@ __device__ void backfill_part(const FluxArgs& a, int blk, int nblk) {
     if (T_eff <= 0) return;
     const int64_t per_src = (int64_t)T_eff * a.B;
     const int64_t w0 = (int64_t)blk * blockDim.x + threadIdx.x;
+    // the step of an entry follows from its index alone, so the first entry's
+    // cache label and QC flags are read with the count and the source, and
+    // the box loads come after one round trip
+    auto step_of = [&](int64_t w) { return a.t - T_eff + (int)(w % per_src) / a.B; };
     const int n = *a.count_new;
     const int2 e0 = w0 / per_src < a.cap ? a.list_new[w0 / per_src] : make_int2(0, 0);
+    const int cs0 = pmod(step_of(w0), a.Tc);
+    const int64_t ct0 = a.cache_t[cs0];
+    const uint32_t rej0 = a.cache_rej[cs0];
     const uint32_t allb = (a.B == 32) ? 0xffffffffu : ((1u << a.B) - 1u);
     for (int64_t w = w0; w < (int64_t)n * per_src; w += (int64_t)nblk * blockDim.x) {
-        const int2 e = w == w0 ? e0 : a.list_new[w / per_src];
+        const bool first = w == w0;
+        const int2 e = first ? e0 : a.list_new[w / per_src];
         const int s = e.x;
-        const int rem = (int)(w % per_src);
-        const int d = rem / a.B, b = rem % a.B;
-        const int64_t tau = a.t - T_eff + d;
+        const int b = (int)(w % per_src) % a.B;
+        const int64_t tau = step_of(w);
         if (tau < a.t_start) continue;
         const int cs = pmod(tau, a.Tc);
-        if (a.cache_t[cs] != tau) continue;  // step never ingested (gap)
-        const uint32_t rej = a.cache_rej[cs];
+        if ((first ? ct0 : a.cache_t[cs]) != tau) continue;  // step never ingested (gap)
+        const uint32_t rej = first ? rej0 : a.cache_rej[cs];
         const float* frame = a.cache + (size_t)cs * a.plane;
         const float f = ((rej >> b) & 1u)
                             ? 0.0f
