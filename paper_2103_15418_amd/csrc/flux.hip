@@ -385,16 +385,20 @@ FluxArgs flux_args(lpf_ctx* c, int64_t t) {
     a.list_new = c->buf.list_new;
     a.count_new = &c->buf.status->n_new;
     a.cap = c->cfg.max_sources;
-    a.flux_blocks = 128;
+    a.flux_blocks = 512;
     return a;
 }
 
-int flux_grid(const FluxArgs& a) { return a.T_bf > 0 ? 384 : 128; }
+// Small workgroups: the lanes with work (one per source and band, taken in
+// order) then spread over every CU instead of crowding the random box loads
+// of a few hundred sources into the miss queues of a hundred CUs.
+constexpr int kFluxThreads = 64;
+int flux_grid(const FluxArgs& a) { return a.T_bf > 0 ? 1536 : 512; }
 
 hipError_t launch_flux(lpf_ctx* c, int slot, int64_t t) {
     (void)slot;
     const FluxArgs a = flux_args(c, t);
-    hipLaunchKernelGGL(k_flux, dim3(flux_grid(a)), dim3(256), 0, c->stream, a);
+    hipLaunchKernelGGL(k_flux, dim3(flux_grid(a)), dim3(kFluxThreads), 0, c->stream, a);
     return hipGetLastError();
 }
 
@@ -409,7 +413,7 @@ hipError_t launch_flux_group(lpf_ctx* const* cs, const int64_t* ts, int n, hipSt
         total += flux_grid(g.a[i]);
     }
     g.gi.start[n] = total;
-    hipLaunchKernelGGL(k_flux_group, dim3(total), dim3(256), 0, s, g);
+    hipLaunchKernelGGL(k_flux_group, dim3(total), dim3(kFluxThreads), 0, s, g);
     return hipGetLastError();
 }
 
