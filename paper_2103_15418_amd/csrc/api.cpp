@@ -227,9 +227,9 @@ int pmod(int64_t a, int m) {
     return (int)(r < 0 ? r + m : r);
 }
 
-// Events that order one device's streams only (never waited on by the host):
-// no timing and no system-scope fence, so a record costs no cache write-back
-// for host visibility.
+// Events that order kernels after kernels on one device's streams (never
+// waited on by the host, never ordering a copy): no timing and no system-scope
+// fence, so a record costs no cache maintenance for host visibility.
 constexpr unsigned kDevEvent = hipEventDisableTiming | hipEventDisableSystemFence;
 
 // Waits for every stream of a context (before host reads of its state).

@@ -1016,13 +1016,14 @@ int model_create(const void* weights, size_t bytes, int precision, int maxb, voi
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     // inference stream (default priority), events and pinned result blocks;
-    // the events that only order device streams skip the system-scope fence
-    // (the host waits on ev_done alone)
+    // the events that order kernels after kernels of this device skip the
+    // system-scope fence; ev_in / ev_out (the caller's stream, which may carry
+    // copies) and ev_done (waited on by the host) keep it
     constexpr unsigned kDevEvent = hipEventDisableTiming | hipEventDisableSystemFence;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&m->istream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_gathered, kDevEvent);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_in, kDevEvent);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_out, kDevEvent);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_out, hipEventDisableTiming);
     for (int i = 0; i < kInflight && e == hipSuccess; ++i) {
         e = hipEventCreateWithFlags(&m->ev_done[i], hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&m->ev_gath[i], kDevEvent);
