@@ -231,6 +231,32 @@ def test_gap_in_time_and_backfill():
     assert res["steps"] == len(ts) and res["events"] >= 2
 
 
+@pytest.mark.parametrize("W", [72, 70])
+def test_flux_boxes_at_image_edges(W):
+    """Sources on the first and last rows and columns: the flux boxes are
+    clipped to the image (W = 72: two aligned 16-byte loads per box row,
+    clamped at 0 and W - 8; W = 70: the scalar path); fluxes, backward fills
+    and spectra bitwise equal to the oracle's."""
+    _torch_cuda()
+    rng = np.random.default_rng(11)
+    B, H = 2, 64
+    # a wide background kernel, so that a corner source's own share of the
+    # clipped spread leaves it above kappa (the oracle finds all seven; the
+    # last two merge within dup_radius): six open at t = 4 with four steps of
+    # backward fill, are measured at 5 .. 7 and end at 8
+    ctx, orc = make_pair(B, H, W, kappa=6.0, bg_sigma=8.0, backfill_steps=4, monitor_steps=3)
+    spots = [(0, 0), (1, W - 1), (H - 1, 2), (30, 1), (33, W - 2), (H - 2, W - 3), (H - 1, W - 1)]
+    frames, ts = [], list(range(9))
+    for t in ts:
+        cube = rng.standard_normal((B, H, W)).astype(np.float32)
+        if t in (4, 5):
+            for q, (r, c) in enumerate(spots):
+                cube[q % B, r, c] += 30.0 + 2.0 * q
+        frames.append(cube)
+    res = run_steps(ctx, orc, frames, ts, label=f"edges W={W}")
+    assert res["steps"] == len(ts) and res["events"] >= 12 and res["resyncs"] == 0
+
+
 def test_association_conflicts_and_duplicates():
     """Catalogue cases that take the sequential resolutions: two kept peaks
     (farther apart than dup_radius) both within assoc_radius of one live
