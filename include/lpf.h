@@ -289,7 +289,8 @@ int lpf_infer_windows_static(const lpf_model* model, const float* windows, int32
  * are copied into a pinned host slot; nothing waits.  For one context with
  * pipeline_ingest = 1 the network is launched after the centre pass of that
  * context's next lpf_detect (beside its spread pass and catalogue), or by
- * lpf_infer_collect or lpf_destroy of the context if those come first.  Each context's later
+ * the context's next lpf_infer_async, lpf_infer_collect of the ticket or
+ * lpf_destroy of the context if one of those comes first.  Each context's later
  * work is ordered after the gather, so the caller may ingest the next frame
  * at once.  *ticket
  * identifies the results for lpf_infer_collect.  At most 4 tickets may be
