@@ -65,7 +65,8 @@ struct SrvStream {
     lpf_ctx* ctx = nullptr;
     void* ws = nullptr;            // workspace: the caller's, or the server's own
     bool own_ws = false;
-    size_t ws_bytes = 0;
+    size_t ws_bytes = 0;           // what the configuration needs (the budget's unit)
+    size_t ws_cap = 0;             // size of an own workspace (a reused one may be larger)
     DevStatus* h_status = nullptr; // pinned copy of the device counters of its current frame
     std::deque<SrvFrame> pending;
     bool busy = false;             // a frame is in a round that is not done
@@ -83,9 +84,19 @@ struct Round {
 
 }  // namespace
 
+// A closed stream's own workspace and pinned status block, kept for a later
+// admission: freeing them would synchronise the whole device mid-serving.
+struct PooledWs {
+    void* ws;
+    size_t cap;
+    DevStatus* h_status;
+};
+
 struct lpf_server {
     const lpf_model* model = nullptr;
     size_t budget = 0, used = 0;
+    std::vector<PooledWs> pool;   // under mu; freed at destroy, or when an admission needs the memory
+    size_t pooled = 0;
     bool record = false;
     hipStream_t hs = nullptr;
     std::mutex mu;
@@ -108,16 +119,33 @@ namespace {
 constexpr int kMaxRounds = kInflight;
 
 // Creates the stream's context on the server's HIP stream (and its own
-// workspace if the caller gave none).  Called without the server lock.
+// workspace if the caller gave none: the smallest pooled one that is large
+// enough, else a new one).  Called without the server lock.
 int activate(lpf_server* srv, SrvStream* s) {
     lpf_config cfg = s->cfg;
     cfg.sky_mask = s->mask.empty() ? nullptr : s->mask.data();
     cfg.grid_rows = s->rows.empty() ? nullptr : s->rows.data();
     cfg.pipeline_ingest = 0;
     if (!s->ws) {
-        if (hipMalloc(&s->ws, s->ws_bytes) != hipSuccess) {
-            s->ws = nullptr;
-            return LPF_ENOMEM;
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            int best = -1;
+            for (int i = 0; i < (int)srv->pool.size(); ++i)
+                if (srv->pool[i].cap >= s->ws_bytes && (best < 0 || srv->pool[i].cap < srv->pool[best].cap)) best = i;
+            if (best >= 0) {
+                s->ws = srv->pool[best].ws;
+                s->ws_cap = srv->pool[best].cap;
+                s->h_status = srv->pool[best].h_status;
+                srv->pooled -= s->ws_cap;
+                srv->pool.erase(srv->pool.begin() + best);
+            }
+        }
+        if (!s->ws) {
+            if (hipMalloc(&s->ws, s->ws_bytes) != hipSuccess) {
+                s->ws = nullptr;
+                return LPF_ENOMEM;
+            }
+            s->ws_cap = s->ws_bytes;
         }
         s->own_ws = true;
     }
@@ -127,11 +155,32 @@ int activate(lpf_server* srv, SrvStream* s) {
     return lpf_create(&cfg, s->ws, s->ws_bytes, srv->hs, &s->ctx);
 }
 
-void free_stream(SrvStream* s) {
-    if (s->ctx) lpf_destroy(s->ctx);
-    if (s->h_status) (void)hipHostFree(s->h_status);
-    if (s->own_ws && s->ws) (void)hipFree(s->ws);
+// Ends a stream: its context, then its own workspace and status block back
+// to the pool (pool = false: freed, at server destruction).
+void free_stream(lpf_server* srv, SrvStream* s, bool pool = true) {
+    if (s->ctx) lpf_destroy(s->ctx);   // waits for the stream's work on the server's HIP stream
+    if (pool && s->own_ws && s->ws) {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->pool.push_back(PooledWs{s->ws, s->ws_cap, s->h_status});
+        srv->pooled += s->ws_cap;
+    } else {
+        if (s->h_status) (void)hipHostFree(s->h_status);
+        if (s->own_ws && s->ws) (void)hipFree(s->ws);
+    }
     delete s;
+}
+
+// Frees pooled workspaces, largest first, until `need` more bytes of the
+// server's own allocations fit the budget (caller holds mu).
+void trim_pool(lpf_server* srv, size_t need) {
+    while (!srv->pool.empty() && srv->used + srv->pooled + need > srv->budget) {
+        auto it = std::max_element(srv->pool.begin(), srv->pool.end(),
+                                   [](const PooledWs& x, const PooledWs& y) { return x.cap < y.cap; });
+        (void)hipHostFree(it->h_status);
+        (void)hipFree(it->ws);
+        srv->pooled -= it->cap;
+        srv->pool.erase(it);
+    }
 }
 
 // Launches one round over the given streams (dispatcher thread).
@@ -319,6 +368,7 @@ void admit_waiting(lpf_server* srv) {
             SrvStream* w = srv->waiting.front();
             if (srv->used + w->ws_bytes > srv->budget) return;
             srv->waiting.pop_front();
+            if (!w->ws) trim_pool(srv, w->ws_bytes);
             srv->used += w->ws_bytes;
             s = w;
         }
@@ -381,7 +431,11 @@ void lpf_server_destroy(lpf_server* srv) {
     while (finish_round(srv, true)) {
     }
     (void)hipStreamSynchronize(srv->hs);
-    for (auto& kv : srv->streams) free_stream(kv.second);
+    for (auto& kv : srv->streams) free_stream(srv, kv.second, false);
+    for (const PooledWs& p : srv->pool) {
+        (void)hipHostFree(p.h_status);
+        (void)hipFree(p.ws);
+    }
     (void)hipStreamDestroy(srv->hs);
     delete srv;
 }
@@ -411,18 +465,22 @@ int lpf_server_admit(lpf_server* srv, const lpf_config* cfg, void* ws, size_t ws
         }
         s->id = srv->next_id++;
         srv->streams[s->id] = s;
+        if (fits && !ws) trim_pool(srv, bytes);   // the pool gives way to admitted streams
         if (fits) srv->used += bytes;   // reserve
         else srv->waiting.push_back(s);
     }
     if (fits) {
         rc = activate(srv, s);
-        std::lock_guard<std::mutex> lk(srv->mu);
         if (rc != LPF_OK) {
-            srv->streams.erase(s->id);
-            srv->used -= bytes;
-            free_stream(s);
+            {
+                std::lock_guard<std::mutex> lk(srv->mu);
+                srv->streams.erase(s->id);
+                srv->used -= bytes;
+            }
+            free_stream(srv, s);   // takes the lock itself
             return rc;
         }
+        std::lock_guard<std::mutex> lk(srv->mu);
         s->state = kActive;
     }
     *stream_id = s->id;
@@ -452,7 +510,7 @@ int lpf_server_close(lpf_server* srv, int32_t id) {
         srv->streams.erase(it);
         if (was_active) srv->used -= s->ws_bytes;
     }
-    free_stream(s);
+    free_stream(srv, s);
     srv->cv_done.notify_all();
     admit_waiting(srv);
     return LPF_OK;

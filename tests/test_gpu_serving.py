@@ -144,3 +144,37 @@ def test_admission_by_hbm_budget():
     for t in range(4):
         for x, y in zip(served[t], alone[(0, t)]):
             assert x.tobytes() == y.tobytes(), t
+
+
+def test_closed_stream_workspace_reused():
+    """A closed stream's workspace allocated by the server goes to its pool instead of
+    being freed (which would synchronise the device mid-serving); a stream
+    admitted later with the same shape takes it, still holding the first
+    stream's state, and its outputs are the same bytes as those of the stream
+    served alone."""
+    import dataclasses
+    torch = _torch_cuda()
+    from paper_2103_15418_amd import Model, Server
+    model = Model(synth.cnn_weights(seed=9), max_batch=8)
+    specs = small_specs(4)
+    streams = [synth.Stream(specs[0]), synth.Stream(dataclasses.replace(specs[0], seed=91))]
+    frames = [[torch.from_numpy(st.frame(t)).cuda() for t in range(4)] for st in streams]
+    s = specs[0]
+    srv = Server(model, 1 << 36, record=True)
+    a = srv.admit(s.B, s.H, s.W, sky_mask=streams[0].mask, own_workspace=False, **SERVE_PARAMS)
+    for t in range(4):
+        srv.submit(a, t, frames[0][t])
+    srv.drain()
+    srv.close(a)                           # its workspace is pooled
+    b = srv.admit(s.B, s.H, s.W, sky_mask=streams[1].mask, own_workspace=False, **SERVE_PARAMS)
+    for t in range(4):
+        srv.submit(b, t, frames[1][t])
+    srv.drain()
+    res = srv.poll(cap=64)
+    assert len(res) == 8 and np.all(res["status"] == 0)
+    served = [srv.fetch(b, t) for t in range(4)]
+    srv.close_all()
+    alone, _ = run_server(model, [streams[1]], [frames[1]], budget=1 << 36)
+    for t in range(4):
+        for x, y in zip(served[t], alone[(0, t)]):
+            assert x.tobytes() == y.tobytes(), t
